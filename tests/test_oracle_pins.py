@@ -1,0 +1,370 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these tests retypes an oracle formula: each compares the oracle with
+an independent definition (explicit residual, finite differences, library
+routines, brute-force loops, closed forms) or with values printed in the
+paper (tests/golden/).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+import torch
+
+import oracle as o
+import synth
+
+
+def _rand_sym(n, seed):
+    r = np.random.default_rng(seed)
+    A = r.random((n, n))
+    return 0.5 * (A + A.T)
+
+
+# --- objective and gradient (section "Memory-Efficient Loss Reformulation") ---
+def test_trace_identity_matches_explicit_residual():
+    r = np.random.default_rng(0)
+    for n, k in [(7, 2), (64, 5), (300, 12)]:
+        S = _rand_sym(n, n)
+        H = r.random((n, k))
+        fe = o.objective_explicit(S, H)
+        ft = o.objective_trace(S, H)
+        assert abs(fe - ft) <= 1e-12 * fe
+
+
+def test_gradient_matches_central_differences_of_explicit_objective():
+    r = np.random.default_rng(1)
+    n, k = 12, 3
+    S = _rand_sym(n, 3)
+    H = r.random((n, k))
+    g = o.gradient(S, H)
+    h = 1e-6
+    fd = np.zeros_like(H)
+    for i in range(n):
+        for j in range(k):
+            Hp, Hm = H.copy(), H.copy()
+            Hp[i, j] += h
+            Hm[i, j] -= h
+            fd[i, j] = (o.objective_explicit(S, Hp) - o.objective_explicit(S, Hm)) / (2 * h)
+    assert np.max(np.abs(fd - g)) <= 1e-6 * np.max(np.abs(g))
+
+
+def test_zero_factor_is_critical_with_unit_error():
+    S = o.abs_corr(synth.c1_instance(0, T=300, n=40, groups=4).X.numpy())
+    H = np.zeros((40, 4))
+    assert np.all(o.gradient(S, H) == 0.0)
+    assert o.objective_trace(S, H) / (S * S).sum() == 1.0
+
+
+def test_permutation_invariance_and_no_diagonal_scaling():
+    r = np.random.default_rng(2)
+    S = _rand_sym(30, 5)
+    H = r.random((30, 4))
+    P = np.eye(4)[[2, 0, 3, 1]]
+    assert abs(o.objective_trace(S, H @ P) - o.objective_trace(S, H)) <= 1e-12 * o.objective_trace(S, H)
+    D = np.diag([1.0, 2.0, 0.5, 1.5])
+    assert abs(o.objective_trace(S, H @ D) - o.objective_trace(S, H)) > 1e-3
+    assert o.subspace_error(H, H @ P) < 1e-12
+
+
+def test_projected_gradient_is_zero_exactly_at_kkt_points():
+    H = np.array([[0.0, 1.0], [0.0, 2.0]])
+    g = np.array([[3.0, 0.0], [-1.0, 0.0]])
+    pg = o.projected_gradient(g, H)
+    assert pg.tolist() == [[0.0, 0.0], [-1.0, 0.0]]
+    assert o.kkt_measure(g, H) == pytest.approx(1.0 / 4)
+    assert o.kkt_measure(g, H, softplus=True) == pytest.approx(math.sqrt(10.0) / 4)
+
+
+# --- S construction ---------------------------------------------------------
+def test_abs_corr_matches_library_and_pairwise_formula():
+    X = synth.c1_instance(3, T=200, n=16, groups=4).X.numpy().astype(np.float64)
+    S = o.abs_corr(X)
+    C = np.corrcoef(X, rowvar=False)
+    off = ~np.eye(16, dtype=bool)
+    assert np.max(np.abs(S[off] - np.abs(C[off]))) < 1e-12
+    for i in range(0, 16, 5):
+        for j in range(16):
+            if i != j:
+                assert S[i, j] == pytest.approx(abs(scipy.stats.pearsonr(X[:, i], X[:, j])[0]), abs=1e-12)
+    assert np.all(np.diag(S) == 1.0)
+
+
+def test_abs_corr_rejects_constant_column():
+    X = np.random.default_rng(0).random((20, 4))
+    X[:, 2] = 3.0
+    with pytest.raises(ValueError):
+        o.abs_corr(X)
+
+
+def test_rank_transform_matches_scipy_ordinal_ranks():
+    r = np.random.default_rng(4)
+    X = r.integers(0, 5, size=(50, 6)).astype(np.float64)   # many ties
+    R = o.rank_columns(X)
+    for j in range(6):
+        assert np.array_equal(R[:, j], scipy.stats.rankdata(X[:, j], method="ordinal").astype(np.int64))
+
+
+def test_pareto2_margins_have_the_pareto_tail():
+    T = 1000
+    x = o.pareto2_from_ranks(np.arange(1, T + 1), T)
+    # P(X > x) = x^-2 for the empirical distribution function F = r/(T+1)
+    emp_tail = 1.0 - np.arange(1, T + 1) / (T + 1.0)
+    assert np.allclose(x ** -2.0, emp_tail, rtol=1e-12)
+
+
+def test_tpdm_invariants():
+    inst = synth.tpdm_returns(0, T=4000, n=48, groups=4, nu=3.0)
+    S, parts = o.tpdm(inst.X.numpy(), q=0.05, return_parts=True)
+    n_exc = 200
+    assert parts["sel"].size == n_exc
+    assert np.allclose(S, S.T, atol=1e-15)
+    assert np.all(np.diag(S) == 1.0) and np.trace(S) == 48
+    assert S.min() >= 0.0 and S.max() <= 1.0 + 1e-12
+    ev = np.linalg.eigvalsh(S)
+    assert ev.min() > -1e-10
+    assert np.sum(ev > 1e-8 * ev.max()) <= n_exc
+    # the kept samples are the largest radial norms
+    r = parts["r"]
+    assert r[parts["sel"]].min() >= np.delete(r, parts["sel"]).max()
+
+
+def test_tpdm_population_limit_of_noiseless_factor_model():
+    """Noiseless X = A Z with i.i.d. Pareto(2) factors: the unit-diagonal
+    TPDM tends to D^-1/2 A A^T D^-1/2 (section "Tail Pairwise Dependence
+    Matrix", alpha = 2)."""
+    g = np.random.default_rng(5)
+    A = np.array([[1.0, 0.0], [0.8, 0.3], [0.2, 1.0], [0.0, 1.0], [0.5, 0.5]])
+    AA = A @ A.T
+    d = np.sqrt(np.diag(AA))
+    target = AA / np.outer(d, d)
+    errs = []
+    for T, q in [(400000, 0.02), (2000000, 0.0005)]:
+        Z = (1.0 - g.random((T, 2))) ** -0.5          # Pareto(2): P(Z > z) = z^-2
+        S = o.tpdm(Z @ A.T, q=q, lower_tail=False)
+        errs.append(np.max(np.abs(S - target)))
+    # the finite-threshold bias is O(1/r_0): it shrinks as the threshold rises
+    assert errs[1] < 0.06 and errs[1] < 0.3 * errs[0]
+
+
+# --- storage formats -------------------------------------------------------
+def test_bf16_rounding_matches_torch():
+    x = np.random.default_rng(6).random(20000).astype(np.float32) * np.float32(2.0) - np.float32(0.5)
+    ours = o.to_bf16(x.astype(np.float64))
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
+
+
+def test_fp8_rounding_matches_torch_in_range():
+    g = np.random.default_rng(7)
+    x = np.concatenate([g.random(20000) * 448.0, g.random(2000) * 0.05, -g.random(2000) * 3.0]).astype(np.float32)
+    ours = o.to_fp8_e4m3(x.astype(np.float64))
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
+    assert o.to_fp8_e4m3(np.array([1000.0]))[0] == 448.0
+
+
+def test_fp8_panel_quantisation_error_bound_and_exact_diagonal():
+    S = o.abs_corr(synth.c1_instance(1, T=300, n=64, groups=4).X.numpy())
+    Sq, sc = o.quantise(S, "fp8", panel_rows=16)
+    assert sc.size == 4
+    assert np.all(np.diag(Sq) == 1.0)
+    off = ~np.eye(64, dtype=bool)
+    # normals of e4m3 carry 4 significand bits: relative error <= 2^-4
+    big = off & (np.abs(S) * np.repeat(sc, 16)[:, None] >= 2.0 ** -6)
+    assert np.all(np.abs(Sq - S)[big] <= 2.0 ** -4 * np.abs(S)[big] + 1e-15)
+
+
+# --- counter RNG and sampling -------------------------------------------------
+def test_splitmix64_published_outputs(golden_dir):
+    for line in open(f"{golden_dir}/splitmix64_seed0.txt"):
+        if line.startswith("#") or not line.strip():
+            continue
+        c, v = line.split()
+        assert int(o.splitmix64(0, int(c))) == int(v, 16)
+
+
+def test_block_sampling_is_uniform_without_replacement():
+    counts = np.zeros(20)
+    for t in range(2000):
+        s = o.sample_blocks(11, t, 0, 20, 7)
+        assert len(set(s.tolist())) == 7 and np.all(np.diff(s) > 0) and s.min() >= 0 and s.max() < 20
+        counts[s] += 1
+    expected = 2000 * 7 / 20
+    assert np.max(np.abs(counts - expected)) < 5 * math.sqrt(expected)
+    assert np.array_equal(o.sample_blocks(11, 5, 1, 20, 7), o.sample_blocks(11, 5, 1, 20, 7))
+
+
+def test_init_H_range_and_mean():
+    H = o.init_H(0.25, 4000, 16, seed=3)
+    scale = math.sqrt(0.25 / 16)
+    assert H.min() >= 0.0 and H.max() < scale
+    assert H.mean() == pytest.approx(scale / 2, rel=0.01)
+    H32 = o.init_H(0.25, 4000, 16, seed=3, as_float32=True)
+    assert np.max(np.abs(H32 - H)) <= 2 ** -24 * scale
+
+
+# --- update rules (appendix, family 3) --------------------------------------
+def _c1_small():
+    inst = synth.c1_instance(0, T=400, n=64, groups=4)
+    S = o.abs_corr(inst.X.numpy())
+    return S, o.init_H(S.mean(), 64, 4, seed=0)
+
+
+def test_first_adagrad_step_closed_form():
+    S, H0 = _c1_small()
+    eta, eps = 0.05, 1e-10
+    s = o.Solver(S, 4, o.Params(eta=eta, eps=eps), H0)
+    g0 = o.gradient(S, H0)
+    s.step()
+    # with G_0 = 0 the first step is eta * g / (|g| + eps): a signed unit step
+    assert np.allclose(s.H, np.maximum(H0 - eta * g0 / (np.abs(g0) + eps), 0.0), rtol=0, atol=1e-15)
+
+
+def test_adagrad_invariants_and_kkt_at_convergence():
+    S, H0 = _c1_small()
+    s = o.Solver(S, 4, o.Params(eta=math.sqrt(S.mean() / 4), eps=1e-12, max_iter=20000, tau_stag=0.0,
+                                tau_g_inf=1e-12), H0)
+    Gprev = s.G.copy()
+    for _ in range(30):
+        s.step()
+        assert np.all(s.H >= 0) and np.all(s.G >= Gprev)
+        Gprev = s.G.copy()
+    H, st = s.solve()
+    g = o.gradient(S, H)
+    assert np.max(np.abs(np.minimum(H, g))) < 1e-9       # complementarity min(H, grad) = 0
+    assert np.all(g[H == 0] >= -1e-9)                      # grad >= 0 on the boundary
+    assert np.any(H == 0)                                  # the boundary is active on this instance
+
+
+def test_planted_exact_factorisation_is_recovered():
+    Hs = synth.planted_factor(3, 64, 4).numpy()
+    S = Hs @ Hs.T
+    H0 = o.init_H(S.mean(), 64, 4, seed=1)
+    p = o.Params(eta=math.sqrt(S.mean() / 4), max_iter=20000, tau_g_inf=1e-14, tau_stag=0.0)
+    H, st = o.Solver(S, 4, p, H0).solve()
+    assert st.converged and st.E < 1e-12
+    assert o.subspace_error(H, Hs) < 1e-6
+
+
+def test_softplus_chain_rule_matches_finite_differences():
+    S, _ = _c1_small()
+    theta = np.random.default_rng(9).normal(-2.0, 1.0, size=(64, 4))
+    f = lambda th: o.objective_explicit(S, o.softplus(th))
+    g = o.gradient(S, o.softplus(theta)) * o.sigmoid(theta)
+    h = 1e-6
+    for (i, j) in [(0, 0), (5, 3), (63, 1), (20, 2)]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i, j] += h
+        tm[i, j] -= h
+        assert (f(tp) - f(tm)) / (2 * h) == pytest.approx(g[i, j], rel=1e-6, abs=1e-9)
+    assert np.allclose(o.softplus(o.softplus_inverse(np.array([1e-3, 0.5, 30.0]))), [1e-3, 0.5, 30.0], rtol=1e-12)
+
+
+def test_rmsprop_first_step_closed_form():
+    S, H0 = _c1_small()
+    p = o.Params(method=o.RMSPROP, eta=0.01, eps=1e-8, alpha=0.99, mu=0.5)
+    s = o.Solver(S, 4, p, H0)
+    g = o.gradient(S, H0)
+    s.step()
+    m1 = 0.01 * g / (np.sqrt(0.01 * g * g) + 1e-8)
+    assert np.allclose(s.H, np.maximum(H0 - m1, 0.0), rtol=0, atol=1e-15)
+
+
+def test_lower_median_and_reset_formula():
+    g = np.array([[3.0, -1.0], [0.5, 2.0], [0.0, -4.0]])      # g^2 = 9,1,.25,4,0,16
+    assert o.lower_median(g * g) == 1.0                         # sorted: 0,.25,1,4,9,16 -> index 2
+    G = o.piecewise_reset(g, 10.0)
+    assert G.tolist() == [[90.0, 10.0], [10.0, 40.0], [10.0, 160.0]]
+    x = np.random.default_rng(0).random(1001)
+    assert o.lower_median(x) == np.sort(x)[500] == np.median(x)
+
+
+def test_piecewise_equals_adagrad_before_first_reset():
+    S, H0 = _c1_small()
+    pa = o.Params(eta=0.05, max_iter=200)
+    pp = o.Params(method=o.PIECEWISE_ADAGRAD, eta=0.05, max_iter=200)
+    a, b = o.Solver(S, 4, pa, H0), o.Solver(S, 4, pp, H0)
+    a.solve(max_iter=200)
+    b.solve(max_iter=200)
+    first = next((h.t for h in b.history if h.reset_fired), None)
+    upto = 200 if first is None else first
+    for x, y in zip(a.history[:upto + 1], b.history[:upto + 1]):
+        assert x.f == y.f
+
+
+def test_row_svrg_full_fraction_equals_adagrad():
+    S, H0 = _c1_small()
+    pa = o.Params(eta=0.05)
+    pr = o.Params(method=o.ROW_SVRG, eta=0.05, row_frac=1.0, block_rows=16, snapshot_s=5)
+    a, b = o.Solver(S, 4, pa, H0), o.Solver(S, 4, pr, H0)
+    for _ in range(23):
+        a.step()
+        b.step()
+    assert np.array_equal(a.H, b.H)
+
+
+def test_block_svrg_full_coverage_equals_adagrad_and_block_gradient_is_exact():
+    S, H0 = _c1_small()
+    pa = o.Params(eta=0.05)
+    pb = o.Params(method=o.BLOCK_SVRG, eta=0.05, phi0=1.0, block_rows=16)
+    a, b = o.Solver(S, 4, pa, H0), o.Solver(S, 4, pb, H0)
+    for _ in range(15):
+        a.step()
+        b.step()
+    assert np.array_equal(a.H, b.H)
+    # I = J = [n]: 2 R H + 2 R^T H = 4 R H = grad f
+    c = o.Solver(S, 4, o.Params(method=o.BLOCK_SVRG, phi0=0.99, block_rows=16, snapshot_s=1000), H0)
+    c.step()                      # snapshot step
+    g, _, kind = c.gradient_of_step()
+    assert kind == "block"
+    assert np.allclose(g, o.gradient(S, c.H), rtol=1e-12, atol=1e-14)
+
+
+def test_block_svrg_partial_step_uses_snapshot_on_untouched_rows():
+    S, H0 = _c1_small()
+    c = o.Solver(S, 4, o.Params(method=o.BLOCK_SVRG, phi0=0.25, block_rows=8, snapshot_s=1000,
+                                independent_blocks=False), H0)
+    c.step()
+    I, J = c.sampled_sets()
+    assert np.array_equal(I, J) and I.size == 4
+    g, _, _ = c.gradient_of_step()
+    rows = c._rows_of(I)
+    assert np.array_equal(g[~rows], c.mu_snap[~rows])
+    full = o.gradient(S, c.H)
+    # principal I = J: both terms coincide, g_I = 4(H_I G_I - S_II H_I)
+    HI = c.H[rows]
+    assert np.allclose(g[rows], 4.0 * (HI @ (HI.T @ HI) - S[np.ix_(rows, rows)] @ HI))
+    assert not np.allclose(g[rows], full[rows])
+
+
+# --- stop rule (section "Convergence Criterion") --------------------------
+def test_tau_g_scaled_values_from_the_paper(golden_dir):
+    for line in open(f"{golden_dir}/kkt_scaled.txt"):
+        if line.startswith("#") or not line.strip():
+            continue
+        n, v = line.split()
+        assert o.tau_g(int(n)) == pytest.approx(float(v), rel=1e-12)
+
+
+def test_stop_rule_scripted_trace(golden_dir):
+    vals = dict(l.split() for l in open(f"{golden_dir}/stop_rule_examples.txt") if l[0] != "#" and l.strip())
+    p = o.Params(warmup=int(vals["warmup"]), delta=int(vals["delta"]), tau_E=float(vals["tau_E"]),
+                 tau_stag=float(vals["tau_stag"]))
+    assert math.sqrt(p.tau_E) == pytest.approx(float(vals["rel_residual_gate"]), abs=1e-3)
+    s = o.Solver(np.eye(4), 1, p, np.ones((4, 1)))
+    tg = o.tau_g(4)
+    seq = [(0, 1.0, 1.0), (10, 0.5, 1.0), (20, 0.05, tg / 2), (30, 0.05, tg / 2), (40, 0.05, tg / 2),
+           (50, 0.09, tg / 2), (60, 0.09, tg / 2)]
+    out = []
+    for t, E, kkt in seq:
+        st = o.Stats(t=t, full=True, E=E, kkt=kkt)
+        out.append(s.check(st, None))
+    # E stops moving at t = 30 but the stagnation test is suppressed before t = 50;
+    # E rises at t = 50 (stagnation ratio negative < tau) and is flat at 60
+    assert out == [False, False, False, False, False, True, True]
+    # the loss gate rejects H = 0 (E = 1) even with zero gradient and no progress
+    s2 = o.Solver(np.eye(4), 1, p, np.ones((4, 1)))
+    s2.check(o.Stats(t=0, full=True, E=float(vals["E_at_H0"]), kkt=0.0), None)
+    assert not s2.check(o.Stats(t=60, full=True, E=1.0, kkt=0.0), None)
