@@ -1,0 +1,263 @@
+/*
+ * symnmf.h - C ABI of the MI355X (gfx950) SymNMF hot path.
+ *
+ * Problem (paper section "Symmetric Non-negative Matrix Factorization",
+ * eq. symnmf): given a dense symmetric non-negative S (n x n), find
+ * H >= 0 (n x k, k << n) minimising f(H) = ||S - H H^T||_F^2.  Every step
+ * works in the trace-identity form (eq. trace_loss)
+ *     f(H) = ||S||_F^2 - 2 tr(H^T S H) + ||H^T H||_F^2,
+ *     grad f = 4 (H (H^T H) - S H),
+ * so no n x n intermediate is ever formed: each iteration streams S once
+ * (or the sampled part of it) against H.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All sizes are int64_t.  Matrices are row-major.  "device" pointers are
+ *   HIP device allocations owned by the caller unless stated otherwise.
+ * - Every call is enqueued on the context's HIP stream and returns without
+ *   waiting, except where a description says it synchronises (calls that
+ *   hand back host scalars).
+ * - Nothing throws across the ABI.  A non-zero symnmf_status is returned and
+ *   symnmf_last_error() describes it.  Invalid arguments are rejected before
+ *   any kernel is launched (SYMNMF_EINVAL); a non-finite value detected in a
+ *   reduction is SYMNMF_ENUMERIC.
+ * - S storage (symnmf_S): rows_pad = rows rounded up to 256, leading
+ *   dimension ld = n rounded up to 256 elements; padding is zero.  FP8 S keeps
+ *   per-row-panel scales after the matrix in the same buffer.
+ * - H buffers handed to the library are n x k, contiguous k.
+ * - A context is not thread safe; use one per host thread.
+ */
+#ifndef SYMNMF_H
+#define SYMNMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SYMNMF_OK = 0,
+    SYMNMF_EINVAL = 1,       /* bad argument, shape or state                    */
+    SYMNMF_ENOMEM = 2,       /* device allocation failed / buffer too small     */
+    SYMNMF_EDEVICE = 3,      /* HIP runtime error                               */
+    SYMNMF_ENUMERIC = 4,     /* non-finite value in a reduction                 */
+    SYMNMF_ENOTCONV = 5,     /* solve_to_tol hit max_iter before the stop rule  */
+    SYMNMF_EUNSUPPORTED = 6  /* valid request this build does not implement     */
+} symnmf_status;
+
+/* Storage type of S.  The paper runs fp32; BF16 and FP8 storage are an
+ * addition (the paper leaves half precision open in its numerical
+ * consideration paragraph).  FP64 is kept for exact parity runs. */
+typedef enum {
+    SYMNMF_S_FP32 = 0,
+    SYMNMF_S_BF16 = 1,       /* round-to-nearest-even                            */
+    SYMNMF_S_FP8 = 2,        /* OCP E4M3, per-row-panel scale, exact unit diag   */
+    SYMNMF_S_FP64 = 3
+} symnmf_sdtype;
+
+typedef enum {
+    SYMNMF_ABS_CORR = 0,     /* |Pearson correlation| (appendix, correlation construction) */
+    SYMNMF_TPDM = 1          /* empirical tail pairwise dependence (section "Empirical Estimation") */
+} symnmf_skind;
+
+/* Solver families of appendix "Detailed Algorithm Descriptions", family 3. */
+typedef enum {
+    SYMNMF_ADAGRAD = 0,
+    SYMNMF_RMSPROP = 1,
+    SYMNMF_PIECEWISE_ADAGRAD = 2,
+    SYMNMF_ROW_SVRG = 3,
+    SYMNMF_BLOCK_SVRG = 4    /* Block-SVRG AdaptGrow */
+} symnmf_method;
+
+typedef struct symnmf_ctx symnmf_ctx;
+typedef struct symnmf_state symnmf_state;
+
+/* Parameters of S construction. */
+typedef struct {
+    int32_t kind;            /* symnmf_skind                                     */
+    int32_t dtype;           /* symnmf_sdtype of the stored S                    */
+    int64_t n;               /* instruments = columns of X                       */
+    int64_t T;               /* samples = rows of X (T >= 2)                     */
+    int64_t row0;            /* first row of S to build (0 for the full matrix)  */
+    int64_t rows;            /* rows to build: n for the full matrix, fewer for a row panel */
+    double q;                /* TPDM: exceedance fraction, n_exc = floor(q T) >= 1 */
+    int32_t lower_tail;      /* TPDM: 1 = lower tail (transform -X), 0 = upper   */
+    int32_t reserved0;
+    int64_t fp8_panel_rows;  /* FP8: rows per scale panel (>= 1)                 */
+} symnmf_sbuild_params;
+
+/* Descriptor of a stored S (or of a row panel of S).  Filled by
+ * symnmf_build_S / symnmf_S_load; the caller owns the memory at ``data``. */
+typedef struct {
+    void* data;              /* device: rows_pad x ld elements of dtype           */
+    float* panel_scale;      /* device: FP8 scales (stored code = S * scale), else NULL */
+    float* diag;             /* device: FP8 S_ii of every panel row (codes hold 0 there), else NULL */
+    int64_t n, row0, rows, ld, rows_pad, fp8_panel_rows;
+    int32_t dtype, kind;
+    double fro2;             /* ||S||_F^2 before storage rounding (FP64 sum)      */
+    double fro2_stored;      /* ||S_stored||_F^2, what the solver's objective uses */
+    double sum;              /* sum of the entries before storage rounding        */
+    double mean;             /* sum / (rows * n)                                  */
+} symnmf_S;
+
+/* Solver parameters.  Readings of values the paper leaves open are listed
+ * with the fields; defaults come from symnmf_params_default(). */
+typedef struct {
+    int32_t method;          /* symnmf_method                                    */
+    int32_t softplus;        /* 1: H = softplus(Theta), optimiser on Theta (eq. logspace_grad) */
+    double eta;              /* learning rate                                     */
+    double eps;              /* added outside the square root                     */
+    double alpha;            /* RMSprop EMA factor                                */
+    double mu;               /* RMSprop momentum                                  */
+    double c;                /* Piecewise: reset scale c                          */
+    double c_r;              /* Piecewise: reset only while KKT > c_r * tau_g     */
+    double eps_med;          /* Piecewise: median(g^2) floor                      */
+    double row_frac;         /* Row-SVRG: |I| / n                                 */
+    double phi0;             /* Block-SVRG: initial entry coverage phi_0          */
+    double c_grow;           /* Block-SVRG: grow only while KKT > c_grow * tau_g  */
+    int64_t grow_checks;     /* Block-SVRG: consecutive stagnating checks to grow */
+    int64_t snapshot_s;      /* SVRG snapshot period s (full step at t = 0 mod s) */
+    int64_t block_rows;      /* SVRG row-block size, a multiple of 256            */
+    int32_t independent_blocks; /* Block-SVRG: 1 = independent I and J, 0 = J = I */
+    int32_t reserved0;
+    int64_t delta;           /* check interval (eq. obj_stag), multiple of snapshot_s for SVRG */
+    int64_t warmup;          /* stagnation test suppressed for t < warmup         */
+    int64_t max_iter;
+    double tau_E;            /* loss gate (eq. loss_gate)                         */
+    double tau_g_inf;        /* KKT gate tau_g^inf (eq. kkt_scaled)               */
+    double n_ref;            /* n_ref of eq. kkt_scaled                           */
+    double tau_stag;         /* stagnation tolerance (eq. obj_stag)               */
+    uint64_t seed;           /* key of the index-set sampler                      */
+} symnmf_params;
+
+/* Statistics of one iteration, of the iterate H_t that the step read. */
+typedef struct {
+    int64_t t;
+    double f;                /* f(H_t) on the stored S (NaN on sub-sampled steps) */
+    double E;                /* f / ||S_stored||_F^2                              */
+    double kkt;              /* ||grad_proj f(H_t)||_F / (n k) (eq. kkt_stop)     */
+    double stag;             /* (E_{t-delta} - E_t) / E_0 at checks, else NaN     */
+    double phi;              /* Block-SVRG coverage used by this step             */
+    double wall_ms;          /* host wall time since the state was created        */
+    int32_t full;            /* 1: the step read all of S                         */
+    int32_t reset_fired;     /* Piecewise reset applied after this step           */
+    int32_t converged;       /* stop rule (eq. conv_and) satisfied at this check  */
+    int32_t nonfinite;       /* non-finite gradient entries seen                   */
+} symnmf_stats;
+
+int32_t symnmf_abi_version(void);
+void symnmf_params_default(symnmf_params* p);
+
+/* Create a context bound to HIP device ``device`` and stream ``hip_stream``
+ * (a hipStream_t; NULL = the null stream).  Allocates nothing on the device. */
+symnmf_status symnmf_create(symnmf_ctx** ctx, int32_t device, void* hip_stream);
+void symnmf_destroy(symnmf_ctx* ctx);
+const char* symnmf_last_error(const symnmf_ctx* ctx);
+
+/* Bytes of the buffer a stored S (rows x n, dtype) needs, scales included. */
+int64_t symnmf_S_bytes(int64_t rows, int64_t n, int32_t dtype, int64_t fp8_panel_rows);
+
+/* Build S (or rows [row0, row0+rows) of S) from the returns panel X.
+ * X: device, T x n float32 row-major (samples x instruments), read only.
+ * |corr| (appendix, correlation construction): columns centred and scaled to
+ *   unit norm in FP64, S = |Z^T Z| by an MFMA GEMM, S_ii = 1.
+ * TPDM (section "Empirical Estimation"): per-column ranks (ties to the lower
+ *   sample), Pareto(2) margins x = (1 - r/(T+1))^-1/2, FP64 radial norms, the
+ *   floor(qT) largest kept (ties to the lower sample), angular rows Omega,
+ *   S = D^-1/2 Omega^T Omega D^-1/2 by the same GEMM, S_ii = 1.
+ * buf: device, >= symnmf_S_bytes(...) bytes, caller owned.  Temporary device
+ * memory is allocated and freed inside the call.  Synchronises (fills the FP64
+ * sums of ``out``).  EINVAL: T < 2, n < 1, bad row range, zero-variance
+ * column, floor(qT) < 1. */
+symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuild_params* p,
+                             void* buf, int64_t buf_bytes, symnmf_S* out);
+
+/* Store a given dense S panel (device, rows x n row-major, float32 or float64
+ * when src_is_f64) in ``dtype`` - e.g. a planted S = H* H*^T.  Same storage
+ * and sums as symnmf_build_S.  Synchronises. */
+symnmf_status symnmf_S_load(symnmf_ctx* ctx, const void* src, int32_t src_is_f64, int64_t n,
+                            int64_t row0, int64_t rows, int32_t dtype, int64_t fp8_panel_rows,
+                            void* buf, int64_t buf_bytes, symnmf_S* out);
+
+/* Initial factor (section "Initialization and seeds"): H_ij = u_ij * sqrt(mean(S)/k),
+ * u_ij = 2^-24 * (top 24 bits of SplitMix64 output number i*k+j of key ``seed``).
+ * H: device n x k float32.  Uses S->mean. */
+symnmf_status symnmf_init_H(symnmf_ctx* ctx, const symnmf_S* S, int64_t k, uint64_t seed, float* H);
+
+/* Solver state for S and rank k.  H0: device n x k (float32, or float64 when
+ * h0_is_f64; FP64 storage of S runs the whole iteration in FP64 and needs
+ * an FP64 H0).  The state owns its device workspace (iterates H_t and H_{t+1},
+ * optimiser buffers, snapshot gradient, reduction partials) and frees it in
+ * symnmf_state_destroy.  1 <= k <= 64.  For a row panel (rows < n) the state
+ * updates the panel's rows of H and keeps the other rows fixed. */
+symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
+                                  const symnmf_params* p, const void* H0, int32_t h0_is_f64,
+                                  symnmf_state** st);
+void symnmf_state_destroy(symnmf_state* st);
+
+/* One solver iteration t -> t+1 (appendix family 3 rules; Piecewise resets,
+ * phi growth and the stop rule live in symnmf_solve_to_tol).  Reads H_t,
+ * forms g_t = grad f(H_t) from S H_t (or its sampled blocks), updates the
+ * optimiser state, writes H_{t+1}, and reduces in FP64 the statistics of H_t.
+ * ``out`` NULL: nothing waits; otherwise the call synchronises and fills it. */
+symnmf_status symnmf_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st, symnmf_stats* out);
+
+/* Copy a state buffer to ``dst`` (device, n x k elements of the state's
+ * precision: float32, or float64 for FP64 S).  which: 0 = current iterate,
+ * 1 = previous iterate, 2 = accumulator G (RMSprop v), 3 = RMSprop momentum,
+ * 4 = Theta (softplus), 5 = snapshot gradient mu, 6 = gradient of the last step. */
+symnmf_status symnmf_state_read(symnmf_ctx* ctx, symnmf_state* st, int32_t which, void* dst);
+/* Host copy of the statistics of the last step (synchronises). */
+symnmf_status symnmf_state_stats(symnmf_ctx* ctx, symnmf_state* st, symnmf_stats* out);
+/* Block-SVRG coverage phi (0 < phi <= 1). */
+symnmf_status symnmf_state_set_phi(symnmf_state* st, double phi);
+
+/* f(H) and E = f/||S_stored||^2 for any H (device n x k, float32 or float64),
+ * with S H accumulated in FP64 - the judge of results.  Synchronises. */
+symnmf_status symnmf_objective(symnmf_ctx* ctx, const symnmf_S* S, const void* H, int32_t h_is_f64,
+                               int64_t k, double* f, double* E);
+
+/* Iterate until the stop rule (eq. conv_and, checked every delta steps)
+ * certifies an iterate, or (f_target > 0) f(H_t) <= f_target (1 + rel_tol),
+ * or max_iter.  Applies Piecewise resets and Block-SVRG growth at checks.
+ * Copies the certified iterate H_t (or the last one) to H_out (device, may be
+ * NULL).  Returns SYMNMF_OK when a stop condition was met, SYMNMF_ENOTCONV
+ * when max_iter was reached.  Synchronises at every check. */
+symnmf_status symnmf_solve_to_tol(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st,
+                                  double f_target, double rel_tol, symnmf_stats* final_stats,
+                                  void* H_out);
+
+/* Lower median (element floor((m-1)/2) in sorted order) of g_i^2 over a device
+ * float32 array of m values, by radix selection on the bit patterns.
+ * Synchronises; the result goes to *out. */
+symnmf_status symnmf_median_sq(symnmf_ctx* ctx, const float* g, int64_t m, float* out);
+
+/* Piecewise AdaGrad accumulator recalibration G_i <- max(c g_i^2, c median(g^2))
+ * with g the gradient of the state's last step (appendix, Piecewise AdaGrad).
+ * Synchronises; *median_out (may be NULL) receives median(g^2). */
+symnmf_status symnmf_piecewise_reset(symnmf_ctx* ctx, symnmf_state* st, double c, float* median_out);
+
+/* The index-set sampler of the stochastic variants (host only): m distinct
+ * block indices of [0, nblocks), sorted, by a partial Fisher-Yates shuffle
+ * driven by SplitMix64 keyed by (seed, 2t + stream). */
+void symnmf_sample_blocks(uint64_t seed, int64_t t, int32_t stream, int64_t nblocks, int64_t m,
+                          int32_t* out);
+
+/* HIP-event timing of the kernels a step launches, on the context's stream.
+ * Reading (ms_out / launches_out non-NULL, 4 entries each: 0 = S.H stream,
+ * 1 = fused update, 2 = finalize, 3 = plan of a sub-sampled step)
+ * synchronises and returns the summed milliseconds and launch counts since the
+ * last call; every call then clears the record and sets profiling on or off
+ * (enable).  Off by default; timing adds two events per kernel. */
+symnmf_status symnmf_profile(symnmf_ctx* ctx, int32_t enable, double* ms_out, int64_t* launches_out);
+
+/* Device self-check of the FP8 -> BF16 conversion instruction the FP8 stream
+ * relies on: the number of finite E4M3 codes it decodes differently from the
+ * format definition (0 expected), or -1 on a HIP error.  Synchronises. */
+int32_t symnmf_selfcheck_fp8(symnmf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SYMNMF_H */

@@ -107,6 +107,23 @@ def abs_corr(X):
     return S
 
 
+def abs_corr_panel(Z, row0: int, rows: int):
+    """Rows [row0, row0+rows) of |corr| from the standardised columns Z
+    (Z = standardise_columns(X)), S_ii = 1: the same definition as abs_corr,
+    evaluated for a row panel only."""
+    P = np.abs(Z[:, row0:row0 + rows].T @ Z)
+    r = np.arange(rows)
+    P[r, r + row0] = 1.0
+    return P
+
+
+def gradient_panel(S_panel, H, row0: int):
+    """Rows [row0, row0+rows) of grad f = 4 (H (H^T H) - S H) from the
+    matching row panel of S and the full H."""
+    rows = S_panel.shape[0]
+    return 4.0 * (H[row0:row0 + rows] @ (H.T @ H) - S_panel @ H)
+
+
 def rank_columns(X):
     """Rank 1..T of every entry within its column; ties go to the lower row."""
     X = np.asarray(X)

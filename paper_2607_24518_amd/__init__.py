@@ -1,0 +1,317 @@
+"""Python binding of libsymnmf (the MI355X SymNMF hot path).
+
+Argument marshalling only: every function below calls the C ABI declared in
+``include/symnmf.h`` with the same name; all arithmetic runs in the library's
+HIP kernels.  torch provides device memory (tensors' ``data_ptr``) and the
+HIP stream.  If the shared library is missing the calls raise - there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsymnmf.so")
+
+# enums (include/symnmf.h)
+OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, ENOTCONV, EUNSUPPORTED = range(7)
+S_FP32, S_BF16, S_FP8, S_FP64 = range(4)
+ABS_CORR, TPDM = range(2)
+ADAGRAD, RMSPROP, PIECEWISE_ADAGRAD, ROW_SVRG, BLOCK_SVRG = range(5)
+DTYPES = {"fp32": S_FP32, "bf16": S_BF16, "fp8": S_FP8, "fp64": S_FP64}
+
+c_i32, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
+
+
+class symnmf_sbuild_params(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("dtype", c_i32), ("n", c_i64), ("T", c_i64), ("row0", c_i64),
+                ("rows", c_i64), ("q", c_dbl), ("lower_tail", c_i32), ("reserved0", c_i32),
+                ("fp8_panel_rows", c_i64)]
+
+
+class symnmf_S(ctypes.Structure):
+    _fields_ = [("data", c_vp), ("panel_scale", c_vp), ("diag", c_vp), ("n", c_i64), ("row0", c_i64),
+                ("rows", c_i64), ("ld", c_i64), ("rows_pad", c_i64), ("fp8_panel_rows", c_i64),
+                ("dtype", c_i32), ("kind", c_i32), ("fro2", c_dbl), ("fro2_stored", c_dbl),
+                ("sum", c_dbl), ("mean", c_dbl)]
+
+
+class symnmf_params(ctypes.Structure):
+    _fields_ = [("method", c_i32), ("softplus", c_i32), ("eta", c_dbl), ("eps", c_dbl), ("alpha", c_dbl),
+                ("mu", c_dbl), ("c", c_dbl), ("c_r", c_dbl), ("eps_med", c_dbl), ("row_frac", c_dbl),
+                ("phi0", c_dbl), ("c_grow", c_dbl), ("grow_checks", c_i64), ("snapshot_s", c_i64),
+                ("block_rows", c_i64), ("independent_blocks", c_i32), ("reserved0", c_i32),
+                ("delta", c_i64), ("warmup", c_i64), ("max_iter", c_i64), ("tau_E", c_dbl),
+                ("tau_g_inf", c_dbl), ("n_ref", c_dbl), ("tau_stag", c_dbl), ("seed", c_u64)]
+
+
+class symnmf_stats(ctypes.Structure):
+    _fields_ = [("t", c_i64), ("f", c_dbl), ("E", c_dbl), ("kkt", c_dbl), ("stag", c_dbl), ("phi", c_dbl),
+                ("wall_ms", c_dbl), ("full", c_i32), ("reset_fired", c_i32), ("converged", c_i32),
+                ("nonfinite", c_i32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SymnmfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"symnmf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# exported symbols and their signatures (restype, argtypes)
+SIGNATURES = {
+    "symnmf_abi_version": (c_i32, []),
+    "symnmf_params_default": (None, [ctypes.POINTER(symnmf_params)]),
+    "symnmf_create": (c_i32, [ctypes.POINTER(c_vp), c_i32, c_vp]),
+    "symnmf_destroy": (None, [c_vp]),
+    "symnmf_last_error": (ctypes.c_char_p, [c_vp]),
+    "symnmf_S_bytes": (c_i64, [c_i64, c_i64, c_i32, c_i64]),
+    "symnmf_build_S": (c_i32, [c_vp, c_vp, ctypes.POINTER(symnmf_sbuild_params), c_vp, c_i64,
+                               ctypes.POINTER(symnmf_S)]),
+    "symnmf_S_load": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i64, c_i64, c_i32, c_i64, c_vp, c_i64,
+                              ctypes.POINTER(symnmf_S)]),
+    "symnmf_init_H": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_i64, c_u64, c_vp]),
+    "symnmf_state_create": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_i64, ctypes.POINTER(symnmf_params), c_vp,
+                                    c_i32, ctypes.POINTER(c_vp)]),
+    "symnmf_state_destroy": (None, [c_vp]),
+    "symnmf_step": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, ctypes.POINTER(symnmf_stats)]),
+    "symnmf_state_read": (c_i32, [c_vp, c_vp, c_i32, c_vp]),
+    "symnmf_state_stats": (c_i32, [c_vp, c_vp, ctypes.POINTER(symnmf_stats)]),
+    "symnmf_state_set_phi": (c_i32, [c_vp, c_dbl]),
+    "symnmf_objective": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i32, c_i64, ctypes.POINTER(c_dbl),
+                                 ctypes.POINTER(c_dbl)]),
+    "symnmf_solve_to_tol": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_dbl, c_dbl,
+                                    ctypes.POINTER(symnmf_stats), c_vp]),
+    "symnmf_median_sq": (c_i32, [c_vp, c_vp, c_i64, ctypes.POINTER(ctypes.c_float)]),
+    "symnmf_piecewise_reset": (c_i32, [c_vp, c_vp, c_dbl, ctypes.POINTER(ctypes.c_float)]),
+    "symnmf_sample_blocks": (None, [c_u64, c_i64, c_i32, c_i64, c_i64, ctypes.POINTER(c_i32)]),
+    "symnmf_selfcheck_fp8": (c_i32, [c_vp]),
+    "symnmf_profile": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
+}
+
+PROFILE_KERNELS = ("stream", "update", "finalize", "plan")
+
+
+def lib():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2607_24518_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(ctx, code):
+    if code != OK:
+        msg = lib().symnmf_last_error(ctx)
+        raise SymnmfError(code, msg.decode() if msg else "")
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Matrix:
+    """A stored S: the descriptor plus the torch buffer that owns its memory."""
+
+    def __init__(self, desc: symnmf_S, buf):
+        self.desc = desc
+        self.buf = buf
+
+    @property
+    def n(self):
+        return self.desc.n
+
+    def __getattr__(self, name):
+        return getattr(self.desc, name)
+
+
+def symnmf_abi_version():
+    return lib().symnmf_abi_version()
+
+
+def symnmf_params_default(**overrides) -> symnmf_params:
+    p = symnmf_params()
+    lib().symnmf_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def symnmf_create(device: int = 0, stream=None):
+    ctx = c_vp()
+    code = lib().symnmf_create(ctypes.byref(ctx), device, _stream_handle(stream))
+    if code != OK:
+        raise SymnmfError(code, "symnmf_create failed")
+    return ctx
+
+
+def symnmf_destroy(ctx):
+    lib().symnmf_destroy(ctx)
+
+
+def symnmf_last_error(ctx):
+    return lib().symnmf_last_error(ctx).decode()
+
+
+def symnmf_S_bytes(rows, n, dtype, fp8_panel_rows=256):
+    return lib().symnmf_S_bytes(rows, n, dtype, fp8_panel_rows)
+
+
+def _alloc_bytes(nbytes, device):
+    import torch
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def symnmf_build_S(ctx, X, kind=ABS_CORR, dtype=S_FP32, row0=0, rows=None, q=0.05, lower_tail=1,
+                   fp8_panel_rows=256) -> Matrix:
+    """X: device float32 tensor T x n (contiguous)."""
+    T, n = X.shape
+    rows = n - row0 if rows is None else rows
+    p = symnmf_sbuild_params(kind=kind, dtype=dtype, n=n, T=T, row0=row0, rows=rows, q=q,
+                             lower_tail=lower_tail, fp8_panel_rows=fp8_panel_rows)
+    nbytes = symnmf_S_bytes(rows, n, dtype, fp8_panel_rows)
+    if nbytes < 0:
+        raise SymnmfError(EINVAL, "bad S shape")
+    buf = _alloc_bytes(nbytes, X.device)
+    desc = symnmf_S()
+    _check(ctx, lib().symnmf_build_S(ctx, _ptr(X), ctypes.byref(p), _ptr(buf), nbytes, ctypes.byref(desc)))
+    return Matrix(desc, buf)
+
+
+def symnmf_S_load(ctx, S_dense, dtype=S_FP32, row0=0, fp8_panel_rows=256) -> Matrix:
+    """S_dense: device float32/float64 tensor rows x n (a panel starting at global row row0)."""
+    import torch
+    rows, n = S_dense.shape
+    nbytes = symnmf_S_bytes(rows, n, dtype, fp8_panel_rows)
+    buf = _alloc_bytes(nbytes, S_dense.device)
+    desc = symnmf_S()
+    f64 = 1 if S_dense.dtype == torch.float64 else 0
+    _check(ctx, lib().symnmf_S_load(ctx, _ptr(S_dense), f64, n, row0, rows, dtype, fp8_panel_rows, _ptr(buf),
+                                    nbytes, ctypes.byref(desc)))
+    return Matrix(desc, buf)
+
+
+def symnmf_init_H(ctx, S: Matrix, k: int, seed: int, H):
+    _check(ctx, lib().symnmf_init_H(ctx, ctypes.byref(S.desc), k, seed, _ptr(H)))
+    return H
+
+
+class State:
+    def __init__(self, ctx, handle, S, k, params):
+        self.ctx, self.handle, self.S, self.k, self.params = ctx, handle, S, k, params
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.symnmf_state_destroy(self.handle)
+            self.handle = None
+
+
+def symnmf_state_create(ctx, S: Matrix, k: int, params: symnmf_params, H0) -> State:
+    import torch
+    h = c_vp()
+    f64 = 1 if H0.dtype == torch.float64 else 0
+    _check(ctx, lib().symnmf_state_create(ctx, ctypes.byref(S.desc), k, ctypes.byref(params), _ptr(H0), f64,
+                                          ctypes.byref(h)))
+    return State(ctx, h, S, k, params)
+
+
+def symnmf_state_destroy(st: State):
+    if st.handle is not None:
+        lib().symnmf_state_destroy(st.handle)
+        st.handle = None
+
+
+def symnmf_step(ctx, S: Matrix, st: State, want_stats: bool = True):
+    out = symnmf_stats() if want_stats else None
+    _check(ctx, lib().symnmf_step(ctx, ctypes.byref(S.desc), st.handle, ctypes.byref(out) if out else None))
+    return out
+
+
+def symnmf_state_read(ctx, st: State, which: int, dst):
+    _check(ctx, lib().symnmf_state_read(ctx, st.handle, which, _ptr(dst)))
+    return dst
+
+
+def symnmf_state_stats(ctx, st: State):
+    out = symnmf_stats()
+    _check(ctx, lib().symnmf_state_stats(ctx, st.handle, ctypes.byref(out)))
+    return out
+
+
+def symnmf_state_set_phi(st: State, phi: float):
+    code = lib().symnmf_state_set_phi(st.handle, phi)
+    if code != OK:
+        raise SymnmfError(code, "bad phi")
+
+
+def symnmf_objective(ctx, S: Matrix, H, k: int):
+    import torch
+    f, E = c_dbl(), c_dbl()
+    f64 = 1 if H.dtype == torch.float64 else 0
+    _check(ctx, lib().symnmf_objective(ctx, ctypes.byref(S.desc), _ptr(H), f64, k, ctypes.byref(f), ctypes.byref(E)))
+    return f.value, E.value
+
+
+def symnmf_solve_to_tol(ctx, S: Matrix, st: State, f_target: float = 0.0, rel_tol: float = 1e-4, H_out=None):
+    """Returns (stats, converged: bool)."""
+    out = symnmf_stats()
+    code = lib().symnmf_solve_to_tol(ctx, ctypes.byref(S.desc), st.handle, f_target, rel_tol, ctypes.byref(out),
+                                     _ptr(H_out) if H_out is not None else None)
+    if code not in (OK, ENOTCONV):
+        _check(ctx, code)
+    return out, code == OK
+
+
+def symnmf_median_sq(ctx, g, m=None):
+    out = ctypes.c_float()
+    m = g.numel() if m is None else m
+    _check(ctx, lib().symnmf_median_sq(ctx, _ptr(g), m, ctypes.byref(out)))
+    return out.value
+
+
+def symnmf_piecewise_reset(ctx, st: State, c: float):
+    med = ctypes.c_float()
+    _check(ctx, lib().symnmf_piecewise_reset(ctx, st.handle, c, ctypes.byref(med)))
+    return med.value
+
+
+def symnmf_sample_blocks(seed: int, t: int, stream: int, nblocks: int, m: int):
+    buf = (c_i32 * m)()
+    lib().symnmf_sample_blocks(seed, t, stream, nblocks, m, buf)
+    return list(buf)
+
+
+def symnmf_selfcheck_fp8(ctx):
+    return lib().symnmf_selfcheck_fp8(ctx)
+
+
+def symnmf_profile(ctx, enable: bool, read: bool = True):
+    """Returns {kernel: (ms, launches)} since the last call (when read) and
+    switches HIP-event timing on or off."""
+    if not read:
+        _check(ctx, lib().symnmf_profile(ctx, int(enable), None, None))
+        return None
+    ms = (c_dbl * 4)()
+    cnt = (c_i64 * 4)()
+    _check(ctx, lib().symnmf_profile(ctx, int(enable), ms, cnt))
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(PROFILE_KERNELS)}

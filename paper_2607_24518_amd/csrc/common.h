@@ -1,0 +1,269 @@
+// Internal declarations shared by the HIP sources of the SymNMF library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/symnmf.h"
+
+namespace symnmf {
+
+// Row tile of S handled by one work unit / one update work-group, and the
+// column chunk streamed per unit.  Storage pads rows and columns of S and the
+// rows of H to multiples of these, so no kernel needs a bounds test on the
+// streamed data.
+constexpr int TR = 256;
+constexpr int KC = 256;
+constexpr int KMAX = 64;
+constexpr int64_t PAD = 256;
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Storage conversions (round to nearest even)
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint16_t f32_to_bf16_bits(float x) {
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_bits_to_f32(uint16_t b) {
+    return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+// OCP FP8 E4M3 (bias 7, no infinities, max 448, subnormal quantum 2^-9),
+// saturating, round to nearest even.
+__host__ __device__ inline uint8_t f32_to_fp8e4m3(float x) {
+    uint8_t sign = (x < 0.0f || (x == 0.0f && __builtin_signbit(x))) ? 0x80 : 0;
+    float a = __builtin_fabsf(x);
+    if (!(a == a)) return 0x7f;                       // NaN
+    if (a >= 448.0f) return sign | 0x7e;
+    if (a < 0.015625f) {                              // below 2^-6: subnormal grid 2^-9
+        float q = __builtin_rintf(a * 512.0f);        // 0..8 (8 = smallest normal, code 0x08)
+        return sign | (uint8_t)q;
+    }
+    int e;
+    float m = __builtin_frexpf(a, &e);                // a = m 2^e, m in [0.5, 1)
+    float mant = __builtin_rintf((m * 2.0f - 1.0f) * 8.0f);   // 0..8
+    int E = e - 1 + 7;
+    if (mant >= 8.0f) { mant = 0.0f; E += 1; }
+    uint32_t code = ((uint32_t)E << 3) | (uint32_t)mant;
+    if (code > 0x7e) code = 0x7e;
+    return sign | (uint8_t)code;
+}
+__host__ __device__ inline float fp8e4m3_to_f32(uint8_t b) {
+    int e = (b >> 3) & 15, m = b & 7;
+    float v = e == 0 ? (float)m * (1.0f / 512.0f) : __builtin_ldexpf(1.0f + (float)m * 0.125f, e - 7);
+    return (b & 0x80) ? -v : v;
+}
+
+template <typename T> __device__ inline double load_as_f64(const T* p);
+template <> __device__ inline double load_as_f64<double>(const double* p) { return *p; }
+template <> __device__ inline double load_as_f64<float>(const float* p) { return (double)*p; }
+template <> __device__ inline double load_as_f64<uint16_t>(const uint16_t* p) { return (double)bf16_bits_to_f32(*p); }
+template <> __device__ inline double load_as_f64<uint8_t>(const uint8_t* p) { return (double)fp8e4m3_to_f32(*p); }
+
+// ---------------------------------------------------------------------------
+// Work plan of one S.H pass.
+//
+// A pass covers "active" row tiles; active tile a streams the column-chunk
+// list of its class (0..2), each chunk with weight 1 or 2 (the weight
+// multiplies the H rows of that chunk, exactly).  Unit = (active tile, list
+// position).  Units are numbered tile-major (active tile a owns units
+// [unit_offset[a], unit_offset[a+1])) and split evenly over the Pe = min(P, U)
+// persistent work-groups: WG w owns [w U / Pe, (w+1) U / Pe).  Every maximal
+// run of one tile inside one WG's range writes one partial S.H tile at index
+// (w + a) of the partial buffer; (w, a) -> w + a is one-to-one because the
+// ranges are ordered, so the buffer needs at most (P + active tiles) tiles.
+// The update kernel sums the partials of tile a in increasing w, so results
+// do not depend on scheduling.
+//
+// The device-side plan lives in one int32 array (layout below) written by the
+// plan kernel; a "full" pass (every tile, every chunk, weight 1) needs none of
+// it.
+// ---------------------------------------------------------------------------
+struct PlanView {
+    int32_t full;
+    int32_t n_tiles;          // row tiles of the stored panel
+    int32_t n_chunks;         // column chunks (ld / KC)
+    int32_t P;                // launched persistent work-groups
+    // device arrays (unused when full)
+    const int32_t* hdr;       // [0] n_active, [1] U lo, [2] U hi, [3] class_len[0..2] at 3..5
+    const int32_t* active_tile;    // [n_tiles]
+    const int32_t* active_class;   // [n_tiles]
+    const int32_t* unit_offset;    // [n_tiles + 1]
+    const int32_t* class_chunks;   // [3][n_chunks]
+    const int32_t* class_weight;   // [3][n_chunks]
+    const int32_t* tile_active;    // [n_tiles] active index or -1
+};
+
+// int32 words of the device plan for given sizes
+inline int64_t plan_words(int64_t n_tiles, int64_t n_chunks) {
+    return 8 + 3 * n_tiles + 1 + 6 * n_chunks + n_tiles;
+}
+inline PlanView plan_view(int32_t* base, int32_t full, int32_t n_tiles, int32_t n_chunks, int32_t P) {
+    PlanView v;
+    v.full = full; v.n_tiles = n_tiles; v.n_chunks = n_chunks; v.P = P;
+    v.hdr = base;
+    v.active_tile = base + 8;
+    v.active_class = v.active_tile + n_tiles;
+    v.unit_offset = v.active_class + n_tiles;
+    v.class_chunks = v.unit_offset + n_tiles + 1;
+    v.class_weight = v.class_chunks + 3 * n_chunks;
+    v.tile_active = v.class_weight + 3 * n_chunks;
+    return v;
+}
+
+__host__ __device__ inline int64_t wg_start(int64_t w, int64_t U, int64_t Pe) { return w * U / Pe; }
+// the work-group whose range holds unit u
+__host__ __device__ inline int64_t wg_owner(int64_t u, int64_t U, int64_t Pe) { return ((u + 1) * Pe - 1) / U; }
+
+// SplitMix64 (Steele, Lea & Flood 2014): output number c of the stream keyed s.
+__host__ __device__ inline uint64_t splitmix64(uint64_t key, uint64_t c) {
+    uint64_t z = key + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__host__ __device__ inline double uniform24(uint64_t key, uint64_t c) {
+    return (double)(splitmix64(key, c) >> 40) * (1.0 / 16777216.0);
+}
+
+// Index-set sampler of the stochastic variants: m distinct blocks of
+// [0, nb) by a partial Fisher-Yates shuffle (Knuth, TAOCP 2, Algorithm P)
+// driven by the SplitMix64 stream keyed by (seed, 2t + stream); flags[b] = 1
+// for the chosen blocks.  perm: nb ints of scratch.
+__host__ __device__ inline void sample_block_flags(uint64_t seed, int64_t t, int stream, int nb, int m,
+                                                   int32_t* perm, uint8_t* flags) {
+    const uint64_t key = splitmix64(seed, (uint64_t)(2 * t + stream));
+    for (int i = 0; i < nb; ++i) perm[i] = i;
+    for (int i = 0; i < m; ++i) {
+        const double u = uniform24(key, (uint64_t)i);
+        const int j = i + (int)(u * (double)(nb - i));
+        const int32_t tmp = perm[i];
+        perm[i] = perm[j];
+        perm[j] = tmp;
+    }
+    for (int i = 0; i < nb; ++i) flags[i] = 0;
+    for (int i = 0; i < m; ++i) flags[perm[i]] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+// stream.hip: partial S.H of every active tile.  S: rows_pad x ld of stype;
+// H: global rows, n_pad x k (h_f64: double); part: (P + n_tiles) * TR * k of
+// the accumulation type (acc_f64: double).  Returns hipErrorInvalidValue for
+// combinations without a kernel.
+hipError_t launch_stream(const void* S, int32_t stype, int64_t ld, const void* H, int h_f64, int64_t k,
+                         void* part, int acc_f64, const PlanView& plan, hipStream_t stream);
+int stream_uses_mfma(int32_t stype, int h_f64, int acc_f64, int64_t k);
+
+// plan.hip: build the device plan of a sub-sampled step.
+struct PlanRequest {
+    int32_t mode;            // 1 = row SVRG (I only), 2 = block SVRG
+    int32_t n_tiles, n_chunks, tiles_per_block, chunks_per_block, n_blocks;
+    int32_t m;               // sampled blocks per set
+    int32_t independent;
+    uint64_t seed;
+    int64_t t;
+};
+hipError_t launch_plan(const PlanRequest& r, int32_t* plan_base, int32_t* tiles_I, int32_t* tiles_J,
+                       int32_t* counts, hipStream_t stream);
+
+struct UpdateArgs {
+    int64_t rows, rows_pad, n, k;           // panel rows, padded rows, instruments, rank
+    int64_t row0;                           // global row of panel row 0
+    int32_t method, softplus;
+    double eta, eps, alpha, mu;
+    const void* H;        // H_t   (n_pad x k, global rows)
+    void* Hn;             // H_{t+1}
+    void* G;              // AdaGrad G / RMSprop v   (rows_pad x k, panel rows)
+    void* M;              // RMSprop momentum
+    void* Theta;          // softplus parameter
+    void* Mu;             // snapshot gradient (SVRG), may be null
+    void* Gout;           // gradient of this step, may be null
+    const void* part;     // S.H partials
+    const void* gram_eff; // [3][k][k] effective Gram per class (state precision)
+    double cgrad;         // 4 (full / row steps) or 2 (block steps)
+    int32_t store_mu;     // full SVRG step: mu <- g
+    int32_t fp8;          // FP8 storage: scale partials, add the diagonal back
+    const float* panel_scale;
+    const float* diag;    // FP8: S_ii of every panel row
+    int64_t panel_rows;
+    double* tile_gram;    // [tiles][k][k] Gram of H_{t+1} rows
+    double* tile_tr;      // [tiles] sum H_t * SH_t
+    double* tile_kkt;     // [tiles] sum proj(g)^2
+    int32_t* tile_bad;    // [tiles] non-finite gradient count
+};
+hipError_t launch_update(const UpdateArgs& a, int h_f64, const PlanView& plan, hipStream_t stream);
+
+// Per-tile FP64 Gram partials of rows [row0, row0 + tiles*TR) of H.
+hipError_t launch_tile_gram(const void* H, int h_f64, int64_t row0, int64_t rows, int64_t tiles, int64_t k,
+                            double* tile_gram, hipStream_t stream);
+// FP64 Gram of the rows of [0, n) outside [skip_lo, skip_hi).
+hipError_t launch_gram_rows(const void* H, int h_f64, int64_t n, int64_t skip_lo, int64_t skip_hi, int64_t k,
+                            double* out, hipStream_t stream);
+
+// Reduce tile partials: Gram_{t+1} (gram_next64, and gram_eff = 3 copies in
+// state precision), and the statistics of H_t: stats[0] = tr(H^T S H),
+// [1] = ||grad_proj||^2, [2] = non-finite count, [3] = ||Gram_t||_F^2.
+hipError_t launch_finalize(int64_t tiles, int64_t k, const double* tile_gram, const double* tile_tr,
+                           const double* tile_kkt, const int32_t* tile_bad, const double* gram_fixed,
+                           const double* gram_cur64, double* gram_next64, void* gram_eff, int h_f64,
+                           double* stats, hipStream_t stream);
+
+// Effective Gram matrices of a block step: out[0] = Gram_J, out[1] = Gram_I,
+// out[2] = Gram_I + Gram_J from per-tile Gram partials of H_t.
+hipError_t launch_gram_select(int64_t k, const double* tile_gram, const int32_t* tiles_I,
+                              const int32_t* tiles_J, const int32_t* counts, void* gram_eff, int h_f64,
+                              hipStream_t stream);
+
+hipError_t launch_init_H(float* H, int64_t n, int64_t k, uint64_t seed, float scale, hipStream_t stream);
+hipError_t launch_copy_h(const void* src, int src_f64, void* dst, int dst_f64, int64_t count, hipStream_t stream);
+hipError_t launch_softplus_init(void* H, void* Theta, int h_f64, int64_t count, hipStream_t stream);
+hipError_t launch_sum(const void* x, int x_f64, int64_t m, double* out, hipStream_t stream);
+hipError_t launch_piecewise_apply(void* G, const void* g, int h_f64, int64_t m, double c, const double* med,
+                                  hipStream_t stream);
+
+// select.hip: element number ``rank`` (0-based, ascending) of the keys x_i^2
+// (square = 1) or x_i (square = 0; x_i >= 0 required) over m values, by an
+// MSB-first radix selection on the IEEE bit patterns (monotone for
+// non-negative values).  The value goes to out_dev[0] (double).  tmp: device
+// scratch of select_tmp_bytes().
+int64_t select_tmp_bytes();
+hipError_t launch_select(const void* x, int x_f64, int square, int64_t m, int64_t rank, void* tmp,
+                         double* out_dev, hipStream_t stream);
+
+// build_s.hip
+struct BuildOut {
+    void* data; float* scale; float* diag;
+    int64_t rows, rows_pad, ld, n, row0; int32_t dtype; int64_t panel_rows;
+};
+hipError_t launch_standardise(const float* X, int64_t T, int64_t n, void* Z, int z_f64, int64_t ldz, int32_t* bad,
+                              hipStream_t stream);
+// TPDM: Omega (n_exc x ldz, FP32 or FP64) = column-normalised angular rows.
+hipError_t launch_tpdm_omega(const float* X, int64_t T, int64_t n, int lower, void* Omega, int z_f64,
+                             int64_t ldz, int64_t n_exc, void* work, hipStream_t stream);
+int64_t tpdm_work_bytes(int64_t T, int64_t n);
+// sums: device FP64 array of syrk_sum_words(o) words; [0..2] = sum S, sum S^2,
+// sum S_stored^2 on return.  panel_max: FP8 only, zeroed, one word per panel.
+int64_t syrk_sum_words(const BuildOut& o);
+hipError_t launch_syrk_store(const void* Z, int z_f64, int64_t K, int64_t ldz, const BuildOut& o, double* sums,
+                             uint32_t* panel_max, hipStream_t stream);
+// sums: 4 + 3 * rows_pad words
+hipError_t launch_store_dense(const void* src, int src_f64, const BuildOut& o, double* sums,
+                              uint32_t* panel_max, hipStream_t stream);
+hipError_t launch_fp8_decode_check(int32_t* bad, hipStream_t stream);
+// objective pass: per-tile tr(H^T S H) partial and Gram of H (FP64 H).
+hipError_t launch_objective_tiles(const UpdateArgs& a, const PlanView& plan, hipStream_t stream);
+
+}  // namespace symnmf

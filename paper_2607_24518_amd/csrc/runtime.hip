@@ -1,0 +1,942 @@
+// C ABI of the SymNMF library: contexts, S storage, solver state, the step
+// sequence and the stop-rule driven solve loop (paper section "Convergence
+// Criterion"; appendix "Detailed Algorithm Descriptions", family 3).
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace symnmf;
+
+struct symnmf_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cus = 256;
+    int wgs_per_cu = 2;
+    std::string err;
+    // optional HIP-event timing of every kernel a step launches
+    bool profiling = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;   // (kernel id, start/stop)
+};
+
+namespace {
+// kernel ids of the profiling hook
+enum { PK_STREAM = 0, PK_UPDATE = 1, PK_FINALIZE = 2, PK_PLAN = 3, PK_COUNT = 4 };
+
+struct ProfScope {
+    symnmf_ctx* ctx;
+    int id;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(symnmf_ctx* c, int kid) : ctx(c), id(kid) {
+        if (!ctx->profiling) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        (void)hipEventRecord(a, ctx->stream);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->events.push_back({id, {a, b}});
+    }
+};
+}  // namespace
+
+namespace {
+
+constexpr int HCAP = 128;   // ring of per-step device statistics
+
+struct DevBuf {
+    void* p = nullptr;
+};
+
+symnmf_status fail(symnmf_ctx* ctx, symnmf_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return code;
+}
+
+#define HIP_OK(ctx, expr)                                                                              \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? SYMNMF_ENOMEM : SYMNMF_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                             \
+    } while (0)
+
+int64_t elem_bytes(int32_t dtype) {
+    switch (dtype) {
+        case SYMNMF_S_FP32: return 4;
+        case SYMNMF_S_BF16: return 2;
+        case SYMNMF_S_FP8: return 1;
+        case SYMNMF_S_FP64: return 8;
+    }
+    return 0;
+}
+
+struct Layout {
+    int64_t ld, rows_pad, data_bytes, scale_off, diag_off, total;
+};
+
+Layout s_layout(int64_t rows, int64_t n, int32_t dtype, int64_t panel_rows) {
+    Layout L;
+    L.ld = round_up(n, PAD);
+    L.rows_pad = round_up(rows, PAD);
+    L.data_bytes = round_up(L.rows_pad * L.ld * elem_bytes(dtype), 256);
+    L.scale_off = L.data_bytes;
+    L.diag_off = L.data_bytes;
+    L.total = L.data_bytes;
+    if (dtype == SYMNMF_S_FP8) {
+        const int64_t panels = (rows + panel_rows - 1) / panel_rows;
+        L.diag_off = L.scale_off + round_up(panels * 4, 256);
+        L.total = L.diag_off + round_up(L.rows_pad * 4, 256);
+    }
+    return L;
+}
+
+}  // namespace
+
+struct symnmf_state {
+    symnmf_ctx* ctx = nullptr;
+    symnmf_S S{};
+    symnmf_params p{};
+    int64_t k = 0, n = 0, n_pad = 0, rows = 0, rows_pad = 0, row0 = 0, tiles = 0, chunks = 0;
+    int h_f64 = 0;
+    int64_t hsz = 4;
+    int32_t P = 0;
+    std::vector<void*> allocs;
+    void* H[2] = {nullptr, nullptr};
+    int cur = 0;
+    void *G = nullptr, *M = nullptr, *Theta = nullptr, *Mu = nullptr, *Gout = nullptr, *part = nullptr;
+    double *tile_gram = nullptr, *tile_tr = nullptr, *tile_kkt = nullptr;
+    int32_t* tile_bad = nullptr;
+    double* gram64[2] = {nullptr, nullptr};
+    void* gram_eff = nullptr;
+    double* gram_fixed = nullptr;
+    double* ring = nullptr;
+    int32_t *plan = nullptr, *tiles_I = nullptr, *tiles_J = nullptr, *counts = nullptr;
+    void* sel = nullptr;
+    double* scal = nullptr;          // device scalars (median, sums)
+    int64_t t = 0;
+    int ring_full[HCAP] = {};
+    double ring_phi[HCAP] = {};
+    // control state of the stop rule and the check-time rules
+    double phi = 1.0;
+    bool have_E0 = false, have_prev = false;
+    double E0 = 0.0, E_prev = 0.0;
+    int64_t stag_run = 0;
+    bool pw_enabled = true, pw_cool = false;
+    double pw_cool_target = 0.0, pw_E_reset = 0.0;
+    int64_t pw_resets = 0;
+    std::chrono::steady_clock::time_point t0;
+    symnmf_stats last{};
+};
+
+extern "C" {
+
+int32_t symnmf_abi_version(void) { return 1; }
+
+void symnmf_params_default(symnmf_params* p) {
+    std::memset(p, 0, sizeof(*p));
+    p->method = SYMNMF_ADAGRAD;
+    p->softplus = 0;
+    p->eta = 0.02;
+    p->eps = 1e-10;
+    p->alpha = 0.99;
+    p->mu = 0.5;
+    p->c = 10.0;
+    p->c_r = 10.0;
+    p->eps_med = 1e-30;
+    p->row_frac = 0.5;
+    p->phi0 = 0.75;
+    p->c_grow = 10.0;
+    p->grow_checks = 3;
+    p->snapshot_s = 10;
+    p->block_rows = 1024;
+    p->independent_blocks = 1;
+    p->delta = 10;
+    p->warmup = 50;
+    p->max_iter = 1000;
+    p->tau_E = 0.1;
+    p->tau_g_inf = 1e-4;
+    p->n_ref = 1e4;
+    p->tau_stag = 1e-5;
+    p->seed = 0;
+}
+
+symnmf_status symnmf_create(symnmf_ctx** out, int32_t device, void* hip_stream) {
+    if (!out) return SYMNMF_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SYMNMF_EDEVICE;
+    auto* ctx = new symnmf_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return SYMNMF_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->cus = prop.multiProcessorCount;
+    if (const char* e = std::getenv("SYMNMF_WGS_PER_CU")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 16) ctx->wgs_per_cu = v;
+    }
+    *out = ctx;
+    return SYMNMF_OK;
+}
+
+void symnmf_destroy(symnmf_ctx* ctx) { delete ctx; }
+
+const char* symnmf_last_error(const symnmf_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int64_t symnmf_S_bytes(int64_t rows, int64_t n, int32_t dtype, int64_t fp8_panel_rows) {
+    if (rows < 1 || n < 1 || elem_bytes(dtype) == 0) return -1;
+    if (dtype == SYMNMF_S_FP8 && fp8_panel_rows < 1) return -1;
+    return s_layout(rows, n, dtype, fp8_panel_rows).total;
+}
+
+static symnmf_status fill_descriptor(symnmf_ctx* ctx, void* buf, int64_t n, int64_t row0, int64_t rows, int32_t dtype,
+                                     int32_t kind, int64_t panel_rows, const Layout& L, const double* sums,
+                                     symnmf_S* out) {
+    (void)ctx;
+    std::memset(out, 0, sizeof(*out));
+    out->data = buf;
+    out->panel_scale = dtype == SYMNMF_S_FP8 ? (float*)((char*)buf + L.scale_off) : nullptr;
+    out->diag = dtype == SYMNMF_S_FP8 ? (float*)((char*)buf + L.diag_off) : nullptr;
+    out->n = n;
+    out->row0 = row0;
+    out->rows = rows;
+    out->ld = L.ld;
+    out->rows_pad = L.rows_pad;
+    out->fp8_panel_rows = dtype == SYMNMF_S_FP8 ? panel_rows : 0;
+    out->dtype = dtype;
+    out->kind = kind;
+    out->sum = sums[0];
+    out->fro2 = sums[1];
+    out->fro2_stored = sums[2];
+    out->mean = sums[0] / ((double)rows * (double)n);
+    return SYMNMF_OK;
+}
+
+static BuildOut build_out(void* buf, const Layout& L, int64_t n, int64_t row0, int64_t rows, int32_t dtype,
+                          int64_t panel_rows) {
+    BuildOut o;
+    o.data = buf;
+    o.scale = dtype == SYMNMF_S_FP8 ? (float*)((char*)buf + L.scale_off) : nullptr;
+    o.diag = dtype == SYMNMF_S_FP8 ? (float*)((char*)buf + L.diag_off) : nullptr;
+    o.rows = rows;
+    o.rows_pad = L.rows_pad;
+    o.ld = L.ld;
+    o.n = n;
+    o.row0 = row0;
+    o.dtype = dtype;
+    o.panel_rows = dtype == SYMNMF_S_FP8 ? panel_rows : 1;
+    return o;
+}
+
+symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuild_params* p, void* buf,
+                             int64_t buf_bytes, symnmf_S* out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!X || !p || !buf || !out) return fail(ctx, SYMNMF_EINVAL, "build_S: null argument");
+    if (p->n < 1 || p->T < 2) return fail(ctx, SYMNMF_EINVAL, "build_S: need n >= 1 and T >= 2 (n=%lld T=%lld)",
+                                          (long long)p->n, (long long)p->T);
+    if (p->row0 < 0 || p->rows < 1 || p->row0 + p->rows > p->n)
+        return fail(ctx, SYMNMF_EINVAL, "build_S: bad row range [%lld, %lld) of n=%lld", (long long)p->row0,
+                    (long long)(p->row0 + p->rows), (long long)p->n);
+    if (p->kind != SYMNMF_ABS_CORR && p->kind != SYMNMF_TPDM) return fail(ctx, SYMNMF_EINVAL, "build_S: bad kind");
+    if (elem_bytes(p->dtype) == 0) return fail(ctx, SYMNMF_EINVAL, "build_S: bad dtype");
+    if (p->dtype == SYMNMF_S_FP8 && p->fp8_panel_rows < 1)
+        return fail(ctx, SYMNMF_EINVAL, "build_S: fp8_panel_rows must be >= 1");
+    const int64_t n = p->n, T = p->T;
+    int64_t K = T;
+    if (p->kind == SYMNMF_TPDM) {
+        if (!(p->q > 0.0 && p->q <= 1.0)) return fail(ctx, SYMNMF_EINVAL, "build_S: q must be in (0, 1]");
+        K = (int64_t)std::floor(p->q * (double)T);
+        if (K < 1) return fail(ctx, SYMNMF_EINVAL, "build_S: floor(q T) = 0 exceedances");
+        if (T > 32768) return fail(ctx, SYMNMF_EUNSUPPORTED, "build_S: TPDM supports T <= 32768");
+    }
+    const Layout L = s_layout(p->rows, n, p->dtype, p->fp8_panel_rows);
+    if (buf_bytes < L.total)
+        return fail(ctx, SYMNMF_ENOMEM, "build_S: buffer has %lld bytes, needs %lld", (long long)buf_bytes,
+                    (long long)L.total);
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int z_f64 = p->dtype == SYMNMF_S_FP64;
+    const int64_t zsz = z_f64 ? 8 : 4;
+    const int64_t ldz = round_up(std::max(n, p->row0 + L.rows_pad), 256);
+    const int64_t Kpad = round_up(K, 16);
+    const BuildOut o = build_out(buf, L, n, p->row0, p->rows, p->dtype, p->fp8_panel_rows);
+    const int64_t nsum = syrk_sum_words(o);
+    const int64_t panels = p->dtype == SYMNMF_S_FP8 ? (p->rows + p->fp8_panel_rows - 1) / p->fp8_panel_rows : 1;
+    void *Z = nullptr, *work = nullptr, *sums = nullptr, *pmax = nullptr, *bad = nullptr;
+    auto cleanup = [&]() {
+        if (Z) (void)hipFree(Z);
+        if (work) (void)hipFree(work);
+        if (sums) (void)hipFree(sums);
+        if (pmax) (void)hipFree(pmax);
+        if (bad) (void)hipFree(bad);
+    };
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(hipMalloc(&Z, Kpad * ldz * zsz));
+    chk(hipMalloc(&sums, nsum * 8));
+    chk(hipMalloc(&pmax, panels * 4));
+    chk(hipMalloc(&bad, 4));
+    if (p->kind == SYMNMF_TPDM) chk(hipMalloc(&work, tpdm_work_bytes(T, n)));
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(ctx, SYMNMF_ENOMEM, "build_S: device allocation failed: %s", hipGetErrorString(e));
+    }
+    chk(hipMemsetAsync(Z, 0, Kpad * ldz * zsz, st));
+    chk(hipMemsetAsync(pmax, 0, panels * 4, st));
+    chk(hipMemsetAsync(bad, 0, 4, st));
+    chk(hipMemsetAsync(buf, 0, L.total, st));
+    if (p->kind == SYMNMF_ABS_CORR) chk(launch_standardise(X, T, n, Z, z_f64, ldz, (int32_t*)bad, st));
+    else chk(launch_tpdm_omega(X, T, n, p->lower_tail, Z, z_f64, ldz, K, work, st));
+    int32_t hbad = 0;
+    chk(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
+    chk(hipStreamSynchronize(st));
+    if (e == hipSuccess && hbad) {
+        cleanup();
+        return fail(ctx, SYMNMF_EINVAL, "build_S: %d zero-variance column(s)", hbad);
+    }
+    chk(launch_syrk_store(Z, z_f64, Kpad, ldz, o, (double*)sums, (uint32_t*)pmax, st));
+    double hs[3] = {0, 0, 0};
+    chk(hipMemcpyAsync(hs, sums, 24, hipMemcpyDeviceToHost, st));
+    chk(hipStreamSynchronize(st));
+    cleanup();
+    if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "build_S: %s", hipGetErrorString(e));
+    if (!std::isfinite(hs[0]) || !std::isfinite(hs[1])) return fail(ctx, SYMNMF_ENUMERIC, "build_S: non-finite S");
+    return fill_descriptor(ctx, buf, n, p->row0, p->rows, p->dtype, p->kind, p->fp8_panel_rows, L, hs, out);
+}
+
+symnmf_status symnmf_S_load(symnmf_ctx* ctx, const void* src, int32_t src_is_f64, int64_t n, int64_t row0,
+                            int64_t rows, int32_t dtype, int64_t fp8_panel_rows, void* buf, int64_t buf_bytes,
+                            symnmf_S* out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!src || !buf || !out) return fail(ctx, SYMNMF_EINVAL, "S_load: null argument");
+    if (n < 1 || row0 < 0 || rows < 1 || row0 + rows > n) return fail(ctx, SYMNMF_EINVAL, "S_load: bad shape");
+    if (elem_bytes(dtype) == 0) return fail(ctx, SYMNMF_EINVAL, "S_load: bad dtype");
+    if (dtype == SYMNMF_S_FP8 && fp8_panel_rows < 1) return fail(ctx, SYMNMF_EINVAL, "S_load: fp8_panel_rows >= 1");
+    const Layout L = s_layout(rows, n, dtype, fp8_panel_rows);
+    if (buf_bytes < L.total) return fail(ctx, SYMNMF_ENOMEM, "S_load: buffer too small");
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const BuildOut o = build_out(buf, L, n, row0, rows, dtype, fp8_panel_rows);
+    const int64_t panels = dtype == SYMNMF_S_FP8 ? (rows + fp8_panel_rows - 1) / fp8_panel_rows : 1;
+    void *sums = nullptr, *pmax = nullptr;
+    HIP_OK(ctx, hipMalloc(&sums, (4 + 3 * L.rows_pad) * 8));
+    HIP_OK(ctx, hipMalloc(&pmax, panels * 4));
+    hipError_t e = hipMemsetAsync(pmax, 0, panels * 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(buf, 0, L.total, st);
+    if (e == hipSuccess) e = launch_store_dense(src, src_is_f64, o, (double*)sums, (uint32_t*)pmax, st);
+    double hs[3] = {0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(hs, sums, 24, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(sums);
+    (void)hipFree(pmax);
+    if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "S_load: %s", hipGetErrorString(e));
+    if (!std::isfinite(hs[0]) || !std::isfinite(hs[1])) return fail(ctx, SYMNMF_ENUMERIC, "S_load: non-finite S");
+    return fill_descriptor(ctx, buf, n, row0, rows, dtype, SYMNMF_ABS_CORR, fp8_panel_rows, L, hs, out);
+}
+
+symnmf_status symnmf_init_H(symnmf_ctx* ctx, const symnmf_S* S, int64_t k, uint64_t seed, float* H) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!S || !H || k < 1 || k > KMAX) return fail(ctx, SYMNMF_EINVAL, "init_H: bad argument (k=%lld)", (long long)k);
+    if (!(S->mean >= 0.0) || !std::isfinite(S->mean)) return fail(ctx, SYMNMF_EINVAL, "init_H: S has no valid mean");
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    const float scale = (float)std::sqrt(S->mean / (double)k);
+    HIP_OK(ctx, launch_init_H(H, S->n, k, seed, scale, ctx->stream));
+    return SYMNMF_OK;
+}
+
+void symnmf_state_destroy(symnmf_state* st) {
+    if (!st) return;
+    for (void* p : st->allocs)
+        if (p) (void)hipFree(p);
+    delete st;
+}
+
+static symnmf_status state_alloc(symnmf_state* st, void** out, int64_t bytes) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes > 0 ? bytes : 8);
+    if (e != hipSuccess)
+        return fail(st->ctx, SYMNMF_ENOMEM, "state: hipMalloc(%lld) failed: %s", (long long)bytes, hipGetErrorString(e));
+    st->allocs.push_back(p);
+    e = hipMemsetAsync(p, 0, bytes > 0 ? bytes : 8, st->ctx->stream);
+    if (e != hipSuccess) return fail(st->ctx, SYMNMF_EDEVICE, "state: memset failed: %s", hipGetErrorString(e));
+    *out = p;
+    return SYMNMF_OK;
+}
+
+static double tau_g_of(const symnmf_state* st) {
+    const double n = (double)st->n;
+    return st->p.tau_g_inf * std::max(1.0, st->p.n_ref / n);
+}
+
+symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k, const symnmf_params* p,
+                                  const void* H0, int32_t h0_is_f64, symnmf_state** out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!S || !p || !H0 || !out) return fail(ctx, SYMNMF_EINVAL, "state_create: null argument");
+    *out = nullptr;
+    if (k < 1 || k > KMAX) return fail(ctx, SYMNMF_EINVAL, "state_create: k=%lld outside [1, %d]", (long long)k, KMAX);
+    if (k > S->n) return fail(ctx, SYMNMF_EINVAL, "state_create: k > n");
+    const int h_f64 = S->dtype == SYMNMF_S_FP64;
+    if (h_f64 && !h0_is_f64) return fail(ctx, SYMNMF_EINVAL, "state_create: FP64 S needs an FP64 H0");
+    if (h_f64 && k > 32) return fail(ctx, SYMNMF_EUNSUPPORTED, "state_create: FP64 state supports k <= 32");
+    if (p->method < SYMNMF_ADAGRAD || p->method > SYMNMF_BLOCK_SVRG)
+        return fail(ctx, SYMNMF_EINVAL, "state_create: bad method");
+    if (!(p->eta > 0.0) || !(p->eps >= 0.0) || p->delta < 1 || p->max_iter < 0)
+        return fail(ctx, SYMNMF_EINVAL, "state_create: bad eta/eps/delta/max_iter");
+    const bool svrg = p->method == SYMNMF_ROW_SVRG || p->method == SYMNMF_BLOCK_SVRG;
+    if (svrg) {
+        if (S->rows != S->n || S->row0 != 0)
+            return fail(ctx, SYMNMF_EUNSUPPORTED, "state_create: SVRG methods need the full matrix, not a panel");
+        if (p->block_rows < 256 || p->block_rows % 256)
+            return fail(ctx, SYMNMF_EINVAL, "state_create: block_rows must be a positive multiple of 256");
+        if (p->snapshot_s < 1 || p->delta % p->snapshot_s)
+            return fail(ctx, SYMNMF_EINVAL, "state_create: delta must be a multiple of snapshot_s");
+        if ((S->n + p->block_rows - 1) / p->block_rows > 4096)
+            return fail(ctx, SYMNMF_EUNSUPPORTED, "state_create: more than 4096 row blocks");
+        if (p->method == SYMNMF_ROW_SVRG && !(p->row_frac > 0.0 && p->row_frac <= 1.0))
+            return fail(ctx, SYMNMF_EINVAL, "state_create: row_frac in (0, 1]");
+        if (p->method == SYMNMF_BLOCK_SVRG && !(p->phi0 > 0.0 && p->phi0 <= 1.0))
+            return fail(ctx, SYMNMF_EINVAL, "state_create: phi0 in (0, 1]");
+    }
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    auto* st = new symnmf_state();
+    st->ctx = ctx;
+    st->S = *S;
+    st->p = *p;
+    st->k = k;
+    st->n = S->n;
+    st->n_pad = round_up(S->n, PAD);
+    st->rows = S->rows;
+    st->rows_pad = S->rows_pad;
+    st->row0 = S->row0;
+    st->tiles = S->rows_pad / TR;
+    st->chunks = S->ld / KC;
+    st->h_f64 = h_f64;
+    st->hsz = h_f64 ? 8 : 4;
+    st->P = ctx->cus * ctx->wgs_per_cu;
+    st->phi = p->method == SYMNMF_BLOCK_SVRG ? p->phi0 : 1.0;
+    const int64_t hbytes = std::max(st->n_pad, st->row0 + st->rows_pad) * k * st->hsz;
+    const int64_t pbytes = st->rows_pad * k * st->hsz;
+    symnmf_status s;
+#define ALLOC(ptr, bytes)                                              \
+    do {                                                               \
+        void* tmp_ = nullptr;                                          \
+        if ((s = state_alloc(st, &tmp_, (bytes))) != SYMNMF_OK) {      \
+            symnmf_state_destroy(st);                                  \
+            return s;                                                  \
+        }                                                              \
+        ptr = (decltype(ptr))tmp_;                                     \
+    } while (0)
+    ALLOC(st->H[0], hbytes);
+    ALLOC(st->H[1], hbytes);
+    ALLOC(st->G, pbytes);
+    if (p->method == SYMNMF_RMSPROP) ALLOC(st->M, pbytes);
+    if (p->softplus) ALLOC(st->Theta, pbytes);
+    if (svrg) ALLOC(st->Mu, pbytes);
+    ALLOC(st->Gout, pbytes);
+    ALLOC(st->part, ((int64_t)st->P + st->tiles) * TR * k * st->hsz);
+    ALLOC(st->tile_gram, st->tiles * k * k * 8);
+    ALLOC(st->tile_tr, st->tiles * 8);
+    ALLOC(st->tile_kkt, st->tiles * 8);
+    ALLOC(st->tile_bad, st->tiles * 4);
+    ALLOC(st->gram64[0], k * k * 8);
+    ALLOC(st->gram64[1], k * k * 8);
+    ALLOC(st->gram_eff, 3 * k * k * st->hsz);
+    ALLOC(st->ring, HCAP * 4 * 8);
+    ALLOC(st->scal, 16 * 8);
+    ALLOC(st->sel, select_tmp_bytes());
+    if (svrg) {
+        ALLOC(st->plan, plan_words(st->tiles, st->chunks) * 4);
+        ALLOC(st->tiles_I, st->tiles * 4);
+        ALLOC(st->tiles_J, st->tiles * 4);
+        ALLOC(st->counts, 16);
+    }
+    const bool panel = st->rows < st->n;
+    if (panel) ALLOC(st->gram_fixed, k * k * 8);
+#undef ALLOC
+    hipStream_t sm = ctx->stream;
+    hipError_t e = launch_copy_h(H0, h0_is_f64, st->H[0], h_f64, st->n * k, sm);
+    if (e == hipSuccess && p->softplus) {
+        // Theta and softplus(Theta) for the panel rows
+        void* Hp = (char*)st->H[0] + st->row0 * k * st->hsz;
+        e = launch_softplus_init(Hp, st->Theta, h_f64, st->rows * k, sm);
+    }
+    if (e == hipSuccess && panel)
+        e = launch_gram_rows(st->H[0], h_f64, st->n, st->row0, st->row0 + st->rows, k, st->gram_fixed, sm);
+    if (e == hipSuccess) e = launch_tile_gram(st->H[0], h_f64, st->row0, st->rows, st->tiles, k, st->tile_gram, sm);
+    if (e == hipSuccess)
+        e = launch_finalize(st->tiles, k, st->tile_gram, st->tile_tr, st->tile_kkt, st->tile_bad, st->gram_fixed,
+                            nullptr, st->gram64[0], st->gram_eff, h_f64, st->scal, sm);
+    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    if (e != hipSuccess) {
+        symnmf_state_destroy(st);
+        return fail(ctx, SYMNMF_EDEVICE, "state_create: %s", hipGetErrorString(e));
+    }
+    st->t0 = std::chrono::steady_clock::now();
+    *out = st;
+    return SYMNMF_OK;
+}
+
+static symnmf_status do_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st) {
+    const symnmf_params& p = st->p;
+    hipStream_t sm = ctx->stream;
+    const int64_t t = st->t;
+    int kind = 0;   // 0 full, 1 row, 2 block
+    if (p.method == SYMNMF_ROW_SVRG) kind = (t % p.snapshot_s == 0) ? 0 : 1;
+    if (p.method == SYMNMF_BLOCK_SVRG) kind = (st->phi >= 1.0 || t % p.snapshot_s == 0) ? 0 : 2;
+    PlanView pv = plan_view(st->plan, kind == 0, (int32_t)st->tiles, (int32_t)st->chunks, st->P);
+    if (kind != 0) {
+        PlanRequest r;
+        r.mode = kind;
+        r.n_tiles = (int32_t)st->tiles;
+        r.n_chunks = (int32_t)st->chunks;
+        r.tiles_per_block = (int32_t)(p.block_rows / TR);
+        r.chunks_per_block = (int32_t)(p.block_rows / KC);
+        r.n_blocks = (int32_t)((st->n + p.block_rows - 1) / p.block_rows);
+        const double frac = kind == 1 ? p.row_frac : std::sqrt(st->phi);
+        r.m = (int32_t)std::min<int64_t>(r.n_blocks, (int64_t)std::ceil(frac * (double)r.n_blocks));
+        r.independent = p.independent_blocks;
+        r.seed = p.seed;
+        r.t = t;
+        ProfScope ps(ctx, PK_PLAN);
+        HIP_OK(ctx, launch_plan(r, st->plan, st->tiles_I, st->tiles_J, st->counts, sm));
+        if (kind == 2)
+            HIP_OK(ctx, launch_gram_select(st->k, st->tile_gram, st->tiles_I, st->tiles_J, st->counts, st->gram_eff,
+                                           st->h_f64, sm));
+    }
+    const void* Hc = st->H[st->cur];
+    void* Hn = st->H[1 - st->cur];
+    {
+        ProfScope ps(ctx, PK_STREAM);
+        HIP_OK(ctx, launch_stream(S->data, S->dtype, S->ld, Hc, st->h_f64, st->k, st->part, st->h_f64, pv, sm));
+    }
+    UpdateArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.rows = st->rows;
+    a.rows_pad = st->rows_pad;
+    a.n = st->n;
+    a.k = st->k;
+    a.row0 = st->row0;
+    a.method = p.method == SYMNMF_RMSPROP ? SYMNMF_RMSPROP : SYMNMF_ADAGRAD;
+    a.softplus = p.softplus;
+    a.eta = p.eta;
+    a.eps = p.eps;
+    a.alpha = p.alpha;
+    a.mu = p.mu;
+    a.H = Hc;
+    a.Hn = Hn;
+    a.G = st->G;
+    a.M = st->M;
+    a.Theta = st->Theta;
+    a.Mu = st->Mu;
+    a.Gout = st->Gout;
+    a.part = st->part;
+    a.gram_eff = st->gram_eff;
+    a.cgrad = kind == 2 ? 2.0 : 4.0;
+    a.store_mu = (kind == 0 && st->Mu) ? 1 : 0;
+    a.fp8 = S->dtype == SYMNMF_S_FP8;
+    a.panel_scale = S->panel_scale;
+    a.diag = S->diag;
+    a.panel_rows = S->fp8_panel_rows > 0 ? S->fp8_panel_rows : 1;
+    a.tile_gram = st->tile_gram;
+    a.tile_tr = st->tile_tr;
+    a.tile_kkt = st->tile_kkt;
+    a.tile_bad = st->tile_bad;
+    {
+        ProfScope ps(ctx, PK_UPDATE);
+        HIP_OK(ctx, launch_update(a, st->h_f64, pv, sm));
+    }
+    const int slot = (int)(t % HCAP);
+    ProfScope psf(ctx, PK_FINALIZE);
+    HIP_OK(ctx, launch_finalize(st->tiles, st->k, st->tile_gram, st->tile_tr, st->tile_kkt, st->tile_bad,
+                                st->gram_fixed, st->gram64[st->cur], st->gram64[1 - st->cur], st->gram_eff, st->h_f64,
+                                st->ring + slot * 4, sm));
+    st->ring_full[slot] = kind == 0;
+    st->ring_phi[slot] = kind == 2 ? st->phi : 1.0;
+    st->cur = 1 - st->cur;
+    st->t = t + 1;
+    return SYMNMF_OK;
+}
+
+// statistics of step t (must be one of the last HCAP steps); synchronises
+static symnmf_status read_stats(symnmf_state* st, int64_t t, symnmf_stats* out) {
+    symnmf_ctx* ctx = st->ctx;
+    const int slot = (int)(t % HCAP);
+    double d[4];
+    HIP_OK(ctx, hipMemcpyAsync(d, st->ring + slot * 4, 32, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+    std::memset(out, 0, sizeof(*out));
+    out->t = t;
+    out->full = st->ring_full[slot];
+    out->phi = st->ring_phi[slot];
+    const double nan = std::nan("");
+    if (out->full) {
+        out->f = st->S.fro2_stored - 2.0 * d[0] + d[3];
+        out->E = out->f / st->S.fro2_stored;
+        out->kkt = std::sqrt(d[1]) / ((double)st->rows * (double)st->k);
+    } else {
+        out->f = nan;
+        out->E = nan;
+        out->kkt = nan;
+    }
+    out->stag = nan;
+    out->nonfinite = (int32_t)d[2];
+    out->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - st->t0).count();
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st, symnmf_stats* out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!S || !st || st->ctx != ctx) return fail(ctx, SYMNMF_EINVAL, "step: bad state or context");
+    if (S->data != st->S.data || S->n != st->n || S->rows != st->rows)
+        return fail(ctx, SYMNMF_EINVAL, "step: S does not match the state");
+    symnmf_status s = do_step(ctx, S, st);
+    if (s != SYMNMF_OK) return s;
+    if (out) {
+        s = read_stats(st, st->t - 1, out);
+        if (s != SYMNMF_OK) return s;
+        st->last = *out;
+        if (out->nonfinite) return fail(ctx, SYMNMF_ENUMERIC, "step %lld: %d non-finite gradient entries",
+                                        (long long)out->t, out->nonfinite);
+    }
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_state_stats(symnmf_ctx* ctx, symnmf_state* st, symnmf_stats* out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!st || !out || st->t < 1) return fail(ctx, SYMNMF_EINVAL, "state_stats: no step taken");
+    return read_stats(st, st->t - 1, out);
+}
+
+symnmf_status symnmf_state_set_phi(symnmf_state* st, double phi) {
+    if (!st || !(phi > 0.0 && phi <= 1.0)) return SYMNMF_EINVAL;
+    st->phi = phi;
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_state_read(symnmf_ctx* ctx, symnmf_state* st, int32_t which, void* dst) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!st || !dst) return fail(ctx, SYMNMF_EINVAL, "state_read: null argument");
+    const void* src = nullptr;
+    int64_t count = st->rows * st->k;
+    int64_t off = 0;
+    switch (which) {
+        case 0: src = st->H[st->cur]; count = st->n * st->k; break;
+        case 1: src = st->H[1 - st->cur]; count = st->n * st->k; break;
+        case 2: src = st->G; break;
+        case 3: src = st->M; break;
+        case 4: src = st->Theta; break;
+        case 5: src = st->Mu; break;
+        case 6: src = st->Gout; break;
+        default: return fail(ctx, SYMNMF_EINVAL, "state_read: bad buffer id %d", which);
+    }
+    (void)off;
+    if (!src) return fail(ctx, SYMNMF_EINVAL, "state_read: buffer %d not used by this method", which);
+    HIP_OK(ctx, hipMemcpyAsync(dst, src, count * st->hsz, hipMemcpyDeviceToDevice, ctx->stream));
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_objective(symnmf_ctx* ctx, const symnmf_S* S, const void* H, int32_t h_is_f64, int64_t k,
+                               double* f, double* E) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!S || !H || k < 1 || k > KMAX) return fail(ctx, SYMNMF_EINVAL, "objective: bad argument");
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    hipStream_t sm = ctx->stream;
+    const int64_t tiles = S->rows_pad / TR, chunks = S->ld / KC;
+    const int32_t P = ctx->cus * ctx->wgs_per_cu;
+    const int64_t hrows = std::max(round_up(S->n, PAD), S->row0 + S->rows_pad);
+    void *Hd = nullptr, *part = nullptr, *tg = nullptr, *ttr = nullptr, *tk = nullptr, *tb = nullptr, *g = nullptr,
+         *gi = nullptr, *sc = nullptr;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(hipMalloc(&Hd, hrows * k * 8));
+    chk(hipMalloc(&part, ((int64_t)P + tiles) * TR * k * 8));
+    chk(hipMalloc(&tg, tiles * k * k * 8));
+    chk(hipMalloc(&ttr, tiles * 8));
+    chk(hipMalloc(&tk, tiles * 8));
+    chk(hipMalloc(&tb, tiles * 4));
+    chk(hipMalloc(&g, k * k * 8));
+    chk(hipMalloc(&gi, 3 * k * k * 8));
+    chk(hipMalloc(&sc, 4 * 8));
+    if (e == hipSuccess) {
+        chk(hipMemsetAsync(Hd, 0, hrows * k * 8, sm));
+        chk(launch_copy_h(H, h_is_f64, Hd, 1, S->n * k, sm));
+        PlanView pv = plan_view(nullptr, 1, (int32_t)tiles, (int32_t)chunks, P);
+        chk(launch_stream(S->data, S->dtype, S->ld, Hd, 1, k, part, 1, pv, sm));
+        UpdateArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.rows = S->rows;
+        a.rows_pad = S->rows_pad;
+        a.n = S->n;
+        a.k = k;
+        a.row0 = S->row0;
+        a.H = Hd;
+        a.part = part;
+        a.fp8 = S->dtype == SYMNMF_S_FP8;
+        a.panel_scale = S->panel_scale;
+        a.diag = S->diag;
+        a.panel_rows = S->fp8_panel_rows > 0 ? S->fp8_panel_rows : 1;
+        a.tile_gram = (double*)tg;
+        a.tile_tr = (double*)ttr;
+        a.tile_kkt = (double*)tk;
+        a.tile_bad = (int32_t*)tb;
+        chk(launch_objective_tiles(a, pv, sm));
+        chk(launch_finalize(tiles, k, (double*)tg, (double*)ttr, (double*)tk, (int32_t*)tb, nullptr, nullptr,
+                            (double*)g, gi, 1, (double*)sc, sm));
+    }
+    std::vector<double> gram(k * k);
+    double d[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) chk(hipMemcpyAsync(gram.data(), g, k * k * 8, hipMemcpyDeviceToHost, sm));
+    if (e == hipSuccess) chk(hipMemcpyAsync(d, sc, 32, hipMemcpyDeviceToHost, sm));
+    if (e == hipSuccess) chk(hipStreamSynchronize(sm));
+    for (void* p : {Hd, part, tg, ttr, tk, tb, g, gi, sc})
+        if (p) (void)hipFree(p);
+    if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "objective: %s", hipGetErrorString(e));
+    double gn = 0.0;
+    for (double v : gram) gn += v * v;
+    const double fv = S->fro2_stored - 2.0 * d[0] + gn;
+    if (f) *f = fv;
+    if (E) *E = fv / S->fro2_stored;
+    if (!std::isfinite(fv)) return fail(ctx, SYMNMF_ENUMERIC, "objective: non-finite value");
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_median_sq(symnmf_ctx* ctx, const float* g, int64_t m, float* out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!g || m < 1 || !out) return fail(ctx, SYMNMF_EINVAL, "median_sq: bad argument");
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    void *tmp = nullptr, *res = nullptr;
+    HIP_OK(ctx, hipMalloc(&tmp, select_tmp_bytes()));
+    hipError_t e = hipMalloc(&res, 8);
+    double v = 0.0;
+    if (e == hipSuccess) e = launch_select(g, 0, 1, m, (m - 1) / 2, tmp, (double*)res, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&v, res, 8, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(tmp);
+    if (res) (void)hipFree(res);
+    if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "median_sq: %s", hipGetErrorString(e));
+    *out = (float)v;
+    return SYMNMF_OK;
+}
+
+// G <- max(c g^2, c median(g^2)) with g the last step's gradient.
+static symnmf_status piecewise_reset_impl(symnmf_state* st, double c, double* median_out) {
+    symnmf_ctx* ctx = st->ctx;
+    const int64_t m = st->rows * st->k;
+    HIP_OK(ctx, launch_select(st->Gout, st->h_f64, 1, m, (m - 1) / 2, st->sel, st->scal, ctx->stream));
+    HIP_OK(ctx, launch_piecewise_apply(st->G, st->Gout, st->h_f64, m, c, st->scal, ctx->stream));
+    if (median_out) {
+        HIP_OK(ctx, hipMemcpyAsync(median_out, st->scal, 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_piecewise_reset(symnmf_ctx* ctx, symnmf_state* st, double c, float* median_out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!st || st->t < 1) return fail(ctx, SYMNMF_EINVAL, "piecewise_reset: no step taken");
+    double med = 0.0;
+    symnmf_status s = piecewise_reset_impl(st, c, &med);
+    if (s == SYMNMF_OK && median_out) *median_out = (float)med;
+    return s;
+}
+
+static symnmf_status device_sum(symnmf_state* st, const void* x, double* out) {
+    symnmf_ctx* ctx = st->ctx;
+    HIP_OK(ctx, launch_sum(x, st->h_f64, st->rows * st->k, st->scal + 1, ctx->stream));
+    HIP_OK(ctx, hipMemcpyAsync(out, st->scal + 1, 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+    return SYMNMF_OK;
+}
+
+static symnmf_status median_of_last_gradient(symnmf_state* st, double* med) {
+    symnmf_ctx* ctx = st->ctx;
+    const int64_t m = st->rows * st->k;
+    HIP_OK(ctx, launch_select(st->Gout, st->h_f64, 1, m, (m - 1) / 2, st->sel, st->scal, ctx->stream));
+    HIP_OK(ctx, hipMemcpyAsync(med, st->scal, 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+    return SYMNMF_OK;
+}
+
+// Stop rule and check-time rules for the statistics of a check iteration.
+static symnmf_status check_iteration(symnmf_state* st, symnmf_stats* sv) {
+    const symnmf_params& p = st->p;
+    if (!st->have_E0) {
+        st->E0 = sv->E;
+        st->have_E0 = true;
+    }
+    bool stag_ok = false;
+    if (st->have_prev) {
+        sv->stag = (st->E_prev - sv->E) / st->E0;
+        stag_ok = sv->t >= p.warmup && sv->stag < p.tau_stag;
+    }
+    const double tg = tau_g_of(st);
+    sv->converged = (sv->E < p.tau_E && sv->kkt < tg && stag_ok) ? 1 : 0;
+    if (!sv->converged) {
+        if (p.method == SYMNMF_PIECEWISE_ADAGRAD) {
+            bool eligible = true;
+            if (st->pw_cool) {
+                double gsum = 0.0;
+                symnmf_status s = device_sum(st, st->G, &gsum);
+                if (s != SYMNMF_OK) return s;
+                if (gsum < st->pw_cool_target) eligible = false;
+            }
+            if (eligible && stag_ok && st->pw_enabled) {
+                double med = 0.0;
+                symnmf_status s = median_of_last_gradient(st, &med);
+                if (s != SYMNMF_OK) return s;
+                if (sv->kkt > p.c_r * tg && med > p.eps_med) {
+                    if (st->pw_resets > 0 && !(sv->E < st->pw_E_reset * (1.0 - 10.0 * p.tau_stag))) {
+                        st->pw_enabled = false;
+                    } else {
+                        s = piecewise_reset_impl(st, p.c, nullptr);
+                        if (s != SYMNMF_OK) return s;
+                        double gsum = 0.0;
+                        s = device_sum(st, st->G, &gsum);
+                        if (s != SYMNMF_OK) return s;
+                        st->pw_cool = true;
+                        st->pw_cool_target = 2.0 * gsum;
+                        st->pw_E_reset = sv->E;
+                        st->pw_resets += 1;
+                        sv->reset_fired = 1;
+                    }
+                }
+            }
+        }
+        if (p.method == SYMNMF_BLOCK_SVRG && st->phi < 1.0) {
+            st->stag_run = stag_ok ? st->stag_run + 1 : 0;
+            if (st->stag_run >= p.grow_checks && sv->kkt > p.c_grow * tg) {
+                st->phi = std::min(2.0 * st->phi, 1.0);
+                st->stag_run = 0;
+            }
+        }
+    }
+    st->E_prev = sv->E;
+    st->have_prev = true;
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_solve_to_tol(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st, double f_target,
+                                  double rel_tol, symnmf_stats* final_stats, void* H_out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!S || !st || st->ctx != ctx) return fail(ctx, SYMNMF_EINVAL, "solve_to_tol: bad state or context");
+    if (S->data != st->S.data) return fail(ctx, SYMNMF_EINVAL, "solve_to_tol: S does not match the state");
+    const symnmf_params& p = st->p;
+    symnmf_stats sv{};
+    bool have = false;
+    while (st->t < p.max_iter) {
+        symnmf_status s = do_step(ctx, S, st);
+        if (s != SYMNMF_OK) return s;
+        const int64_t t = st->t - 1;
+        const bool check = t % p.delta == 0;
+        const bool full = st->ring_full[t % HCAP] != 0;
+        if (!(check || (f_target > 0.0 && full))) continue;
+        s = read_stats(st, t, &sv);
+        if (s != SYMNMF_OK) return s;
+        have = true;
+        if (sv.nonfinite) {
+            st->last = sv;
+            if (final_stats) *final_stats = sv;
+            return fail(ctx, SYMNMF_ENUMERIC, "solve: non-finite gradient at t=%lld", (long long)t);
+        }
+        if (f_target > 0.0 && full && (sv.f - f_target) / f_target <= rel_tol) {
+            // H_t is the buffer the step read: now the "previous" iterate
+            if (H_out)
+                HIP_OK(ctx, hipMemcpyAsync(H_out, st->H[1 - st->cur], st->n * st->k * st->hsz, hipMemcpyDeviceToDevice,
+                                           ctx->stream));
+            HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+            st->last = sv;
+            if (final_stats) *final_stats = sv;
+            return SYMNMF_OK;
+        }
+        if (check) {
+            if (!full) return fail(ctx, SYMNMF_EINVAL, "solve: check iteration %lld was not a full step", (long long)t);
+            s = check_iteration(st, &sv);
+            if (s != SYMNMF_OK) return s;
+            if (sv.converged) {
+                if (H_out)
+                    HIP_OK(ctx, hipMemcpyAsync(H_out, st->H[1 - st->cur], st->n * st->k * st->hsz,
+                                               hipMemcpyDeviceToDevice, ctx->stream));
+                HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+                st->last = sv;
+                if (final_stats) *final_stats = sv;
+                return SYMNMF_OK;
+            }
+        }
+    }
+    if (H_out)
+        HIP_OK(ctx, hipMemcpyAsync(H_out, st->H[st->cur], st->n * st->k * st->hsz, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+    HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+    if (!have && st->t > 0) read_stats(st, st->t - 1, &sv);
+    st->last = sv;
+    if (final_stats) *final_stats = sv;
+    return SYMNMF_ENOTCONV;
+}
+
+symnmf_status symnmf_profile(symnmf_ctx* ctx, int32_t enable, double* ms_out, int64_t* launches_out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (ms_out || launches_out) {
+        HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < PK_COUNT; ++i) {
+            if (ms_out) ms_out[i] = 0.0;
+            if (launches_out) launches_out[i] = 0;
+        }
+        for (auto& e : ctx->events) {
+            float ms = 0.f;
+            HIP_OK(ctx, hipEventElapsedTime(&ms, e.second.first, e.second.second));
+            if (ms_out) ms_out[e.first] += ms;
+            if (launches_out) launches_out[e.first] += 1;
+        }
+    }
+    for (auto& e : ctx->events) {
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    ctx->events.clear();
+    ctx->profiling = enable != 0;
+    return SYMNMF_OK;
+}
+
+void symnmf_sample_blocks(uint64_t seed, int64_t t, int32_t stream, int64_t nblocks, int64_t m, int32_t* out) {
+    if (!out || nblocks < 1 || m < 1 || m > nblocks) return;
+    std::vector<int32_t> perm(nblocks);
+    std::vector<uint8_t> flags(nblocks);
+    sample_block_flags(seed, t, stream, (int)nblocks, (int)m, perm.data(), flags.data());
+    int64_t j = 0;
+    for (int64_t b = 0; b < nblocks; ++b)
+        if (flags[b]) out[j++] = (int32_t)b;
+}
+
+// Library self-check of device instructions whose behaviour the kernels rely
+// on: returns the number of FP8 codes the hardware FP8->BF16 conversion
+// decodes differently from the E4M3 definition (0 expected), or -1 on error.
+int32_t symnmf_selfcheck_fp8(symnmf_ctx* ctx) {
+    if (!ctx) return -1;
+    void* bad = nullptr;
+    if (hipMalloc(&bad, 4) != hipSuccess) return -1;
+    int32_t h = -1;
+    hipError_t e = hipMemsetAsync(bad, 0, 4, ctx->stream);
+    if (e == hipSuccess) e = launch_fp8_decode_check((int32_t*)bad, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(bad);
+    return e == hipSuccess ? h : -1;
+}
+
+}  // extern "C"

@@ -1,0 +1,470 @@
+// Fused gradient + optimiser update of one iteration, and the FP64 reductions
+// behind the objective and the stop rule.
+//
+// For every row tile of the panel the update kernel
+//   * sums the S.H partials of the tile (stream kernel output) - or, for a
+//     row the step did not sample, takes the snapshot gradient mu,
+//   * forms g = c_g (H (Gram_eff) - S H) with the k x k Gram in LDS
+//     (paper: grad f = 4 (H (H^T H) - S H), H (H^T H) formed right to left;
+//     block steps: c_g = 2 with the block Gram, appendix Block-SVRG),
+//   * applies the AdaGrad / RMSprop rule in projected or softplus form
+//     (appendix family 3; eq. logspace_grad for softplus),
+//   * writes H_{t+1} and accumulates in FP64 the per-tile partials of
+//     tr(H_t^T S H_t), ||grad_proj||^2 (eq. proj_grad) and Gram(H_{t+1}).
+// The finalize kernel reduces the tile partials in a fixed order.
+#include "common.h"
+
+namespace symnmf {
+
+template <typename T> __device__ inline T dev_sqrt(T x);
+template <> __device__ inline float dev_sqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <> __device__ inline double dev_sqrt<double>(double x) { return __builtin_sqrt(x); }
+
+// softplus(x) = max(x, 0) + log1p(exp(-|x|)); sigmoid(x) = 1 / (1 + exp(-x))
+__device__ inline float softplus_f(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+__device__ inline double softplus_f(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
+__device__ inline float sigmoid_f(float x) { return 0.5f * (1.0f + tanhf(0.5f * x)); }
+__device__ inline double sigmoid_f(double x) { return 0.5 * (1.0 + tanh(0.5 * x)); }
+
+__device__ inline double block_sum(double v, double* sh) {
+    const int t = threadIdx.x;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    __syncthreads();
+    if ((t & 63) == 0) sh[t >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (t == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    __syncthreads();
+    return s;   // valid in thread 0
+}
+
+__device__ inline int64_t upd_unit_off(const PlanView& p, int32_t a) {
+    return p.full ? (int64_t)a * p.n_chunks : (int64_t)p.unit_offset[a];
+}
+
+template <typename HT, int KB>
+__global__ __launch_bounds__(256) void update_kernel(UpdateArgs a, PlanView p) {
+    __shared__ HT Hs[TR * KB];
+    __shared__ HT Hns[TR * KB];
+    __shared__ HT Gs[KB * KB];
+    __shared__ double red[8];
+    const int t = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int k = (int)a.k;
+    const int32_t act = p.full ? (int32_t)tile : p.tile_active[tile];
+    const int cls = (act >= 0 && !p.full) ? p.active_class[act] : 0;
+    const HT* gram = (const HT*)a.gram_eff + (int64_t)cls * k * k;
+    for (int e = t; e < k * k; e += 256) Gs[(e / k) * KB + e % k] = gram[e];
+    const int64_t g0 = a.row0 + tile * TR;            // global row of tile row 0
+    const HT* Ht = (const HT*)a.H;
+    for (int f = t; f < TR * k; f += 256) Hs[(f / k) * KB + f % k] = Ht[g0 * k + f];
+    __syncthreads();
+
+    int64_t w_lo = 0, w_hi = -1, U = 0;
+    if (act >= 0) {
+        int64_t na;
+        if (p.full) { na = p.n_tiles; U = (int64_t)p.n_tiles * p.n_chunks; }
+        else { na = p.hdr[0]; U = (int64_t)(uint32_t)p.hdr[1] | ((int64_t)p.hdr[2] << 32); }
+        (void)na;
+        const int64_t Pe = U < p.P ? U : p.P;
+        w_lo = wg_owner(upd_unit_off(p, act), U, Pe);
+        w_hi = wg_owner(upd_unit_off(p, act + 1) - 1, U, Pe);
+    }
+    const HT* part = (const HT*)a.part;
+    HT* G = (HT*)a.G;
+    HT* M = (HT*)a.M;
+    HT* Th = (HT*)a.Theta;
+    HT* Mu = (HT*)a.Mu;
+    HT* Go = (HT*)a.Gout;
+    HT* Hn = (HT*)a.Hn;
+    const HT eta = (HT)a.eta, eps = (HT)a.eps, alpha = (HT)a.alpha, mom = (HT)a.mu, cg = (HT)a.cgrad;
+    double tr = 0.0, kkt = 0.0;
+    int bad = 0;
+    for (int f = t; f < TR * k; f += 256) {
+        const int r = f / k, c = f - r * k;
+        const int64_t prow = tile * TR + r;
+        HT hn = 0;
+        if (prow < a.rows) {
+            const HT h = Hs[r * KB + c];
+            const int64_t idx = prow * k + c;
+            HT g;
+            if (act >= 0) {
+                HT sh = 0;
+                for (int64_t w = w_lo; w <= w_hi; ++w) sh += part[((w + act) * TR + r) * (int64_t)k + c];
+                if (a.fp8)   // codes carry S * scale off the diagonal; S_ii is kept exactly
+                    sh = sh / (HT)a.panel_scale[prow / a.panel_rows] + (HT)a.diag[prow] * h;
+                HT hg = 0;
+                for (int b = 0; b < k; ++b) hg += Hs[r * KB + b] * Gs[b * KB + c];
+                g = cg * (hg - sh);
+                tr += (double)h * (double)sh;
+            } else {
+                g = Mu[idx];
+            }
+            const HT pg = a.softplus ? g : (h > (HT)0 ? g : (g < (HT)0 ? g : (HT)0));
+            kkt += (double)pg * (double)pg;
+            if (!(g == g) || g - g != (HT)0) ++bad;
+            if (a.store_mu) Mu[idx] = g;
+            if (Go) Go[idx] = g;
+            if (a.softplus) {
+                HT th = Th[idx];
+                const HT gt = g * sigmoid_f(th);
+                if (a.method == SYMNMF_RMSPROP) {
+                    const HT v = alpha * G[idx] + ((HT)1 - alpha) * gt * gt;
+                    const HT m = mom * M[idx] + eta * gt / (dev_sqrt(v) + eps);
+                    G[idx] = v;
+                    M[idx] = m;
+                    th -= m;
+                } else {
+                    const HT acc = G[idx] + gt * gt;
+                    G[idx] = acc;
+                    th -= eta * gt / (dev_sqrt(acc) + eps);
+                }
+                Th[idx] = th;
+                hn = softplus_f(th);
+            } else if (a.method == SYMNMF_RMSPROP) {
+                const HT v = alpha * G[idx] + ((HT)1 - alpha) * g * g;
+                const HT m = mom * M[idx] + eta * g / (dev_sqrt(v) + eps);
+                G[idx] = v;
+                M[idx] = m;
+                hn = h - m;
+                hn = hn > (HT)0 ? hn : (HT)0;
+            } else {
+                const HT acc = G[idx] + g * g;
+                G[idx] = acc;
+                hn = h - eta * g / (dev_sqrt(acc) + eps);
+                hn = hn > (HT)0 ? hn : (HT)0;
+            }
+            Hn[(g0 + r) * k + c] = hn;
+        }
+        Hns[r * KB + c] = hn;
+    }
+    __syncthreads();
+    double* tg = a.tile_gram + tile * (int64_t)k * k;
+    for (int e = t; e < k * k; e += 256) {
+        const int ia = e / k, ib = e - ia * k;
+        double s = 0.0;
+        for (int r = 0; r < TR; ++r) s += (double)Hns[r * KB + ia] * (double)Hns[r * KB + ib];
+        tg[e] = s;
+    }
+    const double str = block_sum(tr, red);
+    const double skk = block_sum(kkt, red);
+    const double sbad = block_sum((double)bad, red);
+    if (t == 0) {
+        a.tile_tr[tile] = str;
+        a.tile_kkt[tile] = skk;
+        a.tile_bad[tile] = (int32_t)sbad;
+    }
+}
+
+hipError_t launch_update(const UpdateArgs& a, int h_f64, const PlanView& p, hipStream_t stream) {
+    const int64_t tiles = a.rows_pad / TR;
+    dim3 grid(tiles), block(256);
+    if (h_f64) {
+        if (a.k <= 8) hipLaunchKernelGGL((update_kernel<double, 8>), grid, block, 0, stream, a, p);
+        else if (a.k <= 16) hipLaunchKernelGGL((update_kernel<double, 16>), grid, block, 0, stream, a, p);
+        else if (a.k <= 32) hipLaunchKernelGGL((update_kernel<double, 32>), grid, block, 0, stream, a, p);
+        else return hipErrorInvalidValue;
+    } else {
+        if (a.k <= 8) hipLaunchKernelGGL((update_kernel<float, 8>), grid, block, 0, stream, a, p);
+        else if (a.k <= 16) hipLaunchKernelGGL((update_kernel<float, 16>), grid, block, 0, stream, a, p);
+        else if (a.k <= 32) hipLaunchKernelGGL((update_kernel<float, 32>), grid, block, 0, stream, a, p);
+        else hipLaunchKernelGGL((update_kernel<float, 64>), grid, block, 0, stream, a, p);
+    }
+    return hipGetLastError();
+}
+
+// Per-tile FP64 Gram partials of H rows [row0 + tile*TR, +TR) (rows >= row0+rows are zero).
+template <typename HT>
+__global__ __launch_bounds__(256) void tile_gram_kernel(const HT* __restrict__ H, int64_t row0, int64_t rows,
+                                                        int k, double* __restrict__ out) {
+    const int64_t tile = blockIdx.x;
+    const int t = threadIdx.x;
+    double* dst = out + tile * (int64_t)k * k;
+    for (int e = t; e < k * k; e += 256) {
+        const int ia = e / k, ib = e - ia * k;
+        double s = 0.0;
+        for (int r = 0; r < TR; ++r) {
+            const int64_t prow = tile * TR + r;
+            if (prow < rows) s += (double)H[(row0 + prow) * k + ia] * (double)H[(row0 + prow) * k + ib];
+        }
+        dst[e] = s;
+    }
+}
+
+hipError_t launch_tile_gram(const void* H, int h_f64, int64_t row0, int64_t rows, int64_t tiles, int64_t k,
+                            double* tile_gram, hipStream_t stream) {
+    if (h_f64)
+        hipLaunchKernelGGL(tile_gram_kernel<double>, dim3(tiles), dim3(256), 0, stream, (const double*)H, row0,
+                           rows, (int)k, tile_gram);
+    else
+        hipLaunchKernelGGL(tile_gram_kernel<float>, dim3(tiles), dim3(256), 0, stream, (const float*)H, row0,
+                           rows, (int)k, tile_gram);
+    return hipGetLastError();
+}
+
+// FP64 Gram of the rows of [0, n) outside [skip_lo, skip_hi): one work-group per
+// entry, fixed order.  (For a row panel: the rows that stay fixed.)
+template <typename HT>
+__global__ __launch_bounds__(256) void gram_rows_kernel(const HT* __restrict__ H, int64_t n, int64_t skip_lo,
+                                                        int64_t skip_hi, int k, double* __restrict__ out) {
+    __shared__ double red[8];
+    const int e = blockIdx.x;
+    const int ia = e / k, ib = e - ia * k;
+    double s = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += 256)
+        if (r < skip_lo || r >= skip_hi) s += (double)H[r * k + ia] * (double)H[r * k + ib];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[e] = s;
+}
+
+hipError_t launch_gram_rows(const void* H, int h_f64, int64_t n, int64_t skip_lo, int64_t skip_hi, int64_t k,
+                            double* out, hipStream_t stream) {
+    if (h_f64)
+        hipLaunchKernelGGL(gram_rows_kernel<double>, dim3(k * k), dim3(256), 0, stream, (const double*)H, n, skip_lo,
+                           skip_hi, (int)k, out);
+    else
+        hipLaunchKernelGGL(gram_rows_kernel<float>, dim3(k * k), dim3(256), 0, stream, (const float*)H, n, skip_lo,
+                           skip_hi, (int)k, out);
+    return hipGetLastError();
+}
+
+template <typename HT>
+__global__ __launch_bounds__(256) void finalize_kernel(int64_t tiles, int k, const double* __restrict__ tile_gram,
+                                                       const double* __restrict__ tile_tr,
+                                                       const double* __restrict__ tile_kkt,
+                                                       const int32_t* __restrict__ tile_bad,
+                                                       const double* __restrict__ gram_fixed,
+                                                       const double* __restrict__ gram_cur,
+                                                       double* __restrict__ gram_next, HT* __restrict__ gram_eff,
+                                                       double* __restrict__ stats) {
+    __shared__ double red[8];
+    const int kk = k * k;
+    const int ngram = (kk + 255) / 256;
+    const int t = threadIdx.x;
+    if ((int)blockIdx.x < ngram) {
+        const int e = blockIdx.x * 256 + t;
+        if (e < kk) {
+            double s = gram_fixed ? gram_fixed[e] : 0.0;
+            for (int64_t i = 0; i < tiles; ++i) s += tile_gram[i * kk + e];
+            gram_next[e] = s;
+            gram_eff[e] = (HT)s;
+            gram_eff[kk + e] = (HT)s;
+            gram_eff[2 * kk + e] = (HT)s;
+        }
+        return;
+    }
+    double tr = 0.0, kkt = 0.0, bad = 0.0, gn = 0.0;
+    for (int64_t i = t; i < tiles; i += 256) {
+        tr += tile_tr[i];
+        kkt += tile_kkt[i];
+        bad += (double)tile_bad[i];
+    }
+    if (gram_cur)
+        for (int e = t; e < kk; e += 256) gn += gram_cur[e] * gram_cur[e];
+    tr = block_sum(tr, red);
+    kkt = block_sum(kkt, red);
+    bad = block_sum(bad, red);
+    gn = block_sum(gn, red);
+    if (t == 0) {
+        stats[0] = tr;
+        stats[1] = kkt;
+        stats[2] = bad;
+        stats[3] = gn;
+    }
+}
+
+hipError_t launch_finalize(int64_t tiles, int64_t k, const double* tile_gram, const double* tile_tr,
+                           const double* tile_kkt, const int32_t* tile_bad, const double* gram_fixed,
+                           const double* gram_cur64, double* gram_next64, void* gram_eff, int h_f64,
+                           double* stats, hipStream_t stream) {
+    const int ngram = (int)((k * k + 255) / 256);
+    dim3 grid(ngram + 1), block(256);
+    if (h_f64)
+        hipLaunchKernelGGL(finalize_kernel<double>, grid, block, 0, stream, tiles, (int)k, tile_gram, tile_tr,
+                           tile_kkt, tile_bad, gram_fixed, gram_cur64, gram_next64, (double*)gram_eff, stats);
+    else
+        hipLaunchKernelGGL(finalize_kernel<float>, grid, block, 0, stream, tiles, (int)k, tile_gram, tile_tr,
+                           tile_kkt, tile_bad, gram_fixed, gram_cur64, gram_next64, (float*)gram_eff, stats);
+    return hipGetLastError();
+}
+
+// Block step: Gram_J, Gram_I and their sum from the tile partials of H_t.
+template <typename HT>
+__global__ __launch_bounds__(256) void gram_select_kernel(int k, const double* __restrict__ tile_gram,
+                                                          const int32_t* __restrict__ tI,
+                                                          const int32_t* __restrict__ tJ,
+                                                          const int32_t* __restrict__ counts,
+                                                          HT* __restrict__ out) {
+    const int kk = k * k;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kk) return;
+    double gi = 0.0, gj = 0.0;
+    for (int i = 0; i < counts[0]; ++i) gi += tile_gram[(int64_t)tI[i] * kk + e];
+    for (int i = 0; i < counts[1]; ++i) gj += tile_gram[(int64_t)tJ[i] * kk + e];
+    out[e] = (HT)gj;
+    out[kk + e] = (HT)gi;
+    out[2 * kk + e] = (HT)(gi + gj);
+}
+
+hipError_t launch_gram_select(int64_t k, const double* tile_gram, const int32_t* tiles_I, const int32_t* tiles_J,
+                              const int32_t* counts, void* gram_eff, int h_f64, hipStream_t stream) {
+    dim3 grid((k * k + 255) / 256), block(256);
+    if (h_f64)
+        hipLaunchKernelGGL(gram_select_kernel<double>, grid, block, 0, stream, (int)k, tile_gram, tiles_I, tiles_J,
+                           counts, (double*)gram_eff);
+    else
+        hipLaunchKernelGGL(gram_select_kernel<float>, grid, block, 0, stream, (int)k, tile_gram, tiles_I, tiles_J,
+                           counts, (float*)gram_eff);
+    return hipGetLastError();
+}
+
+// H0_ij = u_ij * scale, u_ij the 24-bit uniform of counter i*k + j.
+__global__ void init_h_kernel(float* __restrict__ H, int64_t count, uint64_t seed, float scale) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        H[i] = (float)uniform24(seed, (uint64_t)i) * scale;
+}
+
+hipError_t launch_init_H(float* H, int64_t n, int64_t k, uint64_t seed, float scale, hipStream_t stream) {
+    const int64_t count = n * k;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(init_h_kernel, dim3(blocks), dim3(256), 0, stream, H, count, seed, scale);
+    return hipGetLastError();
+}
+
+template <typename A, typename B>
+__global__ void copy_kernel(const A* __restrict__ s, B* __restrict__ d, int64_t m) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = (B)s[i];
+}
+
+hipError_t launch_copy_h(const void* src, int src_f64, void* dst, int dst_f64, int64_t count, hipStream_t stream) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) return hipSuccess;
+    if (src_f64 && dst_f64)
+        hipLaunchKernelGGL((copy_kernel<double, double>), dim3(blocks), dim3(256), 0, stream, (const double*)src, (double*)dst, count);
+    else if (src_f64)
+        hipLaunchKernelGGL((copy_kernel<double, float>), dim3(blocks), dim3(256), 0, stream, (const double*)src, (float*)dst, count);
+    else if (dst_f64)
+        hipLaunchKernelGGL((copy_kernel<float, double>), dim3(blocks), dim3(256), 0, stream, (const float*)src, (double*)dst, count);
+    else
+        hipLaunchKernelGGL((copy_kernel<float, float>), dim3(blocks), dim3(256), 0, stream, (const float*)src, (float*)dst, count);
+    return hipGetLastError();
+}
+
+// Theta0 = softplus^-1(max(H0, 1e-12)); H0 <- softplus(Theta0).
+template <typename HT>
+__global__ void softplus_init_kernel(HT* __restrict__ H, HT* __restrict__ Th, int64_t m) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        double h = (double)H[i];
+        h = h > 1e-12 ? h : 1e-12;
+        const double th = h > 20.0 ? h + log(-expm1(-h)) : log(expm1(h));
+        Th[i] = (HT)th;
+        H[i] = softplus_f((HT)th);
+    }
+}
+
+hipError_t launch_softplus_init(void* H, void* Theta, int h_f64, int64_t count, hipStream_t stream) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) return hipSuccess;
+    if (h_f64)
+        hipLaunchKernelGGL(softplus_init_kernel<double>, dim3(blocks), dim3(256), 0, stream, (double*)H, (double*)Theta, count);
+    else
+        hipLaunchKernelGGL(softplus_init_kernel<float>, dim3(blocks), dim3(256), 0, stream, (float*)H, (float*)Theta, count);
+    return hipGetLastError();
+}
+
+// FP64 sum of m values (single work-group, fixed order).
+template <typename T>
+__global__ __launch_bounds__(1024) void sum_kernel(const T* __restrict__ x, int64_t m, double* out) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += 1024) s += (double)x[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int i = 0; i < 16; ++i) r += red[i];
+        *out = r;
+    }
+}
+
+hipError_t launch_sum(const void* x, int x_f64, int64_t m, double* out, hipStream_t stream) {
+    if (x_f64) hipLaunchKernelGGL(sum_kernel<double>, dim3(1), dim3(1024), 0, stream, (const double*)x, m, out);
+    else hipLaunchKernelGGL(sum_kernel<float>, dim3(1), dim3(1024), 0, stream, (const float*)x, m, out);
+    return hipGetLastError();
+}
+
+// Piecewise reset: G_i <- max(c g_i^2, c median(g^2)).
+template <typename HT>
+__global__ void piecewise_kernel(HT* __restrict__ G, const HT* __restrict__ g, int64_t m, double c,
+                                 const double* __restrict__ med) {
+    const HT floor_v = (HT)(c * (double)med[0]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const HT v = (HT)c * g[i] * g[i];
+        G[i] = v > floor_v ? v : floor_v;
+    }
+}
+
+// Objective pass (FP64 H, FP64 S.H partials of a full plan): per tile
+// tr partial sum_r h_r . (S H)_r and the FP64 Gram of the tile's H rows.
+__global__ __launch_bounds__(256) void objective_tiles_kernel(UpdateArgs a, PlanView p) {
+    __shared__ double red[8];
+    const int t = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int k = (int)a.k;
+    const int64_t g0 = a.row0 + tile * TR;
+    const double* H = (const double*)a.H;
+    const double* part = (const double*)a.part;
+    const int64_t U = (int64_t)p.n_tiles * p.n_chunks;
+    const int64_t Pe = U < p.P ? U : p.P;
+    const int64_t w_lo = wg_owner(tile * p.n_chunks, U, Pe);
+    const int64_t w_hi = wg_owner((tile + 1) * p.n_chunks - 1, U, Pe);
+    double tr = 0.0;
+    for (int f = t; f < TR * k; f += 256) {
+        const int r = f / k, c = f - r * k;
+        const int64_t prow = tile * TR + r;
+        if (prow >= a.rows) continue;
+        double sh = 0.0;
+        for (int64_t w = w_lo; w <= w_hi; ++w) sh += part[((w + tile) * TR + r) * (int64_t)k + c];
+        const double h = H[(g0 + r) * k + c];
+        if (a.fp8) sh = sh / (double)a.panel_scale[prow / a.panel_rows] + (double)a.diag[prow] * h;
+        tr += h * sh;
+    }
+    double* tg = a.tile_gram + tile * (int64_t)k * k;
+    for (int e = t; e < k * k; e += 256) {
+        const int ia = e / k, ib = e - ia * k;
+        double s = 0.0;
+        for (int r = 0; r < TR; ++r)
+            if (tile * TR + r < a.rows) s += H[(g0 + r) * k + ia] * H[(g0 + r) * k + ib];
+        tg[e] = s;
+    }
+    const double str = block_sum(tr, red);
+    if (t == 0) {
+        a.tile_tr[tile] = str;
+        a.tile_kkt[tile] = 0.0;
+        a.tile_bad[tile] = 0;
+    }
+}
+
+hipError_t launch_objective_tiles(const UpdateArgs& a, const PlanView& p, hipStream_t stream) {
+    hipLaunchKernelGGL(objective_tiles_kernel, dim3(a.rows_pad / TR), dim3(256), 0, stream, a, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_piecewise_apply(void* G, const void* g, int h_f64, int64_t m, double c, const double* med,
+                                  hipStream_t stream) {
+    int64_t blocks = (m + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (h_f64)
+        hipLaunchKernelGGL(piecewise_kernel<double>, dim3(blocks), dim3(256), 0, stream, (double*)G, (const double*)g, m, c, med);
+    else
+        hipLaunchKernelGGL(piecewise_kernel<float>, dim3(blocks), dim3(256), 0, stream, (float*)G, (const float*)g, m, c, med);
+    return hipGetLastError();
+}
+
+}  // namespace symnmf

@@ -16,3 +16,8 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def golden_dir():
     return os.path.join(ROOT, "tests", "golden")
+
+
+def pytest_runtest_logstart(nodeid, location):
+    # name the case before it runs, so a run that dies mid-test still says which
+    print(f"\n[start] {nodeid}", flush=True)
