@@ -21,9 +21,15 @@
  *   symnmf_last_error() describes it.  Invalid arguments are rejected before
  *   any kernel is launched (SYMNMF_EINVAL); a non-finite value detected in a
  *   reduction is SYMNMF_ENUMERIC.
- * - S storage (symnmf_S): rows_pad = rows rounded up to 256, leading
- *   dimension ld = n rounded up to 256 elements; padding is zero.  FP8 S keeps
- *   per-row-panel scales after the matrix in the same buffer.
+ * - S storage (symnmf_S): rows_pad = rows rounded up to 256, ld = n rounded up
+ *   to 256; padding is zero.  FP64 S is row-major with leading dimension ld.
+ *   FP32 / BF16 / FP8 S are stored in 256 x 256 tiles, tile (R, C) at element
+ *   offset (R * ld/256 + C) * 65536; inside a tile the elements follow the
+ *   order the S.H stream reads them: [wave w 0..3][sub-step s][row group g
+ *   0..3][lane l 0..63][E], E = 16 bytes / element size, lane l holding row
+ *   64 w + 16 g + l%16 and columns 4E s + E (l/16) + e.  FP8 S also keeps the
+ *   per-row-panel scales and the FP32 diagonal after the matrix in the same
+ *   buffer.
  * - H buffers handed to the library are n x k, contiguous k.
  * - A context is not thread safe; use one per host thread.
  */
@@ -157,6 +163,10 @@ const char* symnmf_last_error(const symnmf_ctx* ctx);
 
 /* Bytes of the buffer a stored S (rows x n, dtype) needs, scales included. */
 int64_t symnmf_S_bytes(int64_t rows, int64_t n, int32_t dtype, int64_t fp8_panel_rows);
+
+/* Element offset (in elements of dtype) of panel row r, column c inside the
+ * data of a stored S with leading dimension ld (host only; -1 if out of range). */
+int64_t symnmf_S_offset(int64_t r, int64_t c, int64_t rows_pad, int64_t ld, int32_t dtype);
 
 /* Build S (or rows [row0, row0+rows) of S) from the returns panel X.
  * X: device, T x n float32 row-major (samples x instruments), read only.

@@ -71,6 +71,7 @@ SIGNATURES = {
     "symnmf_destroy": (None, [c_vp]),
     "symnmf_last_error": (ctypes.c_char_p, [c_vp]),
     "symnmf_S_bytes": (c_i64, [c_i64, c_i64, c_i32, c_i64]),
+    "symnmf_S_offset": (c_i64, [c_i64, c_i64, c_i64, c_i64, c_i32]),
     "symnmf_build_S": (c_i32, [c_vp, c_vp, ctypes.POINTER(symnmf_sbuild_params), c_vp, c_i64,
                                ctypes.POINTER(symnmf_S)]),
     "symnmf_S_load": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i64, c_i64, c_i32, c_i64, c_vp, c_i64,
@@ -175,6 +176,10 @@ def symnmf_last_error(ctx):
 
 def symnmf_S_bytes(rows, n, dtype, fp8_panel_rows=256):
     return lib().symnmf_S_bytes(rows, n, dtype, fp8_panel_rows)
+
+
+def symnmf_S_offset(r, c, rows_pad, ld, dtype):
+    return lib().symnmf_S_offset(r, c, rows_pad, ld, dtype)
 
 
 def _alloc_bytes(nbytes, device):

@@ -81,8 +81,11 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ sr
     }
 }
 
+// Unsigned key ordered like the float value; -0.0 and +0.0 get the same key
+// (they are equal values and tie like any other equal pair).
 __device__ inline uint32_t sortable_key(float v) {
-    const uint32_t u = __builtin_bit_cast(uint32_t, v);
+    uint32_t u = __builtin_bit_cast(uint32_t, v);
+    if ((u & 0x7fffffffu) == 0) u = 0;
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
@@ -302,7 +305,8 @@ __global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ Z, 
                     if (valid && !diag) atomicMax(&rowmax[li], __builtin_bit_cast(uint32_t, val));
                     continue;
                 }
-                const int64_t off = i * o.ld + j;
+                const int E = o.dtype == SYMNMF_S_FP32 ? 4 : (o.dtype == SYMNMF_S_BF16 ? 8 : 16);
+                const int64_t off = tiled_offset(i, j, o.ld / KC, E);
                 double stored;
                 if (o.dtype == SYMNMF_S_FP32) {
                     ((float*)o.data)[off] = val;
@@ -478,7 +482,8 @@ __global__ __launch_bounds__(256) void store_dense_kernel(const T* __restrict__ 
             }
             continue;
         }
-        const int64_t off = i * o.ld + j;
+        const int E = o.dtype == SYMNMF_S_FP32 ? 4 : (o.dtype == SYMNMF_S_BF16 ? 8 : 16);
+        const int64_t off = o.dtype == SYMNMF_S_FP64 ? i * o.ld + j : tiled_offset(i, j, o.ld / KC, E);
         double stored;
         if (o.dtype == SYMNMF_S_FP64) { ((double*)o.data)[off] = v; stored = v; }
         else if (o.dtype == SYMNMF_S_FP32) { ((float*)o.data)[off] = (float)v; stored = (float)v; }

@@ -20,6 +20,34 @@ constexpr int64_t PAD = 256;
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// ---------------------------------------------------------------------------
+// Tiled storage of S (FP32, BF16, FP8).  S is cut into 256 x 256 tiles,
+// stored tile after tile in (row tile, column chunk) order.  Inside a tile the
+// elements appear in exactly the order the MFMA stream kernel consumes them:
+// [wave wv 0..3][sub-step s][row group rg 0..3][lane l 0..63][E elements],
+// where one lane holds E consecutive columns (16 bytes: E = 4 FP32, 8 BF16,
+// 16 FP8) of row 64 wv + 16 rg + (l % 16), starting at column
+// s (4E) + (l / 16) E.  Each wave instruction therefore reads 1 KB of
+// contiguous memory and each wave streams 64 (FP32) / 32 / 16 KB sequentially
+// per tile.  FP64 storage (parity runs) is plain row-major with leading
+// dimension ld.
+// ---------------------------------------------------------------------------
+constexpr int64_t TILE_ELEMS = (int64_t)TR * KC;
+
+__host__ __device__ inline int64_t tiled_offset(int64_t r, int64_t c, int64_t n_chunks, int E) {
+    const int64_t R = r >> 8, C = c >> 8;
+    const int rr = (int)(r & 255), cc = (int)(c & 255);
+    const int wv = rr >> 6, rg = (rr >> 4) & 3, lr = rr & 15;
+    const int W = 4 * E;
+    const int NS = 256 / W;
+    const int s = cc / W, lg = (cc % W) / E, e = cc % E;
+    const int64_t in_tile = (((int64_t)(wv * NS + s) * 4 + rg) * 64 + (lg * 16 + lr)) * E + e;
+    return (R * n_chunks + C) * TILE_ELEMS + in_tile;
+}
+inline int elems_per_16B(int32_t dtype) {
+    return dtype == SYMNMF_S_FP32 ? 4 : (dtype == SYMNMF_S_BF16 ? 8 : 16);
+}
+
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -166,6 +194,8 @@ __host__ __device__ inline void sample_block_flags(uint64_t seed, int64_t t, int
 hipError_t launch_stream(const void* S, int32_t stype, int64_t ld, const void* H, int h_f64, int64_t k,
                          void* part, int acc_f64, const PlanView& plan, hipStream_t stream);
 int stream_uses_mfma(int32_t stype, int h_f64, int acc_f64, int64_t k);
+// resident work-groups per CU of the stream kernel for this storage and rank
+int stream_wgs_per_cu(int32_t stype, int64_t k);
 
 // plan.hip: build the device plan of a sub-sampled step.
 struct PlanRequest {

@@ -18,7 +18,7 @@ struct symnmf_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int cus = 256;
-    int wgs_per_cu = 2;
+    int wgs_per_cu = 0;   // 0: chosen per kernel (SYMNMF_WGS_PER_CU overrides)
     std::string err;
     // optional HIP-event timing of every kernel a step launches
     bool profiling = false;
@@ -198,6 +198,12 @@ symnmf_status symnmf_create(symnmf_ctx** out, int32_t device, void* hip_stream) 
 void symnmf_destroy(symnmf_ctx* ctx) { delete ctx; }
 
 const char* symnmf_last_error(const symnmf_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int64_t symnmf_S_offset(int64_t r, int64_t c, int64_t rows_pad, int64_t ld, int32_t dtype) {
+    if (r < 0 || c < 0 || r >= rows_pad || c >= ld || elem_bytes(dtype) == 0 || rows_pad % 256 || ld % 256) return -1;
+    if (dtype == SYMNMF_S_FP64) return r * ld + c;
+    return tiled_offset(r, c, ld / KC, elems_per_16B(dtype));
+}
 
 int64_t symnmf_S_bytes(int64_t rows, int64_t n, int32_t dtype, int64_t fp8_panel_rows) {
     if (rows < 1 || n < 1 || elem_bytes(dtype) == 0) return -1;
@@ -428,7 +434,7 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
     st->chunks = S->ld / KC;
     st->h_f64 = h_f64;
     st->hsz = h_f64 ? 8 : 4;
-    st->P = ctx->cus * ctx->wgs_per_cu;
+    st->P = ctx->cus * (ctx->wgs_per_cu > 0 ? ctx->wgs_per_cu : stream_wgs_per_cu(S->dtype, k));
     st->phi = p->method == SYMNMF_BLOCK_SVRG ? p->phi0 : 1.0;
     const int64_t hbytes = std::max(st->n_pad, st->row0 + st->rows_pad) * k * st->hsz;
     const int64_t pbytes = st->rows_pad * k * st->hsz;
@@ -658,7 +664,7 @@ symnmf_status symnmf_objective(symnmf_ctx* ctx, const symnmf_S* S, const void* H
     HIP_OK(ctx, hipSetDevice(ctx->device));
     hipStream_t sm = ctx->stream;
     const int64_t tiles = S->rows_pad / TR, chunks = S->ld / KC;
-    const int32_t P = ctx->cus * ctx->wgs_per_cu;
+    const int32_t P = ctx->cus * (ctx->wgs_per_cu > 0 ? ctx->wgs_per_cu : 2);
     const int64_t hrows = std::max(round_up(S->n, PAD), S->row0 + S->rows_pad);
     void *Hd = nullptr, *part = nullptr, *tg = nullptr, *ttr = nullptr, *tk = nullptr, *tb = nullptr, *g = nullptr,
          *gi = nullptr, *sc = nullptr;

@@ -2,19 +2,22 @@
 // (paper section "Computational Methodology": S x H dominates each step).
 //
 // Work split: see PlanView in common.h.  Each persistent work-group walks its
-// unit range; per unit it stages the H rows of one 256-column chunk in LDS
-// (permuted into the MFMA B-operand order, scaled by the chunk weight) and
-// streams a 256-row x 256-column tile of S from HBM straight into MFMA
-// A-operand registers.  Each wave owns 64 rows (4 MFMA row groups) so every
-// B fragment read from LDS feeds 4 MFMAs.
+// unit range; per unit (256-row tile x 256-column chunk) it streams the tile of
+// S from HBM straight into MFMA A-operand registers - the tiled storage puts
+// every wave's 64 rows of the tile in one contiguous run - while the H rows of
+// the chunk sit in LDS in B-operand order (scaled by the chunk weight).  The
+// H chunk of the next unit is fetched into registers during the current unit
+// and written to the other LDS buffer, so waves never wait on an H load.
+// Each wave owns 64 rows (4 MFMA row groups) so every B fragment read from LDS
+// feeds 4 MFMAs.
 //
 // MFMA operand layouts used (CDNA3/CDNA4, 64-lane wave, lane l, r = l%16,
 // g = l/16):
 //   v_mfma_f32_16x16x4_f32 : A[r][g], B[g][r], D[4g+v][r] (v = 0..3)
 //   v_mfma_f32_16x16x32_bf16: A[r][8g..8g+7], B[8g..8g+7][r], D as above
 // The reduction index of one MFMA may be any permutation of the columns as
-// long as A and B agree; each kernel picks the one that lets a lane load a
-// contiguous 16-byte piece of its S row.
+// long as A and B agree; each kernel uses the one in which a lane's 16 bytes
+// of S are consecutive columns.
 #include "common.h"
 
 namespace symnmf {
@@ -48,11 +51,23 @@ __device__ inline void unit_chunk(const PlanView& p, int32_t a, int64_t j, int32
 }
 __device__ inline int32_t tile_of(const PlanView& p, int32_t a) { return p.full ? a : p.active_tile[a]; }
 
+// unit u -> (active tile, chunk, weight), a = active tile holding u or a hint below it
+__device__ inline void unit_decode(const PlanView& p, int64_t u, int32_t& a, int32_t& chunk, float& w) {
+    while (u >= unit_off(p, a + 1)) ++a;
+    unit_chunk(p, a, u - unit_off(p, a), chunk, w);
+}
+
 // ---------------------------------------------------------------------------
 // Generic kernel: any storage type, FP32 or FP64 H and accumulation, k <= KB.
 // One thread per row of the tile.  Used for FP64 parity runs, ranks that are
 // not a multiple of 16, and the FP64-accumulated objective.
 // ---------------------------------------------------------------------------
+template <typename ST>
+__device__ inline int64_t s_index(int64_t r, int64_t c, int64_t ld, int64_t n_chunks) {
+    if (sizeof(ST) == 8) return r * ld + c;
+    return tiled_offset(r, c, n_chunks, (int)(16 / sizeof(ST)));
+}
+
 template <typename ST, typename HT, typename AT, int KB>
 __global__ __launch_bounds__(256) void stream_generic(const ST* __restrict__ S, int64_t ld,
                                                       const HT* __restrict__ H, int k,
@@ -76,7 +91,7 @@ __global__ __launch_bounds__(256) void stream_generic(const ST* __restrict__ S, 
         AT acc[KB];
 #pragma unroll
         for (int c = 0; c < KB; ++c) acc[c] = 0;
-        const ST* srow = S + (tile * TR + t) * ld;
+        const int64_t row = tile * TR + t;
         for (; u < run_end; ++u) {
             int32_t chunk; float wt;
             unit_chunk(p, a, u - abase, chunk, wt);
@@ -87,9 +102,9 @@ __global__ __launch_bounds__(256) void stream_generic(const ST* __restrict__ S, 
                     Hs[kk * KB + c] = (AT)H[((int64_t)chunk * KC + sub + kk) * k + c] * (AT)wt;
                 }
                 __syncthreads();
-                const ST* sp = srow + (int64_t)chunk * KC + sub;
+                const int64_t col0 = (int64_t)chunk * KC + sub;
                 for (int kk = 0; kk < SUB; ++kk) {
-                    const AT s = (AT)load_as_f64(sp + kk);
+                    const AT s = (AT)load_as_f64(S + s_index<ST>(row, col0 + kk, ld, p.n_chunks));
 #pragma unroll
                     for (int c = 0; c < KB; ++c)
                         if (c < k) acc[c] += s * Hs[kk * KB + c];
@@ -105,84 +120,21 @@ __global__ __launch_bounds__(256) void stream_generic(const ST* __restrict__ S, 
 }
 
 // ---------------------------------------------------------------------------
-// FP32 S: v_mfma_f32_16x16x4_f32.  Lane (r, g) of wave wv holds, for row
-// group rg and sub-step s, the float4 S[row][16 s + 4 g .. +3] of row
-// 64 wv + 16 rg + r; MFMA number m of the sub-step reduces over columns
-// 16 s + 4 g + m.  H is staged as Hs[nt][s][g][c][m].
+// MFMA kernels.  The unit loop is shared; LOAD/STAGE/COMPUTE differ by type.
+//
+// FP32 S (v_mfma_f32_16x16x4_f32): sub-step s (0..15) covers 16 columns;
+//   lane (r, g) holds the float4 S[row][16 s + 4 g .. +3] of row
+//   64 wv + 16 rg + r; MFMA number m reduces over columns 16 s + 4 g + m.
+//   H staged as Hs[nt][s][g][c][m] (floats).
+// BF16 S (v_mfma_f32_16x16x32_bf16, H = hi + mid + lo in three bf16 planes):
+//   sub-step s (0..7) covers 32 columns; lane (r, g) holds S[row][32 s + 8 g
+//   .. +7]; H staged as Hb[p][nt][s][g][c][i].
+// FP8 S: sub-step s (0..3) covers 64 columns; lane (r, g) holds the 16 codes
+//   S[row][64 s + 16 g .. +15], widened to two bf16x8 halves h; half h reduces
+//   over columns 64 s + 16 g + 8 h + i; H staged as Hb[p][nt][s][h][g][c][i].
+//   Codes are unscaled (the update kernel applies the panel scale) and the
+//   diagonal is stored as 0 (added back from the FP32 diagonal).
 // ---------------------------------------------------------------------------
-template <int NT>
-__global__ __launch_bounds__(256, 2) void stream_mfma_f32(const float* __restrict__ S, int64_t ld,
-                                                          const float* __restrict__ H,
-                                                          float* __restrict__ part, PlanView p) {
-    constexpr int K = 16 * NT;
-    __shared__ __attribute__((aligned(16))) float Hs[KC * K];
-    int64_t U; int32_t na;
-    plan_bounds(p, U, na);
-    if (U == 0) return;
-    const int64_t Pe = U < p.P ? U : p.P;
-    const int64_t w = blockIdx.x;
-    if (w >= Pe) return;
-    int64_t u = wg_start(w, U, Pe);
-    const int64_t u1 = wg_start(w + 1, U, Pe);
-    int32_t a = find_active(p, u, na);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int lr = lane & 15, lg = lane >> 4;
-    while (u < u1) {
-        const int64_t abase = unit_off(p, a);
-        const int64_t run_end = min(u1, unit_off(p, a + 1));
-        const int64_t tile = tile_of(p, a);
-        floatx4 acc[4][NT];
-#pragma unroll
-        for (int rg = 0; rg < 4; ++rg)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[rg][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const float* sbase = S + (tile * TR + 64 * wv + lr) * ld + 4 * lg;
-        for (; u < run_end; ++u) {
-            int32_t chunk; float wt;
-            unit_chunk(p, a, u - abase, chunk, wt);
-            __syncthreads();
-            const float* hsrc = H + (int64_t)chunk * KC * K;
-            for (int f = threadIdx.x; f < KC * K; f += 256) {
-                const int kk = f / K, col = f % K;
-                const int nt = col >> 4, c = col & 15, s = kk >> 4, g = (kk >> 2) & 3, m = kk & 3;
-                Hs[((((nt * 16 + s) * 4 + g) * 16 + c) << 2) + m] = hsrc[f] * wt;
-            }
-            __syncthreads();
-            const float* sp = sbase + (int64_t)chunk * KC;
-#pragma unroll 4
-            for (int s = 0; s < 16; ++s) {
-                floatx4 av[4];
-#pragma unroll
-                for (int rg = 0; rg < 4; ++rg)
-                    av[rg] = __builtin_nontemporal_load((const floatx4*)(sp + (int64_t)(16 * rg) * ld + 16 * s));
-                floatx4 bv[NT];
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    bv[nt] = *(const floatx4*)&Hs[(((nt * 16 + s) * 4 + lg) * 16 + lr) << 2];
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-#pragma unroll
-                    for (int rg = 0; rg < 4; ++rg)
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt)
-                            acc[rg][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rg][m], bv[nt][m],
-                                                                               acc[rg][nt], 0, 0, 0);
-            }
-        }
-        float* dst = part + (w + a) * (int64_t)TR * K;
-#pragma unroll
-        for (int rg = 0; rg < 4; ++rg)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    dst[(64 * wv + 16 * rg + 4 * lg + v) * K + 16 * nt + lr] = acc[rg][nt][v];
-        ++a;
-    }
-}
-
-// Split x into three bfloat16 pieces hi + mid + lo (each rounded to nearest
-// even from the remainder), which carry the 24 significand bits of x.
 __device__ inline void split3_bf16(float x, uint16_t& hi, uint16_t& mid, uint16_t& lo) {
     hi = f32_to_bf16_bits(x);
     const float r1 = x - bf16_bits_to_f32(hi);
@@ -191,94 +143,160 @@ __device__ inline void split3_bf16(float x, uint16_t& hi, uint16_t& mid, uint16_
     lo = f32_to_bf16_bits(r2);
 }
 
-// ---------------------------------------------------------------------------
-// BF16 / FP8 S: v_mfma_f32_16x16x32_bf16 with H carried as three bf16 planes
-// (H = hi + mid + lo), so S_stored x H is formed to FP32 accuracy with FP32
-// accumulation.
-//  BF16: sub-step s (0..7) covers 32 columns; lane (r, g) loads the 8 values
-//        S[row][32 s + 8 g .. +7]; H staged as Hb[p][nt][s][g][c][i].
-//  FP8 : sub-step s (0..3) covers 64 columns; lane (r, g) loads the 16 codes
-//        S[row][64 s + 16 g .. +15] and converts them to two bf16x8 halves h;
-//        half h reduces over columns 64 s + 16 g + 8 h + i; H staged as
-//        Hb[p][nt][s][h][g][c][i].  Codes are unscaled (scale applied by the
-//        update kernel) and the unit diagonal is stored as 0.
-// ---------------------------------------------------------------------------
-template <int NT, bool FP8>
-__global__ __launch_bounds__(256, 2) void stream_mfma_lp(const uint8_t* __restrict__ Sbytes, int64_t ld,
-                                                         const float* __restrict__ H,
-                                                         float* __restrict__ part, PlanView p) {
+// LDS index of H element (kk = column of the chunk, col = H column) per type
+template <int KIND, int NT>
+__device__ inline int h_lds_index(int kk, int col) {
+    const int nt = col >> 4, c = col & 15;
+    if (KIND == 0) {
+        const int s = kk >> 4, g = (kk >> 2) & 3, m = kk & 3;
+        return ((((nt * 16 + s) * 4 + g) * 16 + c) << 2) + m;
+    } else if (KIND == 1) {
+        const int s = kk >> 5, g = (kk >> 3) & 3, i = kk & 7;
+        return ((((nt * 8 + s) * 4 + g) * 16 + c) << 3) + i;
+    } else {
+        const int s = kk >> 6, g = (kk >> 4) & 3, h = (kk >> 3) & 1, i = kk & 7;
+        return (((((nt * 4 + s) * 2 + h) * 4 + g) * 16 + c) << 3) + i;
+    }
+}
+
+// KIND: 0 = FP32 S, 1 = BF16 S, 2 = FP8 S.  DB: double-buffered H in LDS.
+template <int KIND, int NT, bool DB>
+__global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ Sv, const float* __restrict__ H,
+                                                      float* __restrict__ part, PlanView p) {
     constexpr int K = 16 * NT;
-    constexpr int PLANE = KC * K;               // bf16 elements per plane
-    constexpr int EB = FP8 ? 1 : 2;             // bytes per S element
-    __shared__ __attribute__((aligned(16))) uint16_t Hb[3 * PLANE];
+    constexpr int HPT = KC * K / 256;                        // H values per thread per chunk
+    // LDS words (32-bit) per H buffer: FP32 KC*K floats; low precision 3 planes of bf16
+    constexpr int BUFW = KIND == 0 ? KC * K : 3 * KC * K / 2;
+    constexpr int PLANE = KC * K;                            // bf16 elements per plane
+    __shared__ __attribute__((aligned(16))) uint32_t lds[(DB ? 2 : 1) * BUFW];
     int64_t U; int32_t na;
     plan_bounds(p, U, na);
     if (U == 0) return;
     const int64_t Pe = U < p.P ? U : p.P;
     const int64_t w = blockIdx.x;
     if (w >= Pe) return;
-    int64_t u = wg_start(w, U, Pe);
+    const int64_t u0 = wg_start(w, U, Pe);
     const int64_t u1 = wg_start(w + 1, U, Pe);
-    int32_t a = find_active(p, u, na);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
-    const int64_t ldb = ld * EB;
-    while (u < u1) {
-        const int64_t abase = unit_off(p, a);
-        const int64_t run_end = min(u1, unit_off(p, a + 1));
-        const int64_t tile = tile_of(p, a);
-        floatx4 acc[4][NT];
+    const int tid = threadIdx.x;
+
+    // stage the H chunk of a unit into LDS buffer `buf` (values prefetched in regs)
+    float hreg[HPT];
+    auto fetch_h = [&](int32_t chunk, float wt) {
+        const float* hsrc = H + (int64_t)chunk * KC * K;
 #pragma unroll
-        for (int rg = 0; rg < 4; ++rg)
+        for (int i = 0; i < HPT; ++i) hreg[i] = hsrc[tid + 256 * i] * wt;
+    };
+    auto store_h = [&](int buf) {
+        uint32_t* base = lds + (DB ? buf : 0) * BUFW;
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[rg][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const uint8_t* sbase = Sbytes + (tile * TR + 64 * wv + lr) * ldb + 16 * lg;
-        for (; u < run_end; ++u) {
-            int32_t chunk; float wt;
-            unit_chunk(p, a, u - abase, chunk, wt);
-            __syncthreads();
-            const float* hsrc = H + (int64_t)chunk * KC * K;
-            for (int f = threadIdx.x; f < KC * K; f += 256) {
-                const int kk = f / K, col = f % K;
-                const int nt = col >> 4, c = col & 15;
-                int idx;
-                if (FP8) {
-                    const int s = kk >> 6, g = (kk >> 4) & 3, h = (kk >> 3) & 1, i = kk & 7;
-                    idx = (((((nt * 4 + s) * 2 + h) * 4 + g) * 16 + c) << 3) + i;
-                } else {
-                    const int s = kk >> 5, g = (kk >> 3) & 3, i = kk & 7;
-                    idx = ((((nt * 8 + s) * 4 + g) * 16 + c) << 3) + i;
-                }
+        for (int i = 0; i < HPT; ++i) {
+            const int f = tid + 256 * i;
+            const int kk = f / K, col = f % K;
+            const int idx = h_lds_index<KIND, NT>(kk, col);
+            if (KIND == 0) {
+                ((float*)base)[idx] = hreg[i];
+            } else {
                 uint16_t hi, mid, lo;
-                split3_bf16(hsrc[f] * wt, hi, mid, lo);
-                Hb[idx] = hi;
-                Hb[PLANE + idx] = mid;
-                Hb[2 * PLANE + idx] = lo;
+                split3_bf16(hreg[i], hi, mid, lo);
+                uint16_t* hb = (uint16_t*)base;
+                hb[idx] = hi;
+                hb[PLANE + idx] = mid;
+                hb[2 * PLANE + idx] = lo;
             }
-            __syncthreads();
-            const uint8_t* sp = sbase + (int64_t)chunk * KC * EB;
-            constexpr int NS = FP8 ? 4 : 8;
-#pragma unroll 2
+        }
+    };
+
+    int32_t a = find_active(p, u0, na);
+    int32_t chunk;
+    float wt;
+    unit_decode(p, u0, a, chunk, wt);
+    fetch_h(chunk, wt);
+    store_h(0);
+    __syncthreads();
+
+    floatx4 acc[4][NT];
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[rg][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    int32_t a_next = a;
+    for (int64_t u = u0; u < u1; ++u) {
+        const int cur = DB ? (int)((u - u0) & 1) : 0;
+        const bool more = u + 1 < u1;
+        int32_t chunk_n = 0;
+        float wt_n = 1.0f;
+        if (more) {
+            unit_decode(p, u + 1, a_next, chunk_n, wt_n);
+            fetch_h(chunk_n, wt_n);                 // in flight during the compute below
+        }
+        const int64_t tile = tile_of(p, a);
+        const uint32_t* hb = lds + cur * BUFW;
+        if (KIND == 0) {
+            // 16 sub-steps; wave wv reads its 64 KB run of the tile sequentially
+            const floatx4* sp = (const floatx4*)((const float*)Sv + ((int64_t)tile * p.n_chunks + chunk) * TILE_ELEMS +
+                                                 (int64_t)wv * 16384) + lane;
+            floatx4 av[3][4];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int rg = 0; rg < 4; ++rg) av[q][rg] = __builtin_nontemporal_load(sp + (q * 4 + rg) * 64);
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                if (s + 2 < 16) {
+#pragma unroll
+                    for (int rg = 0; rg < 4; ++rg)
+                        av[(s + 2) % 3][rg] = __builtin_nontemporal_load(sp + ((s + 2) * 4 + rg) * 64);
+                }
+                floatx4 bv[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    bv[nt] = *(const floatx4*)((const float*)hb + ((((nt * 16 + s) * 4 + lg) * 16 + lr) << 2));
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[rg][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s % 3][rg][m], bv[nt][m],
+                                                                               acc[rg][nt], 0, 0, 0);
+            }
+        } else {
+            constexpr int NS = KIND == 1 ? 8 : 4;
+            constexpr int EB = KIND == 1 ? 2 : 1;                      // bytes per element
+            // wave run: NS sub-steps x 4 row groups x 1 KB
+            const u32x4* sp = (const u32x4*)((const uint8_t*)Sv +
+                                             (((int64_t)tile * p.n_chunks + chunk) * TILE_ELEMS) * EB +
+                                             (int64_t)wv * NS * 4 * 1024) + lane;
+            const uint16_t* hp = (const uint16_t*)hb;
+            u32x4 raw[2][4];
+#pragma unroll
+            for (int rg = 0; rg < 4; ++rg) raw[0][rg] = __builtin_nontemporal_load(sp + rg * 64);
+#pragma unroll
             for (int s = 0; s < NS; ++s) {
-                u32x4 raw[4];
+                if (s + 1 < NS) {
 #pragma unroll
-                for (int rg = 0; rg < 4; ++rg)
-                    raw[rg] = __builtin_nontemporal_load((const u32x4*)(sp + (int64_t)(16 * rg) * ldb + 64 * s));
+                    for (int rg = 0; rg < 4; ++rg)
+                        raw[(s + 1) & 1][rg] = __builtin_nontemporal_load(sp + ((s + 1) * 4 + rg) * 64);
+                }
 #pragma unroll
-                for (int h = 0; h < (FP8 ? 2 : 1); ++h) {
+                for (int h = 0; h < (KIND == 2 ? 2 : 1); ++h) {
                     bf16x8 av[4];
 #pragma unroll
                     for (int rg = 0; rg < 4; ++rg) {
-                        if (FP8) {
-                            const uint32_t w0 = h ? raw[rg][2] : raw[rg][0];
-                            const uint32_t w1 = h ? raw[rg][3] : raw[rg][1];
+                        const u32x4 r = raw[s & 1][rg];
+                        if (KIND == 2) {
+                            const uint32_t w0 = h ? r[2] : r[0];
+                            const uint32_t w1 = h ? r[3] : r[1];
                             bf16x2 q0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, 1.0f, false);
                             bf16x2 q1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, 1.0f, true);
                             bf16x2 q2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, 1.0f, false);
                             bf16x2 q3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, 1.0f, true);
                             av[rg] = bf16x8{q0[0], q0[1], q1[0], q1[1], q2[0], q2[1], q3[0], q3[1]};
                         } else {
-                            av[rg] = __builtin_bit_cast(bf16x8, raw[rg]);
+                            av[rg] = __builtin_bit_cast(bf16x8, r);
                         }
                     }
 #pragma unroll
@@ -287,29 +305,40 @@ __global__ __launch_bounds__(256, 2) void stream_mfma_lp(const uint8_t* __restri
 #pragma unroll
                         for (int nt = 0; nt < NT; ++nt) {
                             int idx;
-                            if (FP8) idx = (((((nt * 4 + s) * 2 + h) * 4 + lg) * 16 + lr) << 3);
+                            if (KIND == 2) idx = (((((nt * 4 + s) * 2 + h) * 4 + lg) * 16 + lr) << 3);
                             else idx = ((((nt * 8 + s) * 4 + lg) * 16 + lr) << 3);
-                            bv[nt] = *(const bf16x8*)&Hb[pl * PLANE + idx];
+                            bv[nt] = *(const bf16x8*)(hp + pl * PLANE + idx);
                         }
 #pragma unroll
                         for (int rg = 0; rg < 4; ++rg)
 #pragma unroll
                             for (int nt = 0; nt < NT; ++nt)
-                                acc[rg][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rg], bv[nt],
-                                                                                      acc[rg][nt], 0, 0, 0);
+                                acc[rg][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rg], bv[nt], acc[rg][nt],
+                                                                                      0, 0, 0);
                     }
                 }
             }
         }
-        float* dst = part + (w + a) * (int64_t)TR * K;
+        // end of this tile's run: write the partial and start the next tile
+        if (!more || a_next != a) {
+            float* dst = part + (w + a) * (int64_t)TR * K;
 #pragma unroll
-        for (int rg = 0; rg < 4; ++rg)
+            for (int rg = 0; rg < 4; ++rg)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
+                for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    dst[(64 * wv + 16 * rg + 4 * lg + v) * K + 16 * nt + lr] = acc[rg][nt][v];
-        ++a;
+                    for (int v = 0; v < 4; ++v)
+                        dst[(64 * wv + 16 * rg + 4 * lg + v) * K + 16 * nt + lr] = acc[rg][nt][v];
+                    acc[rg][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+        if (more) {
+            if (!DB) __syncthreads();                 // single buffer: everyone done reading
+            store_h(DB ? cur ^ 1 : 0);
+            __syncthreads();
+            a = a_next;
+            chunk = chunk_n;
+        }
     }
 }
 
@@ -345,30 +374,33 @@ static hipError_t launch_generic_s(const void* S, int64_t ld, const void* H, int
     return launch_generic<ST, float, float>(S, ld, H, k, part, p, stream);
 }
 
+// LDS per work-group: FP32 k=16/32 double-buffered (32/64 KB), k=64 single
+// (64 KB); BF16/FP8 keep three bf16 planes: k=16 double (48 KB), k=32 single
+// (48 KB), k=64 single (96 KB, one work-group per CU).
+template <int KIND>
+static void launch_mfma_kind(const void* S, const float* H, float* part, int64_t k, const PlanView& p,
+                             hipStream_t stream) {
+    dim3 grid(p.P), block(256);
+    if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true>), grid, block, 0, stream, S, H, part, p);
+    else if (k == 32) hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0>), grid, block, 0, stream, S, H, part, p);
+    else hipLaunchKernelGGL((stream_mfma<KIND, 4, false>), grid, block, 0, stream, S, H, part, p);
+}
+
+int stream_wgs_per_cu(int32_t stype, int64_t k) {
+    if ((stype == SYMNMF_S_BF16 || stype == SYMNMF_S_FP8) && k == 64) return 1;
+    return 2;
+}
+
 hipError_t launch_stream(const void* S, int32_t stype, int64_t ld, const void* H, int h_f64, int64_t k,
                          void* part, int acc_f64, const PlanView& p, hipStream_t stream) {
     if (k < 1 || k > KMAX) return hipErrorInvalidValue;
     if (stream_uses_mfma(stype, h_f64, acc_f64, k)) {
-        dim3 grid(p.P), block(256);
         const float* Hf = (const float*)H;
         float* pf = (float*)part;
-        if (stype == SYMNMF_S_FP32) {
-            if (k == 16) hipLaunchKernelGGL(stream_mfma_f32<1>, grid, block, 0, stream, (const float*)S, ld, Hf, pf, p);
-            else if (k == 32) hipLaunchKernelGGL(stream_mfma_f32<2>, grid, block, 0, stream, (const float*)S, ld, Hf, pf, p);
-            else hipLaunchKernelGGL(stream_mfma_f32<4>, grid, block, 0, stream, (const float*)S, ld, Hf, pf, p);
-        } else if (stype == SYMNMF_S_BF16) {
-            const uint8_t* sb = (const uint8_t*)S;
-            if (k == 16) hipLaunchKernelGGL((stream_mfma_lp<1, false>), grid, block, 0, stream, sb, ld, Hf, pf, p);
-            else if (k == 32) hipLaunchKernelGGL((stream_mfma_lp<2, false>), grid, block, 0, stream, sb, ld, Hf, pf, p);
-            else hipLaunchKernelGGL((stream_mfma_lp<4, false>), grid, block, 0, stream, sb, ld, Hf, pf, p);
-        } else if (stype == SYMNMF_S_FP8) {
-            const uint8_t* sb = (const uint8_t*)S;
-            if (k == 16) hipLaunchKernelGGL((stream_mfma_lp<1, true>), grid, block, 0, stream, sb, ld, Hf, pf, p);
-            else if (k == 32) hipLaunchKernelGGL((stream_mfma_lp<2, true>), grid, block, 0, stream, sb, ld, Hf, pf, p);
-            else hipLaunchKernelGGL((stream_mfma_lp<4, true>), grid, block, 0, stream, sb, ld, Hf, pf, p);
-        } else {
-            return hipErrorInvalidValue;
-        }
+        if (stype == SYMNMF_S_FP32) launch_mfma_kind<0>(S, Hf, pf, k, p, stream);
+        else if (stype == SYMNMF_S_BF16) launch_mfma_kind<1>(S, Hf, pf, k, p, stream);
+        else if (stype == SYMNMF_S_FP8) launch_mfma_kind<2>(S, Hf, pf, k, p, stream);
+        else return hipErrorInvalidValue;
         return hipGetLastError();
     }
     switch (stype) {

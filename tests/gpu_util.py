@@ -21,6 +21,17 @@ def dev():
     return torch.device("cuda:0")
 
 
+def untile(flat, rows_pad, ld, E):
+    """Row-major matrix from the tiled storage: 256 x 256 tiles in (row tile,
+    column chunk) order; inside a tile [wave 4][sub-step 256/(4E)][row group 4]
+    [lane 64][E], lane l holding row 64 wave + 16 group + l % 16 and columns
+    (4E) sub-step + E (l // 16) + e."""
+    R, C, NS = rows_pad // 256, ld // 256, 256 // (4 * E)
+    t = flat.view(R, C, 4, NS, 4, 4, 16, E)            # R, C, wv, s, rg, lg, lr, e
+    t = t.permute(0, 2, 4, 6, 1, 3, 5, 7)              # R, wv, rg, lr, C, s, lg, e
+    return t.reshape(rows_pad, ld)
+
+
 def stored_numpy(S):
     """float64 rows x n matrix of what the solver multiplies with (decoded)."""
     d = S.desc
@@ -29,11 +40,11 @@ def stored_numpy(S):
     if d.dtype == sym.S_FP64:
         M = buf[: rp * ld * 8].view(torch.float64).view(rp, ld)[:rows, :n].double()
     elif d.dtype == sym.S_FP32:
-        M = buf[: rp * ld * 4].view(torch.float32).view(rp, ld)[:rows, :n].double()
+        M = untile(buf[: rp * ld * 4].view(torch.float32), rp, ld, 4)[:rows, :n].double()
     elif d.dtype == sym.S_BF16:
-        M = buf[: rp * ld * 2].view(torch.bfloat16).view(rp, ld)[:rows, :n].double()
+        M = untile(buf[: rp * ld * 2].view(torch.bfloat16), rp, ld, 8)[:rows, :n].double()
     else:
-        codes = buf[: rp * ld].view(torch.float8_e4m3fn).view(rp, ld)[:rows, :n].double()
+        codes = untile(buf[: rp * ld].view(torch.float8_e4m3fn), rp, ld, 16)[:rows, :n].double()
         so = d.panel_scale - d.data
         do = d.diag - d.data
         panels = (rows + d.fp8_panel_rows - 1) // d.fp8_panel_rows

@@ -74,3 +74,19 @@ def test_block_sampler_is_bit_identical_to_the_oracle(binding):
         ours = binding.symnmf_sample_blocks(seed, t, stream, nb, m)
         ref = o.sample_blocks(seed, t, stream, nb, m).tolist()
         assert ours == ref
+
+
+def test_tiled_storage_offsets_match_the_documented_layout(binding):
+    """symnmf_S_offset against an independent decoder of the tiled format."""
+    import torch
+    from gpu_util import untile
+    rows_pad, ld = 512, 768
+    for dtype, E in [(binding.S_FP32, 4), (binding.S_BF16, 8), (binding.S_FP8, 16)]:
+        flat = torch.arange(rows_pad * ld, dtype=torch.float64)
+        M = untile(flat, rows_pad, ld, E).numpy()      # M[r, c] = offset of (r, c)
+        rng = np.random.default_rng(E)
+        for r, c in zip(rng.integers(0, rows_pad, 300), rng.integers(0, ld, 300)):
+            assert binding.symnmf_S_offset(int(r), int(c), rows_pad, ld, dtype) == int(M[r, c])
+        assert sorted(M.ravel().astype(np.int64).tolist()) == list(range(rows_pad * ld))
+    assert binding.symnmf_S_offset(3, 5, 512, 768, binding.S_FP64) == 3 * 768 + 5
+    assert binding.symnmf_S_offset(512, 0, 512, 768, binding.S_FP32) == -1
