@@ -113,7 +113,22 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only run the library's plain copy kernel over this many GiB (counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_probe > 0:
+        import torch
+        import paper_2607_24518_amd as sym
+        nbytes = int(args.copy_probe * (1 << 30)) // 16 * 16
+        src = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        ctx = sym.symnmf_create(0)
+        for _ in range(3):
+            sym.symnmf_probe_copy(ctx, src, dst, nbytes)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "dispatches": 3}), flush=True)
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU row sharding is a design "

@@ -254,9 +254,15 @@ symnmf_status symnmf_piecewise_reset(symnmf_ctx* ctx, symnmf_state* st, double c
 void symnmf_sample_blocks(uint64_t seed, int64_t t, int32_t stream, int64_t nblocks, int64_t m,
                           int32_t* out);
 
+/* Plain grid-stride copy of ``bytes`` (a multiple of 16) from src to dst
+ * (device): a kernel of known traffic, for calibrating hardware byte counters
+ * against the S.H stream.  Asynchronous. */
+symnmf_status symnmf_probe_copy(symnmf_ctx* ctx, const void* src, void* dst, int64_t bytes);
+
 /* HIP-event timing of the kernels a step launches, on the context's stream.
- * Reading (ms_out / launches_out non-NULL, 4 entries each: 0 = S.H stream,
- * 1 = fused update, 2 = finalize, 3 = plan of a sub-sampled step)
+ * Reading (ms_out / launches_out non-NULL, 5 entries each: 0 = S.H stream,
+ * 1 = fused update, 2 = finalize, 3 = plan of a sub-sampled step, 4 = H
+ * chunk images for the MFMA stream)
  * synchronises and returns the summed milliseconds and launch counts since the
  * last call; every call then clears the record and sets profiling on or off
  * (enable).  Off by default; timing adds two events per kernel. */

@@ -93,9 +93,10 @@ SIGNATURES = {
     "symnmf_sample_blocks": (None, [c_u64, c_i64, c_i32, c_i64, c_i64, ctypes.POINTER(c_i32)]),
     "symnmf_selfcheck_fp8": (c_i32, [c_vp]),
     "symnmf_profile": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
+    "symnmf_probe_copy": (c_i32, [c_vp, c_vp, c_vp, c_i64]),
 }
 
-PROFILE_KERNELS = ("stream", "update", "finalize", "plan")
+PROFILE_KERNELS = ("stream", "update", "finalize", "plan", "image")
 
 
 def lib():
@@ -316,7 +317,12 @@ def symnmf_profile(ctx, enable: bool, read: bool = True):
     if not read:
         _check(ctx, lib().symnmf_profile(ctx, int(enable), None, None))
         return None
-    ms = (c_dbl * 4)()
-    cnt = (c_i64 * 4)()
+    ms = (c_dbl * len(PROFILE_KERNELS))()
+    cnt = (c_i64 * len(PROFILE_KERNELS))()
     _check(ctx, lib().symnmf_profile(ctx, int(enable), ms, cnt))
     return {name: (ms[i], cnt[i]) for i, name in enumerate(PROFILE_KERNELS)}
+
+
+def symnmf_probe_copy(ctx, src, dst, nbytes=None):
+    nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
+    _check(ctx, lib().symnmf_probe_copy(ctx, _ptr(src), _ptr(dst), nbytes))

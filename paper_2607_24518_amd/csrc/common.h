@@ -191,8 +191,17 @@ __host__ __device__ inline void sample_block_flags(uint64_t seed, int64_t t, int
 // H: global rows, n_pad x k (h_f64: double); part: (P + n_tiles) * TR * k of
 // the accumulation type (acc_f64: double).  Returns hipErrorInvalidValue for
 // combinations without a kernel.
+// MFMA kernels (stream_uses_mfma) read H through chunk images instead of H:
+// img1 = images of H, img2 = images of 2H (block steps; may equal img1 otherwise).
 hipError_t launch_stream(const void* S, int32_t stype, int64_t ld, const void* H, int h_f64, int64_t k,
-                         void* part, int acc_f64, const PlanView& plan, hipStream_t stream);
+                         void* part, int acc_f64, const PlanView& plan, hipStream_t stream,
+                         const void* img1 = nullptr, const void* img2 = nullptr);
+// 32-bit words of the H images of all n_chunks chunks for this storage type and rank
+int64_t h_image_words(int32_t stype, int64_t k, int64_t n_chunks);
+// Write the chunk images of wt * H (H: n_chunks * 256 rows x k, FP32).
+hipError_t launch_h_image(const float* H, int32_t stype, int64_t k, int64_t n_chunks, float wt, uint32_t* img,
+                          hipStream_t stream);
+hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t stream);
 int stream_uses_mfma(int32_t stype, int h_f64, int acc_f64, int64_t k);
 // resident work-groups per CU of the stream kernel for this storage and rank
 int stream_wgs_per_cu(int32_t stype, int64_t k);

@@ -27,7 +27,7 @@ struct symnmf_ctx {
 
 namespace {
 // kernel ids of the profiling hook
-enum { PK_STREAM = 0, PK_UPDATE = 1, PK_FINALIZE = 2, PK_PLAN = 3, PK_COUNT = 4 };
+enum { PK_STREAM = 0, PK_UPDATE = 1, PK_FINALIZE = 2, PK_PLAN = 3, PK_IMAGE = 4, PK_COUNT = 5 };
 
 struct ProfScope {
     symnmf_ctx* ctx;
@@ -124,6 +124,8 @@ struct symnmf_state {
     double* ring = nullptr;
     int32_t *plan = nullptr, *tiles_I = nullptr, *tiles_J = nullptr, *counts = nullptr;
     void* sel = nullptr;
+    void* img[2] = {nullptr, nullptr};   // chunk images of H and 2H (MFMA stream)
+    bool mfma = false;
     double* scal = nullptr;          // device scalars (median, sums)
     int64_t t = 0;
     int ring_full[HCAP] = {};
@@ -455,6 +457,12 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
     if (p->softplus) ALLOC(st->Theta, pbytes);
     if (svrg) ALLOC(st->Mu, pbytes);
     ALLOC(st->Gout, pbytes);
+    st->mfma = stream_uses_mfma(S->dtype, h_f64, h_f64, k) != 0;
+    if (st->mfma) {
+        const int64_t iw = h_image_words(S->dtype, k, st->chunks);
+        ALLOC(st->img[0], iw * 4);
+        if (p->method == SYMNMF_BLOCK_SVRG) ALLOC(st->img[1], iw * 4);
+    }
     ALLOC(st->part, ((int64_t)st->P + st->tiles) * TR * k * st->hsz);
     ALLOC(st->tile_gram, st->tiles * k * k * 8);
     ALLOC(st->tile_tr, st->tiles * 8);
@@ -527,9 +535,16 @@ static symnmf_status do_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* s
     }
     const void* Hc = st->H[st->cur];
     void* Hn = st->H[1 - st->cur];
+    if (st->mfma) {
+        ProfScope pi(ctx, PK_IMAGE);
+        HIP_OK(ctx, launch_h_image((const float*)Hc, S->dtype, st->k, st->chunks, 1.0f, (uint32_t*)st->img[0], sm));
+        if (kind == 2)
+            HIP_OK(ctx, launch_h_image((const float*)Hc, S->dtype, st->k, st->chunks, 2.0f, (uint32_t*)st->img[1], sm));
+    }
     {
         ProfScope ps(ctx, PK_STREAM);
-        HIP_OK(ctx, launch_stream(S->data, S->dtype, S->ld, Hc, st->h_f64, st->k, st->part, st->h_f64, pv, sm));
+        HIP_OK(ctx, launch_stream(S->data, S->dtype, S->ld, Hc, st->h_f64, st->k, st->part, st->h_f64, pv, sm,
+                                  st->img[0], kind == 2 ? st->img[1] : st->img[0]));
     }
     UpdateArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -893,6 +908,13 @@ symnmf_status symnmf_solve_to_tol(symnmf_ctx* ctx, const symnmf_S* S, symnmf_sta
     st->last = sv;
     if (final_stats) *final_stats = sv;
     return SYMNMF_ENOTCONV;
+}
+
+symnmf_status symnmf_probe_copy(symnmf_ctx* ctx, const void* src, void* dst, int64_t bytes) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!src || !dst || bytes < 16 || bytes % 16) return fail(ctx, SYMNMF_EINVAL, "probe_copy: bad arguments");
+    HIP_OK(ctx, launch_copy_probe(src, dst, bytes, ctx->stream));
+    return SYMNMF_OK;
 }
 
 symnmf_status symnmf_profile(symnmf_ctx* ctx, int32_t enable, double* ms_out, int64_t* launches_out) {

@@ -5,11 +5,13 @@
 // unit range; per unit (256-row tile x 256-column chunk) it streams the tile of
 // S from HBM straight into MFMA A-operand registers - the tiled storage puts
 // every wave's 64 rows of the tile in one contiguous run - while the H rows of
-// the chunk sit in LDS in B-operand order (scaled by the chunk weight).  The
-// H chunk of the next unit is fetched into registers during the current unit
-// and written to the other LDS buffer, so waves never wait on an H load.
-// Each wave owns 64 rows (4 MFMA row groups) so every B fragment read from LDS
-// feeds 4 MFMAs.
+// the chunk sit in LDS in B-operand order.  Once per step a prep kernel writes
+// H as "images", one per chunk, already in that LDS order (and, for BF16/FP8
+// S, already split into bf16 planes), so staging a chunk is a plain 16-byte
+// copy; the image of the next unit is fetched during the current unit and S
+// loads run three sub-steps ahead across unit boundaries, so the S stream never
+// drains.  Each wave owns 64 rows (4 MFMA row groups) so every B fragment read
+// from LDS feeds 4 MFMAs.
 //
 // MFMA operand layouts used (CDNA3/CDNA4, 64-lane wave, lane l, r = l%16,
 // g = l/16):
@@ -120,20 +122,11 @@ __global__ __launch_bounds__(256) void stream_generic(const ST* __restrict__ S, 
 }
 
 // ---------------------------------------------------------------------------
-// MFMA kernels.  The unit loop is shared; LOAD/STAGE/COMPUTE differ by type.
-//
-// FP32 S (v_mfma_f32_16x16x4_f32): sub-step s (0..15) covers 16 columns;
-//   lane (r, g) holds the float4 S[row][16 s + 4 g .. +3] of row
-//   64 wv + 16 rg + r; MFMA number m reduces over columns 16 s + 4 g + m.
-//   H staged as Hs[nt][s][g][c][m] (floats).
-// BF16 S (v_mfma_f32_16x16x32_bf16, H = hi + mid + lo in three bf16 planes):
-//   sub-step s (0..7) covers 32 columns; lane (r, g) holds S[row][32 s + 8 g
-//   .. +7]; H staged as Hb[p][nt][s][g][c][i].
-// FP8 S: sub-step s (0..3) covers 64 columns; lane (r, g) holds the 16 codes
-//   S[row][64 s + 16 g .. +15], widened to two bf16x8 halves h; half h reduces
-//   over columns 64 s + 16 g + 8 h + i; H staged as Hb[p][nt][s][h][g][c][i].
-//   Codes are unscaled (the update kernel applies the panel scale) and the
-//   diagonal is stored as 0 (added back from the FP32 diagonal).
+// H images.  KIND 0 (FP32 S): floats in the order Hs[nt][s][g][c][m];
+// KIND 1 (BF16 S): three bf16 planes, each Hb[nt][s][g][c][i];
+// KIND 2 (FP8 S): three bf16 planes, each Hb[nt][s][h][g][c][i].
+// (nt = H column / 16, c = H column % 16; the other indices split the chunk
+// column kk as the matching kernel's sub-step reads it.)
 // ---------------------------------------------------------------------------
 __device__ inline void split3_bf16(float x, uint16_t& hi, uint16_t& mid, uint16_t& lo) {
     hi = f32_to_bf16_bits(x);
@@ -143,8 +136,7 @@ __device__ inline void split3_bf16(float x, uint16_t& hi, uint16_t& mid, uint16_
     lo = f32_to_bf16_bits(r2);
 }
 
-// LDS index of H element (kk = column of the chunk, col = H column) per type
-template <int KIND, int NT>
+template <int KIND>
 __device__ inline int h_lds_index(int kk, int col) {
     const int nt = col >> 4, c = col & 15;
     if (KIND == 0) {
@@ -159,16 +151,91 @@ __device__ inline int h_lds_index(int kk, int col) {
     }
 }
 
-// KIND: 0 = FP32 S, 1 = BF16 S, 2 = FP8 S.  DB: double-buffered H in LDS.
-template <int KIND, int NT, bool DB>
-__global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ Sv, const float* __restrict__ H,
-                                                      float* __restrict__ part, PlanView p) {
+template <int KIND, int K>
+struct ImageShape {
+    static constexpr int BUFW = KIND == 0 ? KC * K : 3 * KC * K / 2;   // 32-bit words per chunk image
+    static constexpr int NV = BUFW / 4;                                 // 16-byte vectors per image
+    static constexpr int PLANE = KC * K;                                // bf16 elements per plane
+};
+
+template <int KIND, int K>
+__global__ __launch_bounds__(256) void h_image_kernel(const float* __restrict__ H, int64_t n_chunks, float wt,
+                                                      uint32_t* __restrict__ img) {
+    using IS = ImageShape<KIND, K>;
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n_chunks * KC * K) return;
+    const int64_t chunk = e / (KC * K);
+    const int f = (int)(e - chunk * (KC * K));
+    const int kk = f / K, col = f % K;
+    const int idx = h_lds_index<KIND>(kk, col);
+    uint32_t* base = img + chunk * IS::BUFW;
+    const float v = H[e] * wt;
+    if (KIND == 0) {
+        ((float*)base)[idx] = v;
+    } else {
+        uint16_t hi, mid, lo;
+        split3_bf16(v, hi, mid, lo);
+        uint16_t* hb = (uint16_t*)base;
+        hb[idx] = hi;
+        hb[IS::PLANE + idx] = mid;
+        hb[2 * IS::PLANE + idx] = lo;
+    }
+}
+
+int64_t h_image_words(int32_t stype, int64_t k, int64_t n_chunks) {
+    const int64_t per = stype == SYMNMF_S_FP32 ? KC * k : 3 * KC * k / 2;
+    return per * n_chunks;
+}
+
+hipError_t launch_h_image(const float* H, int32_t stype, int64_t k, int64_t n_chunks, float wt, uint32_t* img,
+                          hipStream_t stream) {
+    const int64_t count = n_chunks * KC * k;
+    dim3 grid((count + 255) / 256), block(256);
+#define IMG(KIND, KK) hipLaunchKernelGGL((h_image_kernel<KIND, KK>), grid, block, 0, stream, H, n_chunks, wt, img)
+    if (stype == SYMNMF_S_FP32) {
+        if (k == 16) IMG(0, 16); else if (k == 32) IMG(0, 32); else if (k == 64) IMG(0, 64); else return hipErrorInvalidValue;
+    } else if (stype == SYMNMF_S_BF16) {
+        if (k == 16) IMG(1, 16); else if (k == 32) IMG(1, 32); else if (k == 64) IMG(1, 64); else return hipErrorInvalidValue;
+    } else if (stype == SYMNMF_S_FP8) {
+        if (k == 16) IMG(2, 16); else if (k == 32) IMG(2, 32); else if (k == 64) IMG(2, 64); else return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef IMG
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// MFMA stream kernel.
+//
+// FP32 S (v_mfma_f32_16x16x4_f32): sub-step s (0..15) covers 16 columns;
+//   lane (r, g) holds the float4 S[row][16 s + 4 g .. +3] of row
+//   64 wv + 16 rg + r; MFMA number m reduces over columns 16 s + 4 g + m.
+// BF16 S (v_mfma_f32_16x16x32_bf16, H = hi + mid + lo in three bf16 planes):
+//   sub-step s (0..7) covers 32 columns; lane (r, g) holds S[row][32 s + 8 g
+//   .. +7].
+// FP8 S: sub-step s (0..3) covers 64 columns; lane (r, g) holds the 16 codes
+//   S[row][64 s + 16 g .. +15], widened to two bf16x8 halves h; half h reduces
+//   over columns 64 s + 16 g + 8 h + i.  Codes are unscaled (the update kernel
+//   applies the panel scale) and the diagonal is stored as 0 (added back from
+//   the FP32 diagonal).
+// DB: two LDS image buffers (the next image is written while the current one
+// is read).  PF: the next image is fetched into registers at the start of a
+// unit (otherwise it is copied at the unit boundary).
+// ---------------------------------------------------------------------------
+template <int KIND, int NT, bool DB, bool PF>
+__global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ Sv, const u32x4* __restrict__ img1,
+                                                      const u32x4* __restrict__ img2, float* __restrict__ part,
+                                                      PlanView p) {
     constexpr int K = 16 * NT;
-    constexpr int HPT = KC * K / 256;                        // H values per thread per chunk
-    // LDS words (32-bit) per H buffer: FP32 KC*K floats; low precision 3 planes of bf16
-    constexpr int BUFW = KIND == 0 ? KC * K : 3 * KC * K / 2;
-    constexpr int PLANE = KC * K;                            // bf16 elements per plane
-    __shared__ __attribute__((aligned(16))) uint32_t lds[(DB ? 2 : 1) * BUFW];
+    using IS = ImageShape<KIND, K>;
+    constexpr int NV = IS::NV;
+    constexpr int CPT = NV / 256;                          // image vectors per thread
+    constexpr int NS = KIND == 0 ? 16 : (KIND == 1 ? 8 : 4);
+    constexpr int EB = KIND == 0 ? 4 : (KIND == 1 ? 2 : 1);
+    constexpr int RING = 4, D = 3;                         // S prefetch ring and distance (sub-steps)
+    static_assert(NS % RING == 0, "ring must divide the sub-steps of a unit");
+    __shared__ u32x4 lds[(DB ? 2 : 1) * NV];
     int64_t U; int32_t na;
     plan_bounds(p, U, na);
     if (U == 0) return;
@@ -181,39 +248,30 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
     const int lr = lane & 15, lg = lane >> 4;
     const int tid = threadIdx.x;
 
-    // stage the H chunk of a unit into LDS buffer `buf` (values prefetched in regs)
-    float hreg[HPT];
-    auto fetch_h = [&](int32_t chunk, float wt) {
-        const float* hsrc = H + (int64_t)chunk * KC * K;
-#pragma unroll
-        for (int i = 0; i < HPT; ++i) hreg[i] = hsrc[tid + 256 * i] * wt;
+    // this wave's contiguous run of a unit's tile, in 16-byte vectors, plus the lane
+    auto s_run = [&](int32_t aa, int32_t ch) -> const u32x4* {
+        const int64_t tile = tile_of(p, aa);
+        return (const u32x4*)((const uint8_t*)Sv + ((int64_t)tile * p.n_chunks + ch) * TILE_ELEMS * EB +
+                              (int64_t)wv * (TILE_ELEMS * EB / 4)) + lane;
     };
-    auto store_h = [&](int buf) {
-        uint32_t* base = lds + (DB ? buf : 0) * BUFW;
-#pragma unroll
-        for (int i = 0; i < HPT; ++i) {
-            const int f = tid + 256 * i;
-            const int kk = f / K, col = f % K;
-            const int idx = h_lds_index<KIND, NT>(kk, col);
-            if (KIND == 0) {
-                ((float*)base)[idx] = hreg[i];
-            } else {
-                uint16_t hi, mid, lo;
-                split3_bf16(hreg[i], hi, mid, lo);
-                uint16_t* hb = (uint16_t*)base;
-                hb[idx] = hi;
-                hb[PLANE + idx] = mid;
-                hb[2 * PLANE + idx] = lo;
-            }
-        }
+    auto image = [&](int32_t ch, float wt) -> const u32x4* {
+        return (wt > 1.5f ? img2 : img1) + (int64_t)ch * NV;
     };
 
     int32_t a = find_active(p, u0, na);
     int32_t chunk;
     float wt;
     unit_decode(p, u0, a, chunk, wt);
-    fetch_h(chunk, wt);
-    store_h(0);
+    {
+        const u32x4* src = image(chunk, wt);
+        for (int i = tid; i < NV; i += 256) lds[i] = src[i];
+    }
+    const u32x4* sp = s_run(a, chunk);
+    u32x4 ring[RING][4];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) ring[d][rg] = __builtin_nontemporal_load(sp + (d * 4 + rg) * 64);
     __syncthreads();
 
     floatx4 acc[4][NT];
@@ -222,71 +280,58 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[rg][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+    u32x4 hreg[PF ? CPT : 1];
     int32_t a_next = a;
     for (int64_t u = u0; u < u1; ++u) {
         const int cur = DB ? (int)((u - u0) & 1) : 0;
         const bool more = u + 1 < u1;
-        int32_t chunk_n = 0;
+        int32_t chunk_n = chunk;
         float wt_n = 1.0f;
+        const u32x4* sp_n = sp;
         if (more) {
             unit_decode(p, u + 1, a_next, chunk_n, wt_n);
-            fetch_h(chunk_n, wt_n);                 // in flight during the compute below
+            sp_n = s_run(a_next, chunk_n);
+            if (PF) {
+                const u32x4* src = image(chunk_n, wt_n);
+#pragma unroll
+                for (int i = 0; i < CPT; ++i) hreg[i] = src[tid + 256 * i];
+            }
         }
-        const int64_t tile = tile_of(p, a);
-        const uint32_t* hb = lds + cur * BUFW;
-        if (KIND == 0) {
-            // 16 sub-steps; wave wv reads its 64 KB run of the tile sequentially
-            const floatx4* sp = (const floatx4*)((const float*)Sv + ((int64_t)tile * p.n_chunks + chunk) * TILE_ELEMS +
-                                                 (int64_t)wv * 16384) + lane;
-            floatx4 av[3][4];
+        const u32x4* hb = lds + cur * NV;
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+        for (int s = 0; s < NS; ++s) {
+            // keep D sub-steps of S in flight, crossing into the next unit
+            const int sd = s + D;
+            if (sd < NS) {
 #pragma unroll
-                for (int rg = 0; rg < 4; ++rg) av[q][rg] = __builtin_nontemporal_load(sp + (q * 4 + rg) * 64);
+                for (int rg = 0; rg < 4; ++rg)
+                    ring[sd % RING][rg] = __builtin_nontemporal_load(sp + (sd * 4 + rg) * 64);
+            } else if (more) {
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                if (s + 2 < 16) {
-#pragma unroll
-                    for (int rg = 0; rg < 4; ++rg)
-                        av[(s + 2) % 3][rg] = __builtin_nontemporal_load(sp + ((s + 2) * 4 + rg) * 64);
-                }
+                for (int rg = 0; rg < 4; ++rg)
+                    ring[sd % RING][rg] = __builtin_nontemporal_load(sp_n + ((sd - NS) * 4 + rg) * 64);
+            }
+            if (KIND == 0) {
                 floatx4 bv[NT];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
-                    bv[nt] = *(const floatx4*)((const float*)hb + ((((nt * 16 + s) * 4 + lg) * 16 + lr) << 2));
+                    bv[nt] = __builtin_bit_cast(floatx4, hb[((nt * 16 + s) * 4 + lg) * 16 + lr]);
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
 #pragma unroll
-                    for (int rg = 0; rg < 4; ++rg)
+                    for (int rg = 0; rg < 4; ++rg) {
+                        const floatx4 av = __builtin_bit_cast(floatx4, ring[s % RING][rg]);
 #pragma unroll
                         for (int nt = 0; nt < NT; ++nt)
-                            acc[rg][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s % 3][rg][m], bv[nt][m],
-                                                                               acc[rg][nt], 0, 0, 0);
-            }
-        } else {
-            constexpr int NS = KIND == 1 ? 8 : 4;
-            constexpr int EB = KIND == 1 ? 2 : 1;                      // bytes per element
-            // wave run: NS sub-steps x 4 row groups x 1 KB
-            const u32x4* sp = (const u32x4*)((const uint8_t*)Sv +
-                                             (((int64_t)tile * p.n_chunks + chunk) * TILE_ELEMS) * EB +
-                                             (int64_t)wv * NS * 4 * 1024) + lane;
-            const uint16_t* hp = (const uint16_t*)hb;
-            u32x4 raw[2][4];
-#pragma unroll
-            for (int rg = 0; rg < 4; ++rg) raw[0][rg] = __builtin_nontemporal_load(sp + rg * 64);
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                if (s + 1 < NS) {
-#pragma unroll
-                    for (int rg = 0; rg < 4; ++rg)
-                        raw[(s + 1) & 1][rg] = __builtin_nontemporal_load(sp + ((s + 1) * 4 + rg) * 64);
-                }
+                            acc[rg][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m], bv[nt][m], acc[rg][nt], 0, 0, 0);
+                    }
+            } else {
 #pragma unroll
                 for (int h = 0; h < (KIND == 2 ? 2 : 1); ++h) {
                     bf16x8 av[4];
 #pragma unroll
                     for (int rg = 0; rg < 4; ++rg) {
-                        const u32x4 r = raw[s & 1][rg];
+                        const u32x4 r = ring[s % RING][rg];
                         if (KIND == 2) {
                             const uint32_t w0 = h ? r[2] : r[0];
                             const uint32_t w1 = h ? r[3] : r[1];
@@ -304,10 +349,9 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
                         bf16x8 bv[NT];
 #pragma unroll
                         for (int nt = 0; nt < NT; ++nt) {
-                            int idx;
-                            if (KIND == 2) idx = (((((nt * 4 + s) * 2 + h) * 4 + lg) * 16 + lr) << 3);
-                            else idx = ((((nt * 8 + s) * 4 + lg) * 16 + lr) << 3);
-                            bv[nt] = *(const bf16x8*)(hp + pl * PLANE + idx);
+                            const int v16 = KIND == 2 ? ((((nt * 4 + s) * 2 + h) * 4 + lg) * 16 + lr)
+                                                      : (((nt * 8 + s) * 4 + lg) * 16 + lr);
+                            bv[nt] = __builtin_bit_cast(bf16x8, hb[pl * (IS::PLANE / 8) + v16]);
                         }
 #pragma unroll
                         for (int rg = 0; rg < 4; ++rg)
@@ -333,11 +377,19 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
                 }
         }
         if (more) {
+            u32x4* dstb = lds + (DB ? (cur ^ 1) : 0) * NV;
             if (!DB) __syncthreads();                 // single buffer: everyone done reading
-            store_h(DB ? cur ^ 1 : 0);
+            if (PF) {
+#pragma unroll
+                for (int i = 0; i < CPT; ++i) dstb[tid + 256 * i] = hreg[i];
+            } else {
+                const u32x4* src = image(chunk_n, wt_n);
+                for (int i = tid; i < NV; i += 256) dstb[i] = src[i];
+            }
             __syncthreads();
             a = a_next;
             chunk = chunk_n;
+            sp = sp_n;
         }
     }
 }
@@ -374,16 +426,16 @@ static hipError_t launch_generic_s(const void* S, int64_t ld, const void* H, int
     return launch_generic<ST, float, float>(S, ld, H, k, part, p, stream);
 }
 
-// LDS per work-group: FP32 k=16/32 double-buffered (32/64 KB), k=64 single
-// (64 KB); BF16/FP8 keep three bf16 planes: k=16 double (48 KB), k=32 single
-// (48 KB), k=64 single (96 KB, one work-group per CU).
+// LDS per work-group (image buffers): FP32 k=16/32 double-buffered (32/64 KB),
+// k=64 single (64 KB); BF16/FP8 keep three bf16 planes: k=16 double (48 KB),
+// k=32 single (48 KB), k=64 single (96 KB, one work-group per CU).
 template <int KIND>
-static void launch_mfma_kind(const void* S, const float* H, float* part, int64_t k, const PlanView& p,
-                             hipStream_t stream) {
+static void launch_mfma_kind(const void* S, const u32x4* img1, const u32x4* img2, float* part, int64_t k,
+                             const PlanView& p, hipStream_t stream) {
     dim3 grid(p.P), block(256);
-    if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true>), grid, block, 0, stream, S, H, part, p);
-    else if (k == 32) hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0>), grid, block, 0, stream, S, H, part, p);
-    else hipLaunchKernelGGL((stream_mfma<KIND, 4, false>), grid, block, 0, stream, S, H, part, p);
+    if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true, true>), grid, block, 0, stream, S, img1, img2, part, p);
+    else if (k == 32) hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0, true>), grid, block, 0, stream, S, img1, img2, part, p);
+    else hipLaunchKernelGGL((stream_mfma<KIND, 4, false, false>), grid, block, 0, stream, S, img1, img2, part, p);
 }
 
 int stream_wgs_per_cu(int32_t stype, int64_t k) {
@@ -392,14 +444,17 @@ int stream_wgs_per_cu(int32_t stype, int64_t k) {
 }
 
 hipError_t launch_stream(const void* S, int32_t stype, int64_t ld, const void* H, int h_f64, int64_t k,
-                         void* part, int acc_f64, const PlanView& p, hipStream_t stream) {
+                         void* part, int acc_f64, const PlanView& p, hipStream_t stream, const void* img1,
+                         const void* img2) {
     if (k < 1 || k > KMAX) return hipErrorInvalidValue;
     if (stream_uses_mfma(stype, h_f64, acc_f64, k)) {
-        const float* Hf = (const float*)H;
+        if (!img1) return hipErrorInvalidValue;
+        const u32x4* i1 = (const u32x4*)img1;
+        const u32x4* i2 = (const u32x4*)(img2 ? img2 : img1);
         float* pf = (float*)part;
-        if (stype == SYMNMF_S_FP32) launch_mfma_kind<0>(S, Hf, pf, k, p, stream);
-        else if (stype == SYMNMF_S_BF16) launch_mfma_kind<1>(S, Hf, pf, k, p, stream);
-        else if (stype == SYMNMF_S_FP8) launch_mfma_kind<2>(S, Hf, pf, k, p, stream);
+        if (stype == SYMNMF_S_FP32) launch_mfma_kind<0>(S, i1, i2, pf, k, p, stream);
+        else if (stype == SYMNMF_S_BF16) launch_mfma_kind<1>(S, i1, i2, pf, k, p, stream);
+        else if (stype == SYMNMF_S_FP8) launch_mfma_kind<2>(S, i1, i2, pf, k, p, stream);
         else return hipErrorInvalidValue;
         return hipGetLastError();
     }
@@ -432,6 +487,19 @@ __global__ void fp8_decode_check(int32_t* bad) {
 
 hipError_t launch_fp8_decode_check(int32_t* bad, hipStream_t stream) {
     hipLaunchKernelGGL(fp8_decode_check, dim3(1), dim3(256), 0, stream, bad);
+    return hipGetLastError();
+}
+
+// Plain grid-stride 16-byte copy of `bytes` (a multiple of 16): a kernel of
+// known traffic for calibrating hardware byte counters.
+__global__ __launch_bounds__(256) void copy_probe_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                         int64_t n16) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = __builtin_nontemporal_load(src + i);
+}
+
+hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t stream) {
+    hipLaunchKernelGGL(copy_probe_kernel, dim3(4096), dim3(256), 0, stream, (const u32x4*)src, (u32x4*)dst, bytes / 16);
     return hipGetLastError();
 }
 
