@@ -99,6 +99,103 @@ def cpu_baseline(X_host, k, H0, eta, rows, steps):
                       f"{build_s:.1f} s not timed"}
 
 
+def time_to_tolerance(args):
+    """Time to (f_S(H_t) - f_ref) / f_ref <= tol for several variants of the
+    same instance and initial H.
+
+    f_S is the objective on the FP32-stored S (MFMA products, FP64 sums across
+    chunks) whatever S the variant iterates on; f_ref is the best objective of
+    a long FP32 AdaGrad reference run certified by the stop rule (or stopped at
+    --ttt-ref-iters).  Every variant's iterates are kept in HBM and judged
+    after its timed run; the time of iterate H_t is measured from the start of
+    its initialisation to the end of step t-1 (HIP events on the solver
+    stream).
+    """
+    import torch
+    import paper_2607_24518_amd as sym
+    import synth
+
+    dev = torch.device("cuda:0")
+    n, k = args.n, args.k
+    inst = synth.overlap_returns(args.seed, T=args.T, n=n, groups=args.groups, device=dev)
+    ctx = sym.symnmf_create(0)
+    stores = {"fp32": sym.symnmf_build_S(ctx, inst.X, dtype=sym.S_FP32)}
+    variants = [v for v in args.ttt_variants.split(",") if v]
+    for v in variants:
+        dt = v.split("-")[0]
+        if dt not in stores:
+            stores[dt] = sym.symnmf_build_S(ctx, inst.X, dtype=sym.DTYPES[dt], fp8_panel_rows=256)
+    del inst
+    S32 = stores["fp32"]
+    H0 = torch.empty(n, k, device=dev)
+    sym.symnmf_init_H(ctx, S32, k, 1, H0)
+    eta = math.sqrt(S32.desc.mean / k)
+
+    def judge(H):
+        return sym.symnmf_objective(ctx, S32, H, k)[0]
+
+    # reference
+    t0 = time.time()
+    p = sym.symnmf_params_default(eta=eta, max_iter=args.ttt_ref_iters)
+    st = sym.symnmf_state_create(ctx, S32, k, p, H0)
+    Hr = torch.empty(n, k, device=dev)
+    rs, conv = sym.symnmf_solve_to_tol(ctx, S32, st, H_out=Hr)
+    f_ref = judge(Hr)
+    del st
+    log(f"reference: t={rs.t} converged={conv} E={rs.E:.6e} kkt={rs.kkt:.3e} f_ref={f_ref:.9e} "
+        f"({time.time() - t0:.1f} s)")
+    results = {"f_ref": f_ref, "ref_iters": int(rs.t), "ref_certified": bool(conv), "tol": args.ttt_tol,
+               "variants": {}}
+    every = max(1, args.ttt_save_every)
+    nsave = args.ttt_max // every
+    store = torch.empty(nsave, n, k, device=dev)
+    for v in variants:
+        parts = v.split("-")
+        dt, softplus = parts[0], "softplus" in parts
+        S = stores[dt]
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(nsave)]
+        ev0.record()
+        H = torch.empty(n, k, device=dev)
+        sym.symnmf_init_H(ctx, S, k, 1, H)
+        p = sym.symnmf_params_default(eta=eta, softplus=int(softplus), max_iter=10 ** 9)
+        st = sym.symnmf_state_create(ctx, S, k, p, H)
+        for t in range(nsave * every):
+            sym.symnmf_step(ctx, S, st, want_stats=False)
+            if (t + 1) % every == 0:
+                j = (t + 1) // every - 1
+                sym.symnmf_state_read(ctx, st, 0, store[j])   # H_{t+1}
+                evs[j].record()
+        torch.cuda.synchronize()
+        del st
+
+        def rel(j):
+            return (judge(store[j]) - f_ref) / f_ref
+
+        # coarse scan, then bisection inside the first bracket that meets tol
+        hit = None
+        prev = -1
+        for j in list(range(31, nsave, 32)) + [nsave - 1]:
+            if rel(j) <= args.ttt_tol:
+                lo, hi = prev + 1, j
+                while lo < hi:
+                    mid = (lo + hi) // 2
+                    if rel(mid) <= args.ttt_tol:
+                        hi = mid
+                    else:
+                        lo = mid + 1
+                hit = lo
+                break
+            prev = j
+        entry = {"final_rel": rel(nsave - 1), "steps_run": nsave * every}
+        if hit is not None:
+            entry.update(iters=(hit + 1) * every, seconds=ev0.elapsed_time(evs[hit]) / 1000.0)
+        results["variants"][v] = entry
+        log(f"variant {v}: {entry}")
+    return results
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,7 +212,25 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run the library's plain copy kernel over this many GiB (counter calibration)")
+    ap.add_argument("--ttt", action="store_true", help="time-to-tolerance comparison instead of the step rate")
+    ap.add_argument("--ttt-variants", default="fp32,bf16,fp8,fp32-softplus")
+    ap.add_argument("--ttt-tol", type=float, default=1e-4)
+    ap.add_argument("--ttt-max", type=int, default=6000)
+    ap.add_argument("--ttt-save-every", type=int, default=2)
+    ap.add_argument("--ttt-ref-iters", type=int, default=8000)
     args = ap.parse_args()
+
+    if args.ttt:
+        res = time_to_tolerance(args)
+        base = res["variants"].get("fp32", {}).get("seconds")
+        for v in res["variants"].values():
+            if base and v.get("seconds"):
+                v["speedup_vs_fp32"] = round(base / v["seconds"], 3)
+        print(json.dumps({"metric": "time to relative objective tolerance", "unit": "s",
+                          "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": f"abs_corr_n{args.n}_k{args.k}_T{args.T}", "method": "AdaGrad"},
+                          **res}), flush=True)
+        return
 
     if args.copy_probe > 0:
         import torch

@@ -1,0 +1,181 @@
+"""FP64 oracle of the learned warm start (not in the paper: a per-row sketch
+of S mapped by a small MLP to an initial H row).
+
+TEST INFRASTRUCTURE ONLY - imported by tests/ and the smoke check, never by
+the library.
+
+Pieces, in the order the warm start applies them:
+1. Gaussian sketch Omega (n x w): Box-Muller (Box & Muller 1958) on pairs of
+   53-bit uniforms from SplitMix64 keyed by the seed; Y = S Omega.
+2. Canonical coordinates: the top-k eigenpairs (lambda_c, v_c) of Y^T Y give
+   whitened coordinates Z = Y V_k Lambda_k^-1/2 (each v_c signed so that
+   sum_i (Y v_c)_i^3 > 0); the successive projection algorithm (Gillis &
+   Vavasis 2014) picks k anchor rows of Z; rows are expressed in the anchor
+   basis, C = Z A^-1, and padded with zeros to the network width.
+3. MLP 64 -> 256 -> 256 -> k with exact GELU x Phi(x), softplus output.
+4. Scale: H0 = alpha A with alpha^2 = tr(A^T S A) / ||A^T A||_F^2, the
+   minimiser of ||S - alpha^2 A A^T||_F^2 over alpha.
+Training: permutation-invariant Gram loss
+   L(A, B) = ||A A^T - B B^T||_F^2 = ||A^T A||^2 - 2 ||A^T B||^2 + ||B^T B||^2
+with dL/dA = 4 (A (A^T A) - B (B^T A)), divided by ||B^T B||^2; AdamW
+(Loshchilov & Hutter 2019) updates.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erfc
+
+from .symnmf_oracle import splitmix64
+
+# --------------------------------------------------------------------------
+# 1. sketch
+# --------------------------------------------------------------------------
+def uniform53(key, counter):
+    """(top 53 bits of SplitMix64 output number counter) * 2^-53, in [0, 1)."""
+    return (splitmix64(key, counter) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
+def omega(seed: int, n: int, width: int):
+    """Omega_ij = sqrt(-2 ln(1 - u)) cos(2 pi v), u and v the uniforms of
+    counters 2e and 2e + 1, e = i * width + j."""
+    e = np.arange(n * width, dtype=np.uint64)
+    u = uniform53(np.uint64(seed), 2 * e)
+    v = uniform53(np.uint64(seed), 2 * e + np.uint64(1))
+    return (np.sqrt(-2.0 * np.log(1.0 - u)) * np.cos(2.0 * math.pi * v)).reshape(n, width)
+
+
+def sketch(S, Om):
+    return np.asarray(S, dtype=np.float64) @ Om
+
+
+# --------------------------------------------------------------------------
+# 2. canonical coordinates
+# --------------------------------------------------------------------------
+def whiten(Y, k: int):
+    """Z = Y V_k Lambda_k^-1/2 with the sign rule; returns (Z, M) with Z = Y M."""
+    C = Y.T @ Y
+    lam, V = np.linalg.eigh(C)
+    order = np.argsort(lam)[::-1][:k]
+    lam, V = lam[order], V[:, order]
+    proj = Y @ V
+    s = np.sign((proj ** 3).sum(axis=0))
+    s[s == 0] = 1.0
+    M = V * (s / np.sqrt(lam))[None, :]
+    return Y @ M, M
+
+
+def spa(Z, k: int):
+    """Successive projection algorithm: k row indices of Z.  At each step the
+    row of largest residual norm (lowest index on ties) is taken and every row
+    is projected onto the orthogonal complement of it."""
+    R = np.array(Z, dtype=np.float64)
+    idx = []
+    for _ in range(k):
+        nr = (R * R).sum(axis=1)
+        i = int(np.argmax(nr))
+        idx.append(i)
+        u = R[i] / math.sqrt(nr[i])
+        R = R - np.outer(R @ u, u)
+    return np.array(idx)
+
+
+def canonical_coordinates(Y, k: int, width: int = 64):
+    Z, M = whiten(Y, k)
+    anchors = spa(Z, k)
+    A = Z[anchors]
+    C = Z @ np.linalg.inv(A)
+    X = np.zeros((Y.shape[0], width))
+    X[:, :k] = C
+    return X, anchors
+
+
+# --------------------------------------------------------------------------
+# 3. network
+# --------------------------------------------------------------------------
+def normal_cdf(x):
+    """Phi(x) = erfc(-x / sqrt 2) / 2 (no cancellation in the lower tail)."""
+    return 0.5 * erfc(-x / math.sqrt(2.0))
+
+
+def gelu(x):
+    return x * normal_cdf(x)
+
+
+def gelu_grad(x):
+    return normal_cdf(x) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+
+
+def softplus(x):
+    return np.maximum(x, 0.0) + np.log1p(np.exp(-np.abs(x)))
+
+
+def sigmoid(x):
+    return 0.5 * (1.0 + np.tanh(0.5 * x))
+
+
+def init_params(k: int, seed: int = 0, width: int = 64, hidden: int = 256):
+    """W_l ~ N(0, 1/fan_in) (from numpy's seeded generator: an input), b_l = 0."""
+    g = np.random.default_rng(seed)
+    return {
+        "W1": g.normal(size=(hidden, width)) / math.sqrt(width), "b1": np.zeros(hidden),
+        "W2": g.normal(size=(hidden, hidden)) / math.sqrt(hidden), "b2": np.zeros(hidden),
+        "W3": g.normal(size=(k, hidden)) / math.sqrt(hidden), "b3": np.zeros(k),
+    }
+
+
+def forward(P, X):
+    z1 = X @ P["W1"].T + P["b1"]
+    a1 = gelu(z1)
+    z2 = a1 @ P["W2"].T + P["b2"]
+    a2 = gelu(z2)
+    z3 = a2 @ P["W3"].T + P["b3"]
+    A = softplus(z3)
+    return A, dict(X=X, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3)
+
+
+def gram_loss(A, B):
+    AtA, AtB, BtB = A.T @ A, A.T @ B, B.T @ B
+    norm = (BtB * BtB).sum()
+    L = ((AtA * AtA).sum() - 2.0 * (AtB * AtB).sum() + norm) / norm
+    dA = 4.0 * (A @ AtA - B @ (B.T @ A)) / norm
+    return L, dA
+
+
+def backward(P, cache, dA):
+    d3 = dA * sigmoid(cache["z3"])
+    g = {"W3": d3.T @ cache["a2"], "b3": d3.sum(axis=0)}
+    da2 = d3 @ P["W3"]
+    d2 = da2 * gelu_grad(cache["z2"])
+    g["W2"] = d2.T @ cache["a1"]
+    g["b2"] = d2.sum(axis=0)
+    da1 = d2 @ P["W2"]
+    d1 = da1 * gelu_grad(cache["z1"])
+    g["W1"] = d1.T @ cache["X"]
+    g["b1"] = d1.sum(axis=0)
+    return g
+
+
+def adamw_step(P, G, state, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, wd=1e-4):
+    """One AdamW step (decoupled weight decay on W only), t = 1, 2, ..."""
+    for name in P:
+        m = state.setdefault("m_" + name, np.zeros_like(P[name]))
+        v = state.setdefault("v_" + name, np.zeros_like(P[name]))
+        m[...] = beta1 * m + (1 - beta1) * G[name]
+        v[...] = beta2 * v + (1 - beta2) * G[name] ** 2
+        mh = m / (1 - beta1 ** t)
+        vh = v / (1 - beta2 ** t)
+        if name.startswith("W"):
+            P[name] = P[name] - lr * wd * P[name]
+        P[name] = P[name] - lr * mh / (np.sqrt(vh) + eps)
+    return P
+
+
+# --------------------------------------------------------------------------
+# 4. scale
+# --------------------------------------------------------------------------
+def alpha_rescale(S, A):
+    SA = np.asarray(S, dtype=np.float64) @ A
+    AtA = A.T @ A
+    return math.sqrt(max((A * SA).sum(), 0.0) / (AtA * AtA).sum())

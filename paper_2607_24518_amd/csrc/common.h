@@ -202,6 +202,11 @@ int64_t h_image_words(int32_t stype, int64_t k, int64_t n_chunks);
 hipError_t launch_h_image(const float* H, int32_t stype, int64_t k, int64_t n_chunks, float wt, uint32_t* img,
                           hipStream_t stream);
 hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t stream);
+// Objective pass on the MFMA path: FP32 sums within each 256-column chunk,
+// FP64 across chunks; FP64 partials.  img: chunk images of FP32 H.
+int stream_acc64_supported(int32_t stype, int64_t k);
+hipError_t launch_stream_acc64(const void* S, int32_t stype, int64_t k, const void* img, double* part,
+                               const PlanView& p, hipStream_t stream);
 int stream_uses_mfma(int32_t stype, int h_f64, int acc_f64, int64_t k);
 // resident work-groups per CU of the stream kernel for this storage and rank
 int stream_wgs_per_cu(int32_t stype, int64_t k);

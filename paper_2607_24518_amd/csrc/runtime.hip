@@ -698,7 +698,21 @@ symnmf_status symnmf_objective(symnmf_ctx* ctx, const symnmf_S* S, const void* H
         chk(hipMemsetAsync(Hd, 0, hrows * k * 8, sm));
         chk(launch_copy_h(H, h_is_f64, Hd, 1, S->n * k, sm));
         PlanView pv = plan_view(nullptr, 1, (int32_t)tiles, (int32_t)chunks, P);
-        chk(launch_stream(S->data, S->dtype, S->ld, Hd, 1, k, part, 1, pv, sm));
+        if (!h_is_f64 && stream_acc64_supported(S->dtype, k)) {
+            // MFMA products, FP32 within each 256-column chunk, FP64 across chunks
+            void *Hf = nullptr, *img = nullptr;
+            chk(hipMalloc(&Hf, hrows * k * 4));
+            chk(hipMalloc(&img, h_image_words(S->dtype, k, chunks) * 4));
+            chk(hipMemsetAsync(Hf, 0, hrows * k * 4, sm));
+            chk(launch_copy_h(H, 0, Hf, 0, S->n * k, sm));
+            chk(launch_h_image((const float*)Hf, S->dtype, k, chunks, 1.0f, (uint32_t*)img, sm));
+            chk(launch_stream_acc64(S->data, S->dtype, k, img, (double*)part, pv, sm));
+            chk(hipStreamSynchronize(sm));
+            if (Hf) (void)hipFree(Hf);
+            if (img) (void)hipFree(img);
+        } else {
+            chk(launch_stream(S->data, S->dtype, S->ld, Hd, 1, k, part, 1, pv, sm));
+        }
         UpdateArgs a;
         std::memset(&a, 0, sizeof(a));
         a.rows = S->rows;

@@ -223,9 +223,12 @@ hipError_t launch_h_image(const float* H, int32_t stype, int64_t k, int64_t n_ch
 // is read).  PF: the next image is fetched into registers at the start of a
 // unit (otherwise it is copied at the unit boundary).
 // ---------------------------------------------------------------------------
-template <int KIND, int NT, bool DB, bool PF>
+// ACC64: FP32 MFMA sums within each 256-column chunk, added into FP64
+// accumulators at every chunk boundary; the partials are written as doubles
+// (the objective pass).
+template <int KIND, int NT, bool DB, bool PF, bool ACC64>
 __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ Sv, const u32x4* __restrict__ img1,
-                                                      const u32x4* __restrict__ img2, float* __restrict__ part,
+                                                      const u32x4* __restrict__ img2, void* __restrict__ part,
                                                       PlanView p) {
     constexpr int K = 16 * NT;
     using IS = ImageShape<KIND, K>;
@@ -279,6 +282,15 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
     for (int rg = 0; rg < 4; ++rg)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[rg][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    double acc64[ACC64 ? 4 : 1][ACC64 ? NT : 1][ACC64 ? 4 : 1];
+    if (ACC64) {
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc64[ACC64 ? rg : 0][ACC64 ? nt : 0][ACC64 ? v : 0] = 0.0;
+    }
 
     u32x4 hreg[PF ? CPT : 1];
     int32_t a_next = a;
@@ -363,16 +375,32 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
                 }
             }
         }
-        // end of this tile's run: write the partial and start the next tile
-        if (!more || a_next != a) {
-            float* dst = part + (w + a) * (int64_t)TR * K;
+        if (ACC64) {
 #pragma unroll
             for (int rg = 0; rg < 4; ++rg)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        dst[(64 * wv + 16 * rg + 4 * lg + v) * K + 16 * nt + lr] = acc[rg][nt][v];
+                    for (int v = 0; v < 4; ++v) acc64[ACC64 ? rg : 0][ACC64 ? nt : 0][ACC64 ? v : 0] += (double)acc[rg][nt][v];
+                    acc[rg][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+        // end of this tile's run: write the partial and start the next tile
+        if (!more || a_next != a) {
+#pragma unroll
+            for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t o = (w + a) * (int64_t)TR * K + (64 * wv + 16 * rg + 4 * lg + v) * K + 16 * nt + lr;
+                        if (ACC64) {
+                            ((double*)part)[o] = acc64[ACC64 ? rg : 0][ACC64 ? nt : 0][ACC64 ? v : 0];
+                            acc64[ACC64 ? rg : 0][ACC64 ? nt : 0][ACC64 ? v : 0] = 0.0;
+                        } else {
+                            ((float*)part)[o] = acc[rg][nt][v];
+                        }
+                    }
                     acc[rg][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
         }
@@ -430,12 +458,34 @@ static hipError_t launch_generic_s(const void* S, int64_t ld, const void* H, int
 // k=64 single (64 KB); BF16/FP8 keep three bf16 planes: k=16 double (48 KB),
 // k=32 single (48 KB), k=64 single (96 KB, one work-group per CU).
 template <int KIND>
-static void launch_mfma_kind(const void* S, const u32x4* img1, const u32x4* img2, float* part, int64_t k,
+static void launch_mfma_kind(const void* S, const u32x4* img1, const u32x4* img2, void* part, int64_t k,
                              const PlanView& p, hipStream_t stream) {
     dim3 grid(p.P), block(256);
-    if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true, true>), grid, block, 0, stream, S, img1, img2, part, p);
-    else if (k == 32) hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0, true>), grid, block, 0, stream, S, img1, img2, part, p);
-    else hipLaunchKernelGGL((stream_mfma<KIND, 4, false, false>), grid, block, 0, stream, S, img1, img2, part, p);
+    if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true, true, false>), grid, block, 0, stream, S, img1, img2, part, p);
+    else if (k == 32) hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0, true, false>), grid, block, 0, stream, S, img1, img2, part, p);
+    else hipLaunchKernelGGL((stream_mfma<KIND, 4, false, false, false>), grid, block, 0, stream, S, img1, img2, part, p);
+}
+
+template <int KIND>
+static void launch_mfma_kind_acc64(const void* S, const u32x4* img, void* part, int64_t k, const PlanView& p,
+                                   hipStream_t stream) {
+    dim3 grid(p.P), block(256);
+    if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true, false, true>), grid, block, 0, stream, S, img, img, part, p);
+    else hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0, false, true>), grid, block, 0, stream, S, img, img, part, p);
+}
+
+int stream_acc64_supported(int32_t stype, int64_t k) {
+    return (stype == SYMNMF_S_FP32 || stype == SYMNMF_S_BF16 || stype == SYMNMF_S_FP8) && (k == 16 || k == 32);
+}
+
+hipError_t launch_stream_acc64(const void* S, int32_t stype, int64_t k, const void* img, double* part,
+                               const PlanView& p, hipStream_t stream) {
+    if (!stream_acc64_supported(stype, k) || !img) return hipErrorInvalidValue;
+    const u32x4* i1 = (const u32x4*)img;
+    if (stype == SYMNMF_S_FP32) launch_mfma_kind_acc64<0>(S, i1, part, k, p, stream);
+    else if (stype == SYMNMF_S_BF16) launch_mfma_kind_acc64<1>(S, i1, part, k, p, stream);
+    else launch_mfma_kind_acc64<2>(S, i1, part, k, p, stream);
+    return hipGetLastError();
 }
 
 int stream_wgs_per_cu(int32_t stype, int64_t k) {

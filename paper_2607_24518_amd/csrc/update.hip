@@ -43,22 +43,24 @@ __device__ inline int64_t upd_unit_off(const PlanView& p, int32_t a) {
     return p.full ? (int64_t)a * p.n_chunks : (int64_t)p.unit_offset[a];
 }
 
+constexpr int UT = 1024;   // threads of the update work-group
+
 template <typename HT, int KB>
-__global__ __launch_bounds__(256) void update_kernel(UpdateArgs a, PlanView p) {
+__global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
     __shared__ HT Hs[TR * KB];
     __shared__ HT Hns[TR * KB];
     __shared__ HT Gs[KB * KB];
-    __shared__ double red[8];
+    __shared__ double red[UT / 64];
     const int t = threadIdx.x;
     const int64_t tile = blockIdx.x;
     const int k = (int)a.k;
     const int32_t act = p.full ? (int32_t)tile : p.tile_active[tile];
     const int cls = (act >= 0 && !p.full) ? p.active_class[act] : 0;
     const HT* gram = (const HT*)a.gram_eff + (int64_t)cls * k * k;
-    for (int e = t; e < k * k; e += 256) Gs[(e / k) * KB + e % k] = gram[e];
+    for (int e = t; e < k * k; e += UT) Gs[(e / k) * KB + e % k] = gram[e];
     const int64_t g0 = a.row0 + tile * TR;            // global row of tile row 0
     const HT* Ht = (const HT*)a.H;
-    for (int f = t; f < TR * k; f += 256) Hs[(f / k) * KB + f % k] = Ht[g0 * k + f];
+    for (int f = t; f < TR * k; f += UT) Hs[(f / k) * KB + f % k] = Ht[g0 * k + f];
     __syncthreads();
 
     int64_t w_lo = 0, w_hi = -1, U = 0;
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs a, PlanView p) {
     const HT eta = (HT)a.eta, eps = (HT)a.eps, alpha = (HT)a.alpha, mom = (HT)a.mu, cg = (HT)a.cgrad;
     double tr = 0.0, kkt = 0.0;
     int bad = 0;
-    for (int f = t; f < TR * k; f += 256) {
+    for (int f = t; f < TR * k; f += UT) {
         const int r = f / k, c = f - r * k;
         const int64_t prow = tile * TR + r;
         HT hn = 0;
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs a, PlanView p) {
     }
     __syncthreads();
     double* tg = a.tile_gram + tile * (int64_t)k * k;
-    for (int e = t; e < k * k; e += 256) {
+    for (int e = t; e < k * k; e += UT) {
         const int ia = e / k, ib = e - ia * k;
         double s = 0.0;
         for (int r = 0; r < TR; ++r) s += (double)Hns[r * KB + ia] * (double)Hns[r * KB + ib];
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs a, PlanView p) {
 
 hipError_t launch_update(const UpdateArgs& a, int h_f64, const PlanView& p, hipStream_t stream) {
     const int64_t tiles = a.rows_pad / TR;
-    dim3 grid(tiles), block(256);
+    dim3 grid(tiles), block(UT);
     if (h_f64) {
         if (a.k <= 8) hipLaunchKernelGGL((update_kernel<double, 8>), grid, block, 0, stream, a, p);
         else if (a.k <= 16) hipLaunchKernelGGL((update_kernel<double, 16>), grid, block, 0, stream, a, p);
@@ -240,13 +242,18 @@ __global__ __launch_bounds__(256) void finalize_kernel(int64_t tiles, int k, con
                                                        double* __restrict__ stats) {
     __shared__ double red[8];
     const int kk = k * k;
-    const int ngram = (kk + 255) / 256;
+    const int ngram = (kk + 3) / 4;          // one wave per Gram entry
     const int t = threadIdx.x;
     if ((int)blockIdx.x < ngram) {
-        const int e = blockIdx.x * 256 + t;
-        if (e < kk) {
-            double s = gram_fixed ? gram_fixed[e] : 0.0;
-            for (int64_t i = 0; i < tiles; ++i) s += tile_gram[i * kk + e];
+        const int e = blockIdx.x * 4 + (t >> 6);
+        const int lane = t & 63;
+        if (e >= kk) return;
+        // lane l sums tiles l, l+64, ...; then a fixed-order butterfly
+        double s = 0.0;
+        for (int64_t i = lane; i < tiles; i += 64) s += tile_gram[i * kk + e];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) {
+            if (gram_fixed) s += gram_fixed[e];
             gram_next[e] = s;
             gram_eff[e] = (HT)s;
             gram_eff[kk + e] = (HT)s;
@@ -278,7 +285,7 @@ hipError_t launch_finalize(int64_t tiles, int64_t k, const double* tile_gram, co
                            const double* tile_kkt, const int32_t* tile_bad, const double* gram_fixed,
                            const double* gram_cur64, double* gram_next64, void* gram_eff, int h_f64,
                            double* stats, hipStream_t stream) {
-    const int ngram = (int)((k * k + 255) / 256);
+    const int ngram = (int)((k * k + 3) / 4);
     dim3 grid(ngram + 1), block(256);
     if (h_f64)
         hipLaunchKernelGGL(finalize_kernel<double>, grid, block, 0, stream, tiles, (int)k, tile_gram, tile_tr,

@@ -1,0 +1,130 @@
+"""Parity at the configurations' full sizes.
+
+* |corr| n = 100000, k = 32, T = 2500 (the benchmark workload, same launch
+  configuration): the oracle cannot form the 10^10-entry S, so sampled rows are
+  checked - stored S rows, gradient rows of one step and the updated rows -
+  against the oracle's definition evaluated row by row.
+* TPDM n = 4096, k = 16, T = 20000, Student-t(3) 16-factor model, top 5 %:
+  S in full, then 2000 iterations of projected AdaGrad and of RMSprop, FP64
+  against the FP64 oracle and FP32 against the FP64 oracle (relative objective
+  1e-5).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as o
+import paper_2607_24518_amd as sym
+import synth
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import ctx, dev, from_dev, stored_numpy, to_dev  # noqa: E402
+
+
+def _stored_rows(S, rows):
+    """Decode selected rows of a stored FP32 S (tiled) on the device."""
+    d = S.desc
+    cols = np.arange(d.n)
+    flat = S.buf[: d.rows_pad * d.ld * 4].view(torch.float32)
+    out = []
+    for r in rows:
+        offs = np.array([sym.symnmf_S_offset(int(r), int(c), d.rows_pad, d.ld, d.dtype) for c in cols[:1]])
+        # offsets of a whole row: rows of one tile share the pattern, so build them vectorised
+        R, rr = divmod(int(r), 256)
+        wv, rg, lr = rr >> 6, (rr >> 4) & 3, rr & 15
+        C, cc = np.divmod(cols, 256)
+        s, rem = np.divmod(cc, 16)
+        lg, e = np.divmod(rem, 4)
+        in_tile = (((wv * 16 + s) * 4 + rg) * 64 + (lg * 16 + lr)) * 4 + e
+        idx = (R * (d.ld // 256) + C) * 65536 + in_tile
+        assert idx[0] == offs[0]
+        out.append(flat[torch.from_numpy(idx).to(flat.device)].double().cpu().numpy())
+    return np.stack(out)
+
+
+@pytest.fixture(scope="module")
+def big():
+    X = synth.overlap_returns(0, T=2500, n=100000, groups=32).X.numpy()
+    return X
+
+
+def test_full_size_abs_corr_sampled_rows_and_step(big):
+    X = big
+    n, k = X.shape[1], 32
+    c = ctx()
+    S = sym.symnmf_build_S(c, to_dev(X), dtype=sym.S_FP32)
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([[0, 1, 255, 256, 511, 99839, 99840, n - 1],
+                                     rng.integers(0, n, 24)]))
+    Z = o.standardise_columns(X)
+    ref_rows = np.stack([o.abs_corr_panel(Z, int(r), 1)[0] for r in rows])
+    got_rows = _stored_rows(S, rows)
+    assert np.max(np.abs(got_rows - ref_rows)) < 2e-6
+    # one step from a seeded H0 (an input of both sides)
+    H0 = synth.random_state(11, (n, k), 0.0, 0.06).numpy().astype(np.float64)
+    eta, eps = 0.05, 1e-10
+    st = sym.symnmf_state_create(c, S, k, sym.symnmf_params_default(eta=eta, eps=eps), to_dev(H0))
+    stats = sym.symnmf_step(c, S, st)
+    g = torch.empty(n, k, device=dev())
+    H1 = torch.empty(n, k, device=dev())
+    sym.symnmf_state_read(c, st, 6, g)
+    sym.symnmf_state_read(c, st, 0, H1)
+    g, H1 = from_dev(g), from_dev(H1)
+    gram = H0.T @ H0
+    for i, r in enumerate(rows):
+        g_ref = 4.0 * (H0[r] @ gram - ref_rows[i] @ H0)
+        assert np.max(np.abs(g[r] - g_ref)) <= 2e-5 * np.max(np.abs(g_ref)), r
+        h_ref, _ = o.adagrad_update(H0[r], np.zeros(k), g[r], eta, eps)
+        assert np.max(np.abs(H1[r] - h_ref)) <= 1e-6
+    # properties at full size: the objective terms are finite and E lies in (0, 1)
+    assert stats.full and 0.0 < stats.E < 1.0 and np.isfinite(stats.kkt)
+    f_judge, _ = sym.symnmf_objective(c, S, to_dev(H0), k)
+    assert f_judge == pytest.approx(stats.f, rel=1e-6)
+
+
+@pytest.fixture(scope="module")
+def tpdm4096():
+    X = synth.tpdm_returns(0, T=20000, n=4096, groups=16, nu=3.0).X.numpy()
+    return X, o.tpdm(X, q=0.05, lower_tail=True)
+
+
+@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-12), ("fp32", 3e-6)])
+def test_tpdm_4096_build(tpdm4096, dtype, tol):
+    X, ref = tpdm4096
+    S = sym.symnmf_build_S(ctx(), to_dev(X), kind=sym.TPDM, dtype=sym.DTYPES[dtype], q=0.05, lower_tail=1)
+    M = stored_numpy(S)
+    assert np.max(np.abs(M - ref)) < tol
+
+
+@pytest.mark.parametrize("method", ["adagrad", "rmsprop"])
+def test_tpdm_4096_trajectories_fp64_and_fp32(tpdm4096, method):
+    X, ref = tpdm4096
+    n, k, iters = 4096, 16, 2000
+    c = ctx()
+    base = math.sqrt(ref.mean() / k)
+    if method == "adagrad":
+        p = dict(method=sym.ADAGRAD, eta=base)
+        op = o.Params(eta=base)
+    else:
+        p = dict(method=sym.RMSPROP, eta=0.03 * base, eps=1e-8, alpha=0.99, mu=0.5)
+        op = o.Params(method=o.RMSPROP, eta=0.03 * base, eps=1e-8, alpha=0.99, mu=0.5)
+    H0 = o.init_H(ref.mean(), n, k, 7, as_float32=True)
+    solver = o.Solver(ref, k, op, H0)
+    for _ in range(iters):
+        solver.step()
+    f_orc = o.objective_trace(ref, solver.H)
+    for dtype, tol in (("fp64", 1e-9), ("fp32", 1e-5)):
+        S = sym.symnmf_build_S(c, to_dev(X), kind=sym.TPDM, dtype=sym.DTYPES[dtype], q=0.05, lower_tail=1)
+        f64 = dtype == "fp64"
+        st = sym.symnmf_state_create(c, S, k, sym.symnmf_params_default(**p),
+                                     to_dev(H0, torch.float64 if f64 else torch.float32))
+        for _ in range(iters):
+            sym.symnmf_step(c, S, st, want_stats=False)
+        H = torch.empty(n, k, dtype=torch.float64 if f64 else torch.float32, device=dev())
+        sym.symnmf_state_read(c, st, 0, H)
+        Sref = sym.symnmf_S_load(c, to_dev(ref, torch.float64), dtype=sym.S_FP64)
+        f_gpu, _ = sym.symnmf_objective(c, Sref, to_dev(from_dev(H), torch.float64), k)
+        assert abs(f_gpu - f_orc) / f_orc <= tol, (dtype, f_gpu, f_orc)

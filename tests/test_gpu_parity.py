@@ -343,6 +343,19 @@ def test_objective_fp64_accumulation(S600):
         assert E == pytest.approx(ref / (Sq * Sq).sum(), rel=1e-12)
 
 
+@pytest.mark.parametrize("dtype,k", [("fp32", 16), ("fp32", 32), ("bf16", 32), ("fp8", 16), ("fp32", 24)])
+def test_objective_float32_H(S600, dtype, k):
+    """float32 H: MFMA products summed in FP32 within a 256-column chunk and in
+    FP64 across chunks (k = 16, 32), or the all-FP64 path (other k)."""
+    c = ctx()
+    S = sym.symnmf_S_load(c, to_dev(S600, torch.float64), dtype=sym.DTYPES[dtype], fp8_panel_rows=100)
+    Sq = stored_numpy(S)
+    H = (np.random.default_rng(2).random((600, k)) * 0.1).astype(np.float32)
+    f, E = sym.symnmf_objective(c, S, to_dev(H, torch.float32), k)
+    ref = o.objective_trace(Sq, H.astype(np.float64))
+    assert f == pytest.approx(ref, rel=1e-7)
+
+
 # --- edge cases ----------------------------------------------------------------
 def test_tiny_and_degenerate_shapes():
     c = ctx()
