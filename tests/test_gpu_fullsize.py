@@ -5,9 +5,12 @@
   checked - stored S rows, gradient rows of one step and the updated rows -
   against the oracle's definition evaluated row by row.
 * TPDM n = 4096, k = 16, T = 20000, Student-t(3) 16-factor model, top 5 %:
-  S in full, then 2000 iterations of projected AdaGrad and of RMSprop, FP64
-  against the FP64 oracle and FP32 against the FP64 oracle (relative objective
-  1e-5).
+  S in full, then 2000 iterations of projected AdaGrad and 1000 of RMSprop,
+  FP64 against the FP64 oracle and FP32 against the FP64 oracle (relative
+  objective 1e-5).  RMSprop with momentum 0.5 at this step size has objective
+  spikes (near t = 1200 and t = 2000) after which the trajectory is chaotic: in
+  the oracle alone a 1e-14 relative perturbation of H0 moves f(H_2000) by 7 %,
+  while f(H_1000) agrees to 1e-9, so the comparison is taken at t = 1000.
 """
 import math
 
@@ -102,7 +105,8 @@ def test_tpdm_4096_build(tpdm4096, dtype, tol):
 @pytest.mark.parametrize("method", ["adagrad", "rmsprop"])
 def test_tpdm_4096_trajectories_fp64_and_fp32(tpdm4096, method):
     X, ref = tpdm4096
-    n, k, iters = 4096, 16, 2000
+    n, k = 4096, 16
+    iters = 2000 if method == "adagrad" else 1000
     c = ctx()
     base = math.sqrt(ref.mean() / k)
     if method == "adagrad":
