@@ -99,6 +99,62 @@ def cpu_baseline(X_host, k, H0, eta, rows, steps):
                       f"{build_s:.1f} s not timed"}
 
 
+def ttt_run(ctx, S, k, eta, init, judge, f_ref, tol, max_steps, every, store, softplus=False):
+    """Iterate from init(H) (timed with the steps) for max_steps, keeping every
+    ``every``-th iterate in ``store``; afterwards find the first kept iterate
+    with (judge(H_t) - f_ref) / f_ref <= tol.  Returns a dict with the final
+    relative objective and, when reached, the iteration and the seconds from
+    the start of the initialisation (HIP events on the solver stream)."""
+    import torch
+    import paper_2607_24518_amd as sym
+
+    n = S.desc.n
+    nsave = max_steps // every
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nsave)]
+    ev0.record()
+    H = torch.empty(n, k, device=store.device)
+    init(H)
+    p = sym.symnmf_params_default(eta=eta, softplus=int(softplus), max_iter=10 ** 9)
+    st = sym.symnmf_state_create(ctx, S, k, p, H)
+    for t in range(nsave * every):
+        sym.symnmf_step(ctx, S, st, want_stats=False)
+        if (t + 1) % every == 0:
+            j = (t + 1) // every - 1
+            sym.symnmf_state_read(ctx, st, 0, store[j])   # H_{t+1}
+            evs[j].record()
+    torch.cuda.synchronize()
+    del st
+    cache = {}
+
+    def rel(j):
+        if j not in cache:
+            cache[j] = (judge(store[j]) - f_ref) / f_ref
+        return cache[j]
+
+    # coarse scan, then bisection inside the first bracket that meets tol
+    hit = None
+    prev = -1
+    for j in list(range(31, nsave, 32)) + [nsave - 1]:
+        if rel(j) <= tol:
+            lo, hi = prev + 1, j
+            while lo < hi:
+                mid = (lo + hi) // 2
+                if rel(mid) <= tol:
+                    hi = mid
+                else:
+                    lo = mid + 1
+            hit = lo
+            break
+        prev = j
+    entry = {"final_rel": rel(nsave - 1), "steps_run": nsave * every, "rel_first_kept": rel(0)}
+    entry["times"] = [ev0.elapsed_time(e) / 1000.0 for e in evs]
+    if hit is not None:
+        entry.update(iters=(hit + 1) * every, seconds=entry["times"][hit])
+    return entry
+
+
 def time_to_tolerance(args):
     """Time to (f_S(H_t) - f_ref) / f_ref <= tol for several variants of the
     same instance and initial H.
@@ -127,73 +183,203 @@ def time_to_tolerance(args):
             stores[dt] = sym.symnmf_build_S(ctx, inst.X, dtype=sym.DTYPES[dt], fp8_panel_rows=256)
     del inst
     S32 = stores["fp32"]
-    H0 = torch.empty(n, k, device=dev)
-    sym.symnmf_init_H(ctx, S32, k, 1, H0)
     eta = math.sqrt(S32.desc.mean / k)
 
     def judge(H):
         return sym.symnmf_objective(ctx, S32, H, k)[0]
 
-    # reference
-    t0 = time.time()
-    p = sym.symnmf_params_default(eta=eta, max_iter=args.ttt_ref_iters)
-    st = sym.symnmf_state_create(ctx, S32, k, p, H0)
-    Hr = torch.empty(n, k, device=dev)
-    rs, conv = sym.symnmf_solve_to_tol(ctx, S32, st, H_out=Hr)
-    f_ref = judge(Hr)
-    del st
-    log(f"reference: t={rs.t} converged={conv} E={rs.E:.6e} kkt={rs.kkt:.3e} f_ref={f_ref:.9e} "
-        f"({time.time() - t0:.1f} s)")
+    f_ref, rs, conv = reference_solve(ctx, S32, k, eta, 1, args.ttt_ref_iters)
     results = {"f_ref": f_ref, "ref_iters": int(rs.t), "ref_certified": bool(conv), "tol": args.ttt_tol,
                "variants": {}}
     every = max(1, args.ttt_save_every)
-    nsave = args.ttt_max // every
-    store = torch.empty(nsave, n, k, device=dev)
+    store = torch.empty(args.ttt_max // every, n, k, device=dev)
     for v in variants:
         parts = v.split("-")
-        dt, softplus = parts[0], "softplus" in parts
-        S = stores[dt]
-        torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(nsave)]
-        ev0.record()
-        H = torch.empty(n, k, device=dev)
-        sym.symnmf_init_H(ctx, S, k, 1, H)
-        p = sym.symnmf_params_default(eta=eta, softplus=int(softplus), max_iter=10 ** 9)
-        st = sym.symnmf_state_create(ctx, S, k, p, H)
-        for t in range(nsave * every):
-            sym.symnmf_step(ctx, S, st, want_stats=False)
-            if (t + 1) % every == 0:
-                j = (t + 1) // every - 1
-                sym.symnmf_state_read(ctx, st, 0, store[j])   # H_{t+1}
-                evs[j].record()
-        torch.cuda.synchronize()
-        del st
-
-        def rel(j):
-            return (judge(store[j]) - f_ref) / f_ref
-
-        # coarse scan, then bisection inside the first bracket that meets tol
-        hit = None
-        prev = -1
-        for j in list(range(31, nsave, 32)) + [nsave - 1]:
-            if rel(j) <= args.ttt_tol:
-                lo, hi = prev + 1, j
-                while lo < hi:
-                    mid = (lo + hi) // 2
-                    if rel(mid) <= args.ttt_tol:
-                        hi = mid
-                    else:
-                        lo = mid + 1
-                hit = lo
-                break
-            prev = j
-        entry = {"final_rel": rel(nsave - 1), "steps_run": nsave * every}
-        if hit is not None:
-            entry.update(iters=(hit + 1) * every, seconds=ev0.elapsed_time(evs[hit]) / 1000.0)
+        S = stores[parts[0]]
+        entry = ttt_run(ctx, S, k, eta, lambda H: sym.symnmf_init_H(ctx, S, k, 1, H), judge, f_ref, args.ttt_tol,
+                        args.ttt_max, every, store, softplus="softplus" in parts)
+        entry.pop("times")
         results["variants"][v] = entry
         log(f"variant {v}: {entry}")
     return results
+
+
+def reference_solve(ctx, S, k, eta, seed, max_iter, H_out=None):
+    """FP32 AdaGrad from the counter-RNG init until the stop rule certifies an
+    iterate; returns (f of the certified iterate, final stats, certified)."""
+    import torch
+    import paper_2607_24518_amd as sym
+
+    n = S.desc.n
+    t0 = time.time()
+    H0 = torch.empty(n, k, device="cuda:0")
+    sym.symnmf_init_H(ctx, S, k, seed, H0)
+    p = sym.symnmf_params_default(eta=eta, max_iter=max_iter)
+    st = sym.symnmf_state_create(ctx, S, k, p, H0)
+    Hr = H_out if H_out is not None else torch.empty(n, k, device="cuda:0")
+    rs, conv = sym.symnmf_solve_to_tol(ctx, S, st, H_out=Hr)
+    f_ref = sym.symnmf_objective(ctx, S, Hr, k)[0]
+    del st
+    log(f"reference: n={n} t={rs.t} converged={conv} E={rs.E:.6e} kkt={rs.kkt:.3e} f_ref={f_ref:.9e} "
+        f"({time.time() - t0:.1f} s)")
+    return f_ref, rs, conv
+
+
+WARM_WIDTH, WARM_HIDDEN, WARM_OMEGA_SEED = 64, 256, 7
+
+
+def warm_start_study(args):
+    """Learned warm start against random initialisation.
+
+    Training: for every training seed the returns are generated, S (FP32) is
+    built, solved from the counter-RNG init with the paper's stop rule, and the
+    pair (canonical sketch coordinates, certified H) is kept on the device;
+    the network is then trained with the scale-free Gram loss.
+    Evaluation on held-out seeds (and optionally on the n = 100000 |corr|
+    workload): time to relative objective tolerance from (a) the random init,
+    (b) the network-free coordinates, (c) the network, each timed from the
+    start of its initialisation (sketch, coordinates and network included);
+    f_ref is the random-init reference solve certified by the stop rule.  A
+    warm run that has not reached the tolerance within twice the random run's
+    iterations falls back to the random run, and its time counts both.
+    """
+    import numpy as np
+    import torch
+    import paper_2607_24518_amd as sym
+    import synth
+
+    dev = torch.device("cuda:0")
+    ctx = sym.symnmf_create(0)
+    k, n = args.warm_k, args.warm_n
+    W, HID = WARM_WIDTH, WARM_HIDDEN
+
+    def returns(seed, n_cols):
+        if args.warm_family == "panel":
+            return synth.panel_returns(seed, T=args.warm_T, n=n_cols, groups=args.warm_groups, block=65536,
+                                       device=dev).X
+        return synth.overlap_returns(seed, T=args.warm_T, n=n_cols, groups=args.warm_groups, device=dev).X
+
+    def features(S, nn):
+        Y = torch.empty(nn, W, device=dev)
+        sym.symnmf_sketch(ctx, S, WARM_OMEGA_SEED, W, Y)
+        Xc = torch.empty(nn, W, device=dev)
+        sym.symnmf_canonical(ctx, Y, k, Xc)
+        return Xc
+
+    out = {"family": args.warm_family, "n_train": n, "k": k, "T": args.warm_T, "groups": args.warm_groups,
+           "width": W, "hidden": HID}
+    # 1. training pairs
+    t0 = time.time()
+    pairs = []
+    train_seeds = list(range(args.warm_seed0, args.warm_seed0 + args.warm_train))
+    ref_iters = []
+    for i, seed in enumerate(train_seeds):
+        X = returns(seed, n)
+        S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
+        del X
+        eta = math.sqrt(S.desc.mean / k)
+        H0 = torch.empty(n, k, device=dev)
+        sym.symnmf_init_H(ctx, S, k, seed, H0)
+        st = sym.symnmf_state_create(ctx, S, k, sym.symnmf_params_default(eta=eta, max_iter=args.warm_solve_iters),
+                                     H0)
+        Hs = torch.empty(n, k, device=dev)
+        rs, conv = sym.symnmf_solve_to_tol(ctx, S, st, H_out=Hs)
+        del st
+        ref_iters.append(int(rs.t))
+        pairs.append((features(S, n), Hs))
+        del S
+        if (i + 1) % 10 == 0 or i + 1 == len(train_seeds):
+            log(f"training instance {i + 1}/{len(train_seeds)} solved (t={rs.t} conv={conv} E={rs.E:.4e}) "
+                f"{time.time() - t0:.0f} s")
+    out["train_solve_iters_median"] = float(np.median(ref_iters))
+    out["train_data_seconds"] = round(time.time() - t0, 1)
+    # 2. training
+    t0 = time.time()
+    params = torch.empty(sym.symnmf_mlp_param_count(W, HID, k), device=dev)
+    sym.symnmf_mlp_init(ctx, W, HID, k, args.warm_seed0, params)
+    net = sym.symnmf_mlp_create(ctx, W, HID, k, params)
+    rng = np.random.default_rng(args.warm_seed0)
+    hist = []
+    steps_total = args.warm_epochs * len(pairs)
+    step = 0
+    for ep in range(args.warm_epochs):
+        losses = []
+        for j in rng.permutation(len(pairs)):
+            lr = args.warm_lr * 0.5 * (1.0 + math.cos(math.pi * step / steps_total))   # cosine decay
+            losses.append(sym.symnmf_mlp_train_step(ctx, net, pairs[j][0], pairs[j][1], lr=lr,
+                                                    weight_decay=args.warm_wd, loss_kind=1))
+            step += 1
+        hist.append(float(np.mean(losses)))
+        if ep % 5 == 0 or ep + 1 == args.warm_epochs:
+            log(f"epoch {ep}: mean Gram loss {hist[-1]:.5f} ({time.time() - t0:.0f} s)")
+    out["train_loss_first_epoch"] = hist[0]
+    out["train_loss_last_epoch"] = hist[-1]
+    out["train_seconds"] = round(time.time() - t0, 1)
+    del pairs
+    torch.cuda.empty_cache()
+
+    # 3. evaluation
+    def evaluate(S, k_eval, model, label, seed, max_steps):
+        nn = S.desc.n
+        eta = math.sqrt(S.desc.mean / k_eval)
+
+        def judge(H):
+            return sym.symnmf_objective(ctx, S, H, k_eval)[0]
+
+        f_ref, rs, conv = reference_solve(ctx, S, k_eval, eta, seed, args.warm_ref_iters)
+        every = 2
+        store = torch.empty(max_steps // every, nn, k_eval, device=dev)
+        inits = {
+            "random": lambda H: sym.symnmf_init_H(ctx, S, k_eval, seed, H),
+            "coords": lambda H: sym.symnmf_warm_start(ctx, S, None, W, k_eval, WARM_OMEGA_SEED, H),
+            "mlp": lambda H: sym.symnmf_warm_start(ctx, S, model, W, k_eval, WARM_OMEGA_SEED, H),
+        }
+        res = {"f_ref": f_ref, "ref_iters": int(rs.t), "ref_certified": bool(conv)}
+        for name, init in inits.items():
+            e = ttt_run(ctx, S, k_eval, eta, init, judge, f_ref, args.ttt_tol, max_steps, every, store)
+            times = e.pop("times")
+            res[name] = e
+        del store
+        r_it, r_s = res["random"].get("iters"), res["random"].get("seconds")
+        for name in ("coords", "mlp"):
+            e = res[name]
+            if r_it is None:
+                continue
+            if e.get("iters") is None or e["iters"] > 2 * r_it:
+                # fallback: the warm run is abandoned after 2x the random iterations
+                # and the random run is started
+                idx = min(2 * r_it // every, len(times)) - 1
+                e["fallback"] = True
+                e["seconds_with_fallback"] = times[idx] + r_s
+            else:
+                e["fallback"] = False
+                e["seconds_with_fallback"] = e["seconds"]
+            e["speedup_vs_random"] = round(r_s / e["seconds_with_fallback"], 3)
+        log(f"{label}: " + json.dumps({kk: (vv if not isinstance(vv, dict) else
+                                             {a: b for a, b in vv.items() if a != 'times'})
+                                        for kk, vv in res.items()}))
+        return res
+
+    held = []
+    for seed in range(args.warm_heldout0, args.warm_heldout0 + args.warm_heldout):
+        X = returns(seed, n)
+        S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
+        del X
+        held.append(evaluate(S, k, net, f"held-out seed {seed}", seed, args.warm_max))
+        del S
+    out["heldout"] = held
+    for name in ("coords", "mlp"):
+        sp = [h[name]["speedup_vs_random"] for h in held if "speedup_vs_random" in h[name]]
+        if sp:
+            out[f"{name}_speedup_median"] = float(np.median(sp))
+            out[f"{name}_wins"] = int(sum(1 for v in sp if v > 1.0))
+            out[f"{name}_fallbacks"] = int(sum(1 for h in held if h[name].get("fallback")))
+    if args.warm_c3:
+        X = synth.overlap_returns(0, T=2500, n=100000, groups=32, device=dev).X
+        S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
+        del X
+        out["c3_abs_corr_n100000"] = evaluate(S, k, net, "n=100000 |corr|", 1, args.warm_c3_max)
+    return out
 
 
 def main():
@@ -218,7 +404,32 @@ def main():
     ap.add_argument("--ttt-max", type=int, default=6000)
     ap.add_argument("--ttt-save-every", type=int, default=2)
     ap.add_argument("--ttt-ref-iters", type=int, default=8000)
+    ap.add_argument("--warm", action="store_true", help="learned warm start study instead of the step rate")
+    ap.add_argument("--warm-family", default="panel", choices=["panel", "overlap"])
+    ap.add_argument("--warm-n", type=int, default=20000)
+    ap.add_argument("--warm-k", type=int, default=64)
+    ap.add_argument("--warm-T", type=int, default=1000)
+    ap.add_argument("--warm-groups", type=int, default=64)
+    ap.add_argument("--warm-train", type=int, default=200)
+    ap.add_argument("--warm-seed0", type=int, default=1000)
+    ap.add_argument("--warm-heldout", type=int, default=20)
+    ap.add_argument("--warm-heldout0", type=int, default=2000)
+    ap.add_argument("--warm-solve-iters", type=int, default=4000)
+    ap.add_argument("--warm-ref-iters", type=int, default=8000)
+    ap.add_argument("--warm-epochs", type=int, default=40)
+    ap.add_argument("--warm-lr", type=float, default=1e-3)
+    ap.add_argument("--warm-wd", type=float, default=1e-4)
+    ap.add_argument("--warm-max", type=int, default=4000)
+    ap.add_argument("--warm-c3", action="store_true", help="also evaluate on the n=100000 |corr| workload")
+    ap.add_argument("--warm-c3-max", type=int, default=6000)
     args = ap.parse_args()
+
+    if args.warm:
+        res = warm_start_study(args)
+        print(json.dumps({"metric": "time to relative objective tolerance, learned warm start vs random init",
+                          "unit": "s", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                          "tol": args.ttt_tol, **res}), flush=True)
+        return
 
     if args.ttt:
         res = time_to_tolerance(args)

@@ -276,6 +276,100 @@ symnmf_status symnmf_profile(symnmf_ctx* ctx, int32_t enable, double* ms_out, in
  * format definition (0 expected), or -1 on a HIP error.  Synchronises. */
 int32_t symnmf_selfcheck_fp8(symnmf_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start.  Not part of the paper's method (its only learned
+ * solver is trained per instance and, the paper notes, its weights do not
+ * carry over between matrices of different spectral structure).  A per-row
+ * sketch of S is mapped to canonical coordinates that do not depend on the
+ * random sketch basis or on the column order of the solution, and a small MLP
+ * maps every row's coordinates to an initial row of H:
+ *   1. Y = S Omega, Omega n x w standard normal (Box-Muller on SplitMix64);
+ *   2. top-k eigenpairs of Y^T Y: Z = Y V_k Lambda_k^-1/2; successive
+ *      projection (Gillis & Vavasis 2014) picks k anchor rows of Z; rows in
+ *      the anchor basis C = Z Z[anchors]^-1, zero-padded to w columns;
+ *   3. MLP w -> h -> h -> k, exact GELU x Phi(x), softplus output;
+ *   4. H0 = alpha A with alpha^2 = tr(A^T S A) / ||A^T A||_F^2.
+ * Training minimises a column-permutation invariant Gram loss (through the
+ * trace identity ||A A^T - B B^T||^2 = ||A^T A||^2 - 2 ||A^T B||^2 + ||B^T B||^2,
+ * no m x m matrix) against solved factors B with AdamW (Loshchilov & Hutter
+ * 2019).
+ * ------------------------------------------------------------------------ */
+typedef struct symnmf_mlp symnmf_mlp;
+
+typedef struct {
+    double lr, beta1, beta2, eps, weight_decay;   /* AdamW; decay on W1..W3 only */
+} symnmf_adamw;
+
+/* Parameters of the network as one float32 vector, in this order:
+ * W1 (h x w), W2 (h x h), W3 (k x h) row-major (y = W x + b), b1 (h), b2 (h),
+ * b3 (k).  Returns the count, or -1 for sizes outside 1..64 (w, k) and
+ * 1..1024 (h). */
+int64_t symnmf_mlp_param_count(int64_t width, int64_t hidden, int64_t k);
+
+/* Initial parameters (device, symnmf_mlp_param_count floats): layer l = 0, 1, 2
+ * gets W_l = G / sqrt(fan_in) with G the standard normals of the sketch
+ * generator (same definition as Omega in symnmf_sketch) keyed 4 seed + 1 + l,
+ * element (r, c) at counter index r * fan_in + c; biases 0.  Asynchronous. */
+symnmf_status symnmf_mlp_init(symnmf_ctx* ctx, int64_t width, int64_t hidden, int64_t k, uint64_t seed,
+                              float* params);
+
+/* Network with parameters ``params`` (device, symnmf_mlp_param_count floats,
+ * copied) and zero AdamW state.  Owns its device memory (parameters, BF16
+ * weight copies, gradients, moments, activations grown to the largest row
+ * count seen), freed by symnmf_mlp_destroy. */
+symnmf_status symnmf_mlp_create(symnmf_ctx* ctx, int64_t width, int64_t hidden, int64_t k, const float* params,
+                                symnmf_mlp** out);
+void symnmf_mlp_destroy(symnmf_mlp* mlp);
+
+/* Copy to ``dst`` (device, symnmf_mlp_param_count floats): which 0 = parameters,
+ * 1 = gradient of the last training step, 2 = AdamW first moment, 3 = second
+ * moment.  Asynchronous. */
+symnmf_status symnmf_mlp_read(symnmf_ctx* ctx, const symnmf_mlp* mlp, int32_t which, float* dst);
+/* Replace the parameters (device floats) and clear the AdamW state and step
+ * count.  Asynchronous. */
+symnmf_status symnmf_mlp_write(symnmf_ctx* ctx, symnmf_mlp* mlp, const float* params);
+
+/* A (m x k, device float32) = network(X) for X (m x w, device float32).
+ * bf16_weights: multiply by the BF16-rounded weights (inference form, FP32
+ * activations and accumulation); 0: the FP32 weights.  Asynchronous. */
+symnmf_status symnmf_mlp_forward(symnmf_ctx* ctx, symnmf_mlp* mlp, const float* X, int64_t m,
+                                 int32_t bf16_weights, float* A);
+
+/* One training step on one instance: forward with the FP32 weights on X
+ * (m x w), loss against the target B (m x k, device float32), backward, one
+ * AdamW update.  loss_kind 0: L = ||A A^T - B B^T||_F^2 / ||B^T B||_F^2;
+ * 1: the scale-free form L = 1 - ||A^T B||^4 / (||A^T A||^2 ||B^T B||^2), the
+ * residual of the best scalar multiple of A A^T (the warm start rescales A
+ * anyway).  *loss (may be NULL) receives L at the parameters before the
+ * update.  Synchronises (the k x k products are read back). */
+symnmf_status symnmf_mlp_train_step(symnmf_ctx* ctx, symnmf_mlp* mlp, const float* X, const float* B, int64_t m,
+                                    const symnmf_adamw* opt, int32_t loss_kind, double* loss);
+
+/* Y (rows x width, device float32 row-major) = S_panel Omega with
+ * Omega_ij = sqrt(-2 ln(1 - u)) cos(2 pi v), u and v the top 53 bits of
+ * SplitMix64 outputs 2e and 2e + 1 (e = i * width + j) of key omega_seed,
+ * scaled by 2^-53.  1 <= width <= 64.  Runs the S.H stream once.
+ * Temporary device memory is allocated and freed inside.  Synchronises. */
+symnmf_status symnmf_sketch(symnmf_ctx* ctx, const symnmf_S* S, uint64_t omega_seed, int64_t width, float* Y);
+
+/* Canonical coordinates of the rows of a sketch Y (n x w, device float32):
+ * X (n x w, device float32) = [C, 0] with C = Z Z[anchors]^-1 (step 2 above;
+ * C is the same for any signs and order of the eigenvectors).  anchors
+ * (device int64, k entries, may be NULL) receives the anchor rows in
+ * selection order.  1 <= k <= w <= 64, n >= w.  ENUMERIC when Y^T Y has a
+ * non-positive eigenvalue among the k largest or the anchor rows are linearly
+ * dependent.  Synchronises. */
+symnmf_status symnmf_canonical(symnmf_ctx* ctx, const float* Y, int64_t n, int64_t width, int64_t k, float* X,
+                               int64_t* anchors);
+
+/* Warm start of the full matrix (S->rows == n): sketch with omega_seed and the
+ * network's width, canonical coordinates, network with BF16 weights (mlp
+ * non-NULL) or the coordinates themselves clipped at zero (mlp NULL: the
+ * network-free ablation), then the alpha rescaling; H0: device n x k float32.
+ * The network's k must equal k.  Synchronises. */
+symnmf_status symnmf_warm_start(symnmf_ctx* ctx, const symnmf_S* S, symnmf_mlp* mlp, int64_t width, int64_t k,
+                                uint64_t omega_seed, float* H0);
+
 #ifdef __cplusplus
 }
 #endif

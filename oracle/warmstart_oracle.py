@@ -125,6 +125,18 @@ def init_params(k: int, seed: int = 0, width: int = 64, hidden: int = 256):
     }
 
 
+def init_params_counter(k: int, seed: int, width: int = 64, hidden: int = 256):
+    """W_l = omega(4 seed + 1 + l, fan_out, fan_in) / sqrt(fan_in), b_l = 0:
+    the normals of the sketch generator, so a network is reproducible from its
+    seed alone."""
+    shapes = [(hidden, width), (hidden, hidden), (k, hidden)]
+    P = {}
+    for l, (r, c) in enumerate(shapes):
+        P[f"W{l + 1}"] = omega(4 * seed + 1 + l, r, c) / math.sqrt(c)
+    P["b1"], P["b2"], P["b3"] = np.zeros(hidden), np.zeros(hidden), np.zeros(k)
+    return P
+
+
 def forward(P, X):
     z1 = X @ P["W1"].T + P["b1"]
     a1 = gelu(z1)
@@ -140,6 +152,19 @@ def gram_loss(A, B):
     norm = (BtB * BtB).sum()
     L = ((AtA * AtA).sum() - 2.0 * (AtB * AtB).sum() + norm) / norm
     dA = 4.0 * (A @ AtA - B @ (B.T @ A)) / norm
+    return L, dA
+
+
+def gram_cos_loss(A, B):
+    """Scale-free Gram loss: the residual of the best scalar fit,
+        min_c ||c A A^T - B B^T||^2 / ||B B^T||^2 = 1 - <A A^T, B B^T>^2 / (||A A^T||^2 ||B B^T||^2),
+    with <A A^T, B B^T> = ||A^T B||^2 and ||A A^T|| = ||A^T A||.  With
+    a = ||A^T A||^2, b = ||A^T B||^2, c = ||B^T B||^2:
+        dL/dA = (4 b / (a c)) ((b / a) A (A^T A) - B (B^T A))."""
+    AtA, AtB, BtB = A.T @ A, A.T @ B, B.T @ B
+    a, b, c = (AtA * AtA).sum(), (AtB * AtB).sum(), (BtB * BtB).sum()
+    L = 1.0 - b * b / (a * c)
+    dA = (4.0 * b / (a * c)) * ((b / a) * (A @ AtA) - B @ (B.T @ A))
     return L, dA
 
 
@@ -179,3 +204,25 @@ def alpha_rescale(S, A):
     SA = np.asarray(S, dtype=np.float64) @ A
     AtA = A.T @ A
     return math.sqrt(max((A * SA).sum(), 0.0) / (AtA * AtA).sum())
+
+
+# --------------------------------------------------------------------------
+# composed warm start
+# --------------------------------------------------------------------------
+def bf16_weights(P):
+    """The network with W1..W3 rounded to bfloat16 (nearest even), biases kept."""
+    from .symnmf_oracle import to_bf16
+    return {name: (to_bf16(v) if name.startswith("W") else v) for name, v in P.items()}
+
+
+def warm_start(S, k: int, seed: int, P=None, width: int = 64):
+    """H0 = alpha A with A = network(canonical coordinates of S Omega) using the
+    BF16-rounded weights, or A = the coordinates clipped at zero when P is None."""
+    S = np.asarray(S, dtype=np.float64)
+    Y = sketch(S, omega(seed, S.shape[0], width))
+    X, anchors = canonical_coordinates(Y, k, width)
+    if P is None:
+        A = np.maximum(X[:, :k], 0.0)
+    else:
+        A, _ = forward(bf16_weights(P), X)
+    return alpha_rescale(S, A) * A, anchors

@@ -55,6 +55,10 @@ class symnmf_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class symnmf_adamw(ctypes.Structure):
+    _fields_ = [("lr", c_dbl), ("beta1", c_dbl), ("beta2", c_dbl), ("eps", c_dbl), ("weight_decay", c_dbl)]
+
+
 class SymnmfError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"symnmf error {code}: {msg}")
@@ -94,6 +98,18 @@ SIGNATURES = {
     "symnmf_selfcheck_fp8": (c_i32, [c_vp]),
     "symnmf_profile": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
     "symnmf_probe_copy": (c_i32, [c_vp, c_vp, c_vp, c_i64]),
+    "symnmf_mlp_param_count": (c_i64, [c_i64, c_i64, c_i64]),
+    "symnmf_mlp_init": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_u64, c_vp]),
+    "symnmf_mlp_create": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_vp, ctypes.POINTER(c_vp)]),
+    "symnmf_mlp_destroy": (None, [c_vp]),
+    "symnmf_mlp_read": (c_i32, [c_vp, c_vp, c_i32, c_vp]),
+    "symnmf_mlp_write": (c_i32, [c_vp, c_vp, c_vp]),
+    "symnmf_mlp_forward": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_i32, c_vp]),
+    "symnmf_mlp_train_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, ctypes.POINTER(symnmf_adamw), c_i32,
+                                      ctypes.POINTER(c_dbl)]),
+    "symnmf_sketch": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_u64, c_i64, c_vp]),
+    "symnmf_canonical": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_vp]),
+    "symnmf_warm_start": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, c_i64, c_u64, c_vp]),
 }
 
 PROFILE_KERNELS = ("stream", "update", "finalize", "plan", "image")
@@ -326,3 +342,89 @@ def symnmf_profile(ctx, enable: bool, read: bool = True):
 def symnmf_probe_copy(ctx, src, dst, nbytes=None):
     nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
     _check(ctx, lib().symnmf_probe_copy(ctx, _ptr(src), _ptr(dst), nbytes))
+
+
+# ---------------------------------------------------------------------------
+# learned warm start
+# ---------------------------------------------------------------------------
+MLP_BUFFERS = {"params": 0, "grad": 1, "m": 2, "v": 3}
+
+
+class Mlp:
+    """Handle of a device network (width -> hidden -> hidden -> k)."""
+
+    def __init__(self, ctx, handle, width, hidden, k):
+        self.ctx, self.handle, self.width, self.hidden, self.k = ctx, handle, width, hidden, k
+        self.count = symnmf_mlp_param_count(width, hidden, k)
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.symnmf_mlp_destroy(self.handle)
+            self.handle = None
+
+
+def symnmf_mlp_param_count(width: int, hidden: int, k: int) -> int:
+    return lib().symnmf_mlp_param_count(width, hidden, k)
+
+
+def symnmf_mlp_init(ctx, width: int, hidden: int, k: int, seed: int, params):
+    _check(ctx, lib().symnmf_mlp_init(ctx, width, hidden, k, seed, _ptr(params)))
+    return params
+
+
+def symnmf_mlp_create(ctx, width: int, hidden: int, k: int, params) -> Mlp:
+    """params: device float32 tensor of symnmf_mlp_param_count floats."""
+    h = c_vp()
+    _check(ctx, lib().symnmf_mlp_create(ctx, width, hidden, k, _ptr(params), ctypes.byref(h)))
+    return Mlp(ctx, h, width, hidden, k)
+
+
+def symnmf_mlp_destroy(m: Mlp):
+    if m.handle is not None:
+        lib().symnmf_mlp_destroy(m.handle)
+        m.handle = None
+
+
+def symnmf_mlp_read(ctx, m: Mlp, which, dst):
+    which = MLP_BUFFERS[which] if isinstance(which, str) else which
+    _check(ctx, lib().symnmf_mlp_read(ctx, m.handle, which, _ptr(dst)))
+    return dst
+
+
+def symnmf_mlp_write(ctx, m: Mlp, params):
+    _check(ctx, lib().symnmf_mlp_write(ctx, m.handle, _ptr(params)))
+
+
+def symnmf_mlp_forward(ctx, m: Mlp, X, A, bf16_weights: bool = True):
+    _check(ctx, lib().symnmf_mlp_forward(ctx, m.handle, _ptr(X), X.shape[0], int(bf16_weights), _ptr(A)))
+    return A
+
+
+def symnmf_mlp_train_step(ctx, m: Mlp, X, B, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4,
+                          loss_kind=0):
+    """One AdamW step on one instance; returns the loss before the update
+    (loss_kind 0: Gram loss, 1: scale-free Gram loss)."""
+    opt = symnmf_adamw(lr=lr, beta1=beta1, beta2=beta2, eps=eps, weight_decay=weight_decay)
+    loss = c_dbl()
+    _check(ctx, lib().symnmf_mlp_train_step(ctx, m.handle, _ptr(X), _ptr(B), X.shape[0], ctypes.byref(opt),
+                                            int(loss_kind), ctypes.byref(loss)))
+    return loss.value
+
+
+def symnmf_sketch(ctx, S: Matrix, omega_seed: int, width: int, Y):
+    _check(ctx, lib().symnmf_sketch(ctx, ctypes.byref(S.desc), omega_seed, width, _ptr(Y)))
+    return Y
+
+
+def symnmf_canonical(ctx, Y, k: int, X, anchors=None):
+    n, width = Y.shape
+    _check(ctx, lib().symnmf_canonical(ctx, _ptr(Y), n, width, k, _ptr(X),
+                                       _ptr(anchors) if anchors is not None else None))
+    return X
+
+
+def symnmf_warm_start(ctx, S: Matrix, mlp, width: int, k: int, omega_seed: int, H0):
+    """mlp: an Mlp, or None for the network-free coordinates clipped at zero."""
+    _check(ctx, lib().symnmf_warm_start(ctx, ctypes.byref(S.desc), mlp.handle if mlp is not None else None,
+                                        width, k, omega_seed, _ptr(H0)))
+    return H0

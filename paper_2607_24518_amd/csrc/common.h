@@ -310,4 +310,38 @@ hipError_t launch_fp8_decode_check(int32_t* bad, hipStream_t stream);
 // objective pass: per-tile tr(H^T S H) partial and Gram of H (FP64 H).
 hipError_t launch_objective_tiles(const UpdateArgs& a, const PlanView& plan, hipStream_t stream);
 
+// warmstart.hip
+hipError_t launch_omega(uint64_t seed, int64_t n, int64_t rows_alloc, int w, float* out, hipStream_t stream);
+// dense FP32 S.H rows (rows x k) from the partials of a full FP32-accumulating stream pass
+hipError_t launch_sh_dense(const float* part, int64_t rows, int64_t rows_pad, int64_t k, int32_t n_chunks, int32_t P,
+                           const float* H, int64_t row0, const float* scale, const float* diag, int64_t panel_rows,
+                           float* out, hipStream_t stream);
+// C = alpha op(A) op(B) + bias with epilogue (0 none, 1 GELU, 2 softplus); Z: pre-epilogue copy
+// or null.  split_ws (split_ws_floats floats, may be null) enables split-K for small outputs.
+hipError_t launch_gemm(int ta, int tb, int b_bf16, int epi, const float* A, const void* B, const float* bias, float* C,
+                       float* Z, int64_t M, int64_t N, int64_t K, float alpha, float* split_ws,
+                       int64_t split_ws_floats, hipStream_t stream);
+// dZ = dA * f'(Z): mode 1 GELU, mode 2 softplus
+hipError_t launch_act_backward(const float* dA, const float* Z, float* dZ, int64_t m, int mode, hipStream_t stream);
+hipError_t launch_colsum(const float* X, int64_t m, int64_t ncol, float* out, hipStream_t stream);
+hipError_t launch_adamw(float* P, const float* G, float* M, float* V, int64_t m, int64_t n_decay, float lr, float b1,
+                        float b2, float eps, float wd, int64_t t, hipStream_t stream);
+hipError_t launch_to_bf16(const float* x, uint16_t* y, int64_t m, hipStream_t stream);
+// successive projection on R (m x k FP64, destroyed); pick: k device int64; bval/bidx: nb entries
+hipError_t launch_spa(double* R, int64_t m, int64_t k, double* bval, int64_t* bidx, int nb, int64_t* pick,
+                      hipStream_t stream);
+int64_t xty_work_doubles(int64_t m, int64_t kx, int64_t ky);
+hipError_t launch_xty(const float* X, int64_t ldx, int64_t kx, const float* Y, int64_t ldy, int64_t ky, int64_t m,
+                      double* work, double* out, hipStream_t stream);
+hipError_t launch_jacobi_topk(const double* G, int64_t w, int64_t k, double* V, double* M, double* lam,
+                              int32_t* status, hipStream_t stream);
+hipError_t launch_project_rows(const float* Y, int64_t m, int64_t w, const double* W, int64_t k, int64_t ldo,
+                               int out_f64, void* out, hipStream_t stream);
+hipError_t launch_anchor_solve(const float* Y, int64_t w, const double* M, int64_t k, const int64_t* anchors,
+                               double* W, int32_t* status, hipStream_t stream);
+hipError_t launch_gram_loss_grad(const float* A, const float* B, const double* AtA, const double* AtB, int64_t k,
+                                 int64_t m, float ca, float cb, float* dA, hipStream_t stream);
+hipError_t launch_clip_cols(const float* X, int64_t m, int64_t w, int64_t k, float* out, hipStream_t stream);
+hipError_t launch_scale(float* x, int64_t m, float a, hipStream_t stream);
+
 }  // namespace symnmf

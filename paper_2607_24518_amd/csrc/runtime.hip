@@ -10,20 +10,9 @@
 #include <string>
 #include <vector>
 
-#include "common.h"
+#include "runtime.h"
 
 using namespace symnmf;
-
-struct symnmf_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    int cus = 256;
-    int wgs_per_cu = 0;   // 0: chosen per kernel (SYMNMF_WGS_PER_CU overrides)
-    std::string err;
-    // optional HIP-event timing of every kernel a step launches
-    bool profiling = false;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;   // (kernel id, start/stop)
-};
 
 namespace {
 // kernel ids of the profiling hook
@@ -54,23 +43,6 @@ struct DevBuf {
     void* p = nullptr;
 };
 
-symnmf_status fail(symnmf_ctx* ctx, symnmf_status code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    if (ctx) ctx->err = buf;
-    return code;
-}
-
-#define HIP_OK(ctx, expr)                                                                              \
-    do {                                                                                               \
-        hipError_t e_ = (expr);                                                                        \
-        if (e_ != hipSuccess)                                                                          \
-            return fail((ctx), e_ == hipErrorOutOfMemory ? SYMNMF_ENOMEM : SYMNMF_EDEVICE, "%s: %s (%s:%d)", \
-                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                             \
-    } while (0)
 
 int64_t elem_bytes(int32_t dtype) {
     switch (dtype) {
@@ -672,8 +644,10 @@ symnmf_status symnmf_state_read(symnmf_ctx* ctx, symnmf_state* st, int32_t which
     return SYMNMF_OK;
 }
 
-symnmf_status symnmf_objective(symnmf_ctx* ctx, const symnmf_S* S, const void* H, int32_t h_is_f64, int64_t k,
-                               double* f, double* E) {
+}  // extern "C"
+
+symnmf_status objective_terms(symnmf_ctx* ctx, const symnmf_S* S, const void* H, int32_t h_is_f64, int64_t k,
+                              double* tr, double* gram_norm2) {
     if (!ctx) return SYMNMF_EINVAL;
     if (!S || !H || k < 1 || k > KMAX) return fail(ctx, SYMNMF_EINVAL, "objective: bad argument");
     HIP_OK(ctx, hipSetDevice(ctx->device));
@@ -744,7 +718,19 @@ symnmf_status symnmf_objective(symnmf_ctx* ctx, const symnmf_S* S, const void* H
     if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "objective: %s", hipGetErrorString(e));
     double gn = 0.0;
     for (double v : gram) gn += v * v;
-    const double fv = S->fro2_stored - 2.0 * d[0] + gn;
+    *tr = d[0];
+    *gram_norm2 = gn;
+    return SYMNMF_OK;
+}
+
+extern "C" {
+
+symnmf_status symnmf_objective(symnmf_ctx* ctx, const symnmf_S* S, const void* H, int32_t h_is_f64, int64_t k,
+                               double* f, double* E) {
+    double tr = 0.0, gn = 0.0;
+    const symnmf_status s = objective_terms(ctx, S, H, h_is_f64, k, &tr, &gn);
+    if (s != SYMNMF_OK) return s;
+    const double fv = S->fro2_stored - 2.0 * tr + gn;
     if (f) *f = fv;
     if (E) *E = fv / S->fro2_stored;
     if (!std::isfinite(fv)) return fail(ctx, SYMNMF_ENUMERIC, "objective: non-finite value");

@@ -38,6 +38,26 @@ def test_gram_loss_is_permutation_invariant_and_matches_explicit_form():
     assert w.gram_loss(B @ P, B)[0] == pytest.approx(0.0, abs=1e-14)
 
 
+def test_scale_free_gram_loss_is_the_best_scalar_fit():
+    g = np.random.default_rng(2)
+    A, B = g.random((40, 5)), g.random((40, 5))
+    L, dA = w.gram_cos_loss(A, B)
+    # brute force over the scalar c of c A A^T
+    cs = np.linspace(0.0, 3.0, 30001)
+    M, N = A @ A.T, B @ B.T
+    res = ((M * M).sum() * cs ** 2 - 2 * (M * N).sum() * cs + (N * N).sum()) / (N * N).sum()
+    assert L == pytest.approx(res.min(), abs=1e-9)
+    assert w.gram_cos_loss(3.7 * A, 0.2 * B)[0] == pytest.approx(L, rel=1e-12)
+    assert w.gram_cos_loss(B[:, [2, 0, 1, 4, 3]], B)[0] == pytest.approx(0.0, abs=1e-14)
+    h = 1e-6
+    for idx in [(0, 0), (7, 3), (39, 4)]:
+        Ap, Am = A.copy(), A.copy()
+        Ap[idx] += h
+        Am[idx] -= h
+        fd = (w.gram_cos_loss(Ap, B)[0] - w.gram_cos_loss(Am, B)[0]) / (2 * h)
+        assert fd == pytest.approx(dA[idx], rel=1e-6, abs=1e-12)
+
+
 def test_network_and_loss_gradients_match_finite_differences():
     g = np.random.default_rng(1)
     P = w.init_params(4, seed=3, width=8, hidden=16)
