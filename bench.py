@@ -68,9 +68,10 @@ def load_traffic(workload_key):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(X_host, k, H0, eta, rows, steps):
+def cpu_baseline(X_host, k, H0, eta, rows, steps, total_rows):
     """The FP64 oracle on a row panel of the same S: build the panel (not
-    timed), then time `steps` oracle iterations restricted to those rows."""
+    timed), then time `steps` oracle iterations restricted to those rows and
+    scale to the total_rows of one step."""
     import numpy as np
     import oracle as o
     try:
@@ -92,40 +93,42 @@ def cpu_baseline(X_host, k, H0, eta, rows, steps):
         Hr, G = o.adagrad_update(H[:rows], G, g, eta, 1e-10)
         H[:rows] = Hr
     dt = (time.time() - t0) / steps
-    per_full_step = dt * n / rows
+    per_full_step = dt * total_rows / rows
     return {"value": 1.0 / per_full_step, "unit": "iters/s", "cores": int(cores), "kind": "oracle",
             "sample": f"FP64 oracle AdaGrad iterations on rows [0,{rows}) of the n={n} |corr| S "
-                      f"({steps} timed steps, {dt:.3f} s each), scaled by n/rows; panel build "
+                      f"({steps} timed steps, {dt:.3f} s each), scaled by {total_rows}/{rows}; panel build "
                       f"{build_s:.1f} s not timed"}
 
 
-def ttt_run(ctx, S, k, eta, init, judge, f_ref, tol, max_steps, every, store, softplus=False):
-    """Iterate from init(H) (timed with the steps) for max_steps, keeping every
-    ``every``-th iterate in ``store``; afterwards find the first kept iterate
-    with (judge(H_t) - f_ref) / f_ref <= tol.  Returns a dict with the final
-    relative objective and, when reached, the iteration and the seconds from
-    the start of the initialisation (HIP events on the solver stream)."""
+def ttt_trace(ctx, S, k, params, init, max_steps, every, store):
+    """Iterate from init(H) for max_steps with every rule of the solve applied
+    at the checks (symnmf_solve_trace), keeping every ``every``-th iterate in
+    ``store``.  Returns (seconds of every kept iterate from the start of the
+    initialisation, first certified t or -1, initialisation seconds); times
+    come from HIP events on the solver stream."""
     import torch
     import paper_2607_24518_amd as sym
 
     n = S.desc.n
     nsave = max_steps // every
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nsave)]
-    ev0.record()
+    ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev_a.record()
     H = torch.empty(n, k, device=store.device)
     init(H)
-    p = sym.symnmf_params_default(eta=eta, softplus=int(softplus), max_iter=10 ** 9)
-    st = sym.symnmf_state_create(ctx, S, k, p, H)
-    for t in range(nsave * every):
-        sym.symnmf_step(ctx, S, st, want_stats=False)
-        if (t + 1) % every == 0:
-            j = (t + 1) // every - 1
-            sym.symnmf_state_read(ctx, st, 0, store[j])   # H_{t+1}
-            evs[j].record()
+    st = sym.symnmf_state_create(ctx, S, k, params, H)
+    ev_b.record()
+    ms, certified = sym.symnmf_solve_trace(ctx, S, st, nsave * every, every, store)
     torch.cuda.synchronize()
+    t_init = ev_a.elapsed_time(ev_b) / 1000.0
     del st
+    return [t_init + m / 1000.0 for m in ms], certified, t_init
+
+
+def ttt_scan(judge, store, nsave, f_ref, tol, every, times):
+    """First kept iterate with (judge(H) - f_ref) / f_ref <= tol: a coarse scan
+    every 32 kept iterates, then bisection inside the first bracket (the
+    objective of these runs decreases except for small oscillations)."""
     cache = {}
 
     def rel(j):
@@ -133,7 +136,6 @@ def ttt_run(ctx, S, k, eta, init, judge, f_ref, tol, max_steps, every, store, so
             cache[j] = (judge(store[j]) - f_ref) / f_ref
         return cache[j]
 
-    # coarse scan, then bisection inside the first bracket that meets tol
     hit = None
     prev = -1
     for j in list(range(31, nsave, 32)) + [nsave - 1]:
@@ -149,39 +151,74 @@ def ttt_run(ctx, S, k, eta, init, judge, f_ref, tol, max_steps, every, store, so
             break
         prev = j
     entry = {"final_rel": rel(nsave - 1), "steps_run": nsave * every, "rel_first_kept": rel(0)}
-    entry["times"] = [ev0.elapsed_time(e) / 1000.0 for e in evs]
     if hit is not None:
-        entry.update(iters=(hit + 1) * every, seconds=entry["times"][hit])
+        entry.update(iters=(hit + 1) * every, seconds=times[hit])
     return entry
 
 
+def ttt_run(ctx, S, k, params, init, judge, f_ref, tol, max_steps, every, store):
+    """Trace from init(H), then the time to (judge(H_t) - f_ref) / f_ref <= tol."""
+    times, certified, t_init = ttt_trace(ctx, S, k, params, init, max_steps, every, store)
+    entry = ttt_scan(judge, store, max_steps // every, f_ref, tol, every, times)
+    entry.update(init_seconds=round(t_init, 4), certified_at=certified, times=times)
+    return entry
+
+
+METHODS = {"adagrad": 0, "rmsprop": 1, "piecewise": 2, "rowsvrg": 3, "blocksvrg": 4}
+
+
+def variant_params(variant, eta_base, seed=0):
+    """Solver parameters of a variant name "<storage>[-<method>][-softplus]"."""
+    import paper_2607_24518_amd as sym
+
+    parts = variant.split("-")
+    method = next((q for q in parts[1:] if q in METHODS), "adagrad")
+    kw = dict(method=METHODS[method], eta=eta_base, softplus=int("softplus" in parts), max_iter=10 ** 9, seed=seed)
+    if method == "rmsprop":
+        kw.update(eta=0.03 * eta_base, eps=1e-8, alpha=0.99, mu=0.5)
+    if method in ("rowsvrg", "blocksvrg"):
+        kw.update(block_rows=1024, snapshot_s=10, delta=10, phi0=0.75, row_frac=0.5)
+    return sym.symnmf_params_default(**kw)
+
+
+def ttt_instance(args, dev):
+    """Returns of the time-to-tolerance workload and the S kind."""
+    import synth
+
+    if args.ttt_kind == "tpdm":
+        inst = synth.tpdm_returns(args.seed, T=args.T, n=args.n, groups=args.groups, nu=2.5, common=True,
+                                  device=dev)
+        return inst.X, 1
+    return synth.overlap_returns(args.seed, T=args.T, n=args.n, groups=args.groups, device=dev).X, 0
+
+
 def time_to_tolerance(args):
-    """Time to (f_S(H_t) - f_ref) / f_ref <= tol for several variants of the
-    same instance and initial H.
+    """Time to (f_S(H_t) - f_ref) / f_ref <= tol for several variants (storage,
+    method) of the same instance and initial H.
 
     f_S is the objective on the FP32-stored S (MFMA products, FP64 sums across
-    chunks) whatever S the variant iterates on; f_ref is the best objective of
-    a long FP32 AdaGrad reference run certified by the stop rule (or stopped at
+    chunks) whatever S the variant iterates on; f_ref is the objective of the
+    FP32 AdaGrad reference run certified by the stop rule (or stopped at
     --ttt-ref-iters).  Every variant's iterates are kept in HBM and judged
-    after its timed run; the time of iterate H_t is measured from the start of
-    its initialisation to the end of step t-1 (HIP events on the solver
-    stream).
+    after its timed run; the time of iterate H_t runs from the start of its
+    initialisation to the copy of H_t (HIP events on the solver stream), with
+    every check-time rule of the method applied.
     """
     import torch
     import paper_2607_24518_amd as sym
-    import synth
 
     dev = torch.device("cuda:0")
     n, k = args.n, args.k
-    inst = synth.overlap_returns(args.seed, T=args.T, n=n, groups=args.groups, device=dev)
+    X, kind = ttt_instance(args, dev)
     ctx = sym.symnmf_create(0)
-    stores = {"fp32": sym.symnmf_build_S(ctx, inst.X, dtype=sym.S_FP32)}
+    build = dict(kind=kind, q=0.05, lower_tail=1, fp8_panel_rows=256)
+    stores = {"fp32": sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32, **build)}
     variants = [v for v in args.ttt_variants.split(",") if v]
     for v in variants:
         dt = v.split("-")[0]
         if dt not in stores:
-            stores[dt] = sym.symnmf_build_S(ctx, inst.X, dtype=sym.DTYPES[dt], fp8_panel_rows=256)
-    del inst
+            stores[dt] = sym.symnmf_build_S(ctx, X, dtype=sym.DTYPES[dt], **build)
+    del X
     S32 = stores["fp32"]
     eta = math.sqrt(S32.desc.mean / k)
 
@@ -194,10 +231,9 @@ def time_to_tolerance(args):
     every = max(1, args.ttt_save_every)
     store = torch.empty(args.ttt_max // every, n, k, device=dev)
     for v in variants:
-        parts = v.split("-")
-        S = stores[parts[0]]
-        entry = ttt_run(ctx, S, k, eta, lambda H: sym.symnmf_init_H(ctx, S, k, 1, H), judge, f_ref, args.ttt_tol,
-                        args.ttt_max, every, store, softplus="softplus" in parts)
+        S = stores[v.split("-")[0]]
+        entry = ttt_run(ctx, S, k, variant_params(v, eta), lambda H: sym.symnmf_init_H(ctx, S, k, 1, H), judge,
+                        f_ref, args.ttt_tol, args.ttt_max, every, store)
         entry.pop("times")
         results["variants"][v] = entry
         log(f"variant {v}: {entry}")
@@ -232,14 +268,16 @@ def warm_start_study(args):
     """Learned warm start against random initialisation.
 
     Training: for every training seed the returns are generated, S (FP32) is
-    built, solved from the counter-RNG init with the paper's stop rule, and the
-    pair (canonical sketch coordinates, certified H) is kept on the device;
+    built and solved from the network-free warm start (stop rule or
+    --warm-solve-iters), and the pair (canonical sketch coordinates, solved H)
+    is kept on the device;
     the network is then trained with the scale-free Gram loss.
     Evaluation on held-out seeds (and optionally on the n = 100000 |corr|
     workload): time to relative objective tolerance from (a) the random init,
     (b) the network-free coordinates, (c) the network, each timed from the
     start of its initialisation (sketch, coordinates and network included);
-    f_ref is the random-init reference solve certified by the stop rule.  A
+    f_ref is the objective of the random-init run's certified iterate (or of
+    its last iterate when the stop rule does not certify one).  A
     warm run that has not reached the tolerance within twice the random run's
     iterations falls back to the random run, and its time counts both.
     """
@@ -278,8 +316,10 @@ def warm_start_study(args):
         S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
         del X
         eta = math.sqrt(S.desc.mean / k)
+        # target: the solver's factorization from the network-free warm start
+        # (it reaches lower objectives than random initialisation)
         H0 = torch.empty(n, k, device=dev)
-        sym.symnmf_init_H(ctx, S, k, seed, H0)
+        sym.symnmf_warm_start(ctx, S, None, W, k, WARM_OMEGA_SEED, H0)
         st = sym.symnmf_state_create(ctx, S, k, sym.symnmf_params_default(eta=eta, max_iter=args.warm_solve_iters),
                                      H0)
         Hs = torch.empty(n, k, device=dev)
@@ -319,45 +359,47 @@ def warm_start_study(args):
     torch.cuda.empty_cache()
 
     # 3. evaluation
-    def evaluate(S, k_eval, model, label, seed, max_steps):
+    def evaluate(S, k_eval, model, label, seed, rand_steps, warm_steps):
+        """random init run first (it is also the reference: f_ref is its
+        certified iterate, or its last one), then the two warm starts."""
         nn = S.desc.n
         eta = math.sqrt(S.desc.mean / k_eval)
+        params = variant_params("fp32", eta)
 
         def judge(H):
             return sym.symnmf_objective(ctx, S, H, k_eval)[0]
 
-        f_ref, rs, conv = reference_solve(ctx, S, k_eval, eta, seed, args.warm_ref_iters)
         every = 2
-        store = torch.empty(max_steps // every, nn, k_eval, device=dev)
+        store = torch.empty(rand_steps // every, nn, k_eval, device=dev)
+        times, cert, t_init = ttt_trace(ctx, S, k_eval, params, lambda H: sym.symnmf_init_H(ctx, S, k_eval, seed, H),
+                                        rand_steps, every, store)
+        ref_slot = (cert + 1) // every - 1 if cert >= 0 else rand_steps // every - 1
+        f_ref = judge(store[ref_slot])
+        res = {"f_ref": f_ref, "ref_iters": (ref_slot + 1) * every, "ref_certified": cert >= 0}
+        res["random"] = ttt_scan(judge, store, rand_steps // every, f_ref, args.ttt_tol, every, times)
         inits = {
-            "random": lambda H: sym.symnmf_init_H(ctx, S, k_eval, seed, H),
             "coords": lambda H: sym.symnmf_warm_start(ctx, S, None, W, k_eval, WARM_OMEGA_SEED, H),
             "mlp": lambda H: sym.symnmf_warm_start(ctx, S, model, W, k_eval, WARM_OMEGA_SEED, H),
         }
-        res = {"f_ref": f_ref, "ref_iters": int(rs.t), "ref_certified": bool(conv)}
+        r_it, r_s = res["random"].get("iters"), res["random"].get("seconds")
         for name, init in inits.items():
-            e = ttt_run(ctx, S, k_eval, eta, init, judge, f_ref, args.ttt_tol, max_steps, every, store)
-            times = e.pop("times")
+            wt, wcert, w_init = ttt_trace(ctx, S, k_eval, params, init, warm_steps, every, store)
+            e = ttt_scan(judge, store, warm_steps // every, f_ref, args.ttt_tol, every, wt)
+            e["init_seconds"] = round(w_init, 4)
+            if r_it is not None:
+                if e.get("iters") is None or e["iters"] > 2 * r_it:
+                    # fallback: the warm run is abandoned after 2x the random
+                    # iterations (or its cap) and the random run is started
+                    idx = min(2 * r_it // every, len(wt)) - 1
+                    e["fallback"] = True
+                    e["seconds_with_fallback"] = wt[idx] + r_s
+                else:
+                    e["fallback"] = False
+                    e["seconds_with_fallback"] = e["seconds"]
+                e["speedup_vs_random"] = round(r_s / e["seconds_with_fallback"], 3)
             res[name] = e
         del store
-        r_it, r_s = res["random"].get("iters"), res["random"].get("seconds")
-        for name in ("coords", "mlp"):
-            e = res[name]
-            if r_it is None:
-                continue
-            if e.get("iters") is None or e["iters"] > 2 * r_it:
-                # fallback: the warm run is abandoned after 2x the random iterations
-                # and the random run is started
-                idx = min(2 * r_it // every, len(times)) - 1
-                e["fallback"] = True
-                e["seconds_with_fallback"] = times[idx] + r_s
-            else:
-                e["fallback"] = False
-                e["seconds_with_fallback"] = e["seconds"]
-            e["speedup_vs_random"] = round(r_s / e["seconds_with_fallback"], 3)
-        log(f"{label}: " + json.dumps({kk: (vv if not isinstance(vv, dict) else
-                                             {a: b for a, b in vv.items() if a != 'times'})
-                                        for kk, vv in res.items()}))
+        log(f"{label}: " + json.dumps(res))
         return res
 
     held = []
@@ -365,7 +407,7 @@ def warm_start_study(args):
         X = returns(seed, n)
         S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
         del X
-        held.append(evaluate(S, k, net, f"held-out seed {seed}", seed, args.warm_max))
+        held.append(evaluate(S, k, net, f"held-out seed {seed}", seed, args.warm_max, args.warm_warm_max))
         del S
     out["heldout"] = held
     for name in ("coords", "mlp"):
@@ -378,20 +420,24 @@ def warm_start_study(args):
         X = synth.overlap_returns(0, T=2500, n=100000, groups=32, device=dev).X
         S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
         del X
-        out["c3_abs_corr_n100000"] = evaluate(S, k, net, "n=100000 |corr|", 1, args.warm_c3_max)
+        out["c3_abs_corr_n100000"] = evaluate(S, k, net, "n=100000 |corr|", 1, args.warm_c3_max, args.warm_c3_max)
     return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--T", type=int, default=2500)
     ap.add_argument("--groups", type=int, default=32)
+    ap.add_argument("--family", default="overlap", choices=["overlap", "panel"],
+                    help="returns generator: overlapping groups (n = 1e5 workload) or the column-block panel")
+    ap.add_argument("--rows", type=int, default=0, help="row-panel share of S (0: all n rows)")
+    ap.add_argument("--no-read-probe", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=5)
@@ -400,6 +446,7 @@ def main():
                     help="only run the library's plain copy kernel over this many GiB (counter calibration)")
     ap.add_argument("--ttt", action="store_true", help="time-to-tolerance comparison instead of the step rate")
     ap.add_argument("--ttt-variants", default="fp32,bf16,fp8,fp32-softplus")
+    ap.add_argument("--ttt-kind", default="abs_corr", choices=["abs_corr", "tpdm"])
     ap.add_argument("--ttt-tol", type=float, default=1e-4)
     ap.add_argument("--ttt-max", type=int, default=6000)
     ap.add_argument("--ttt-save-every", type=int, default=2)
@@ -414,12 +461,13 @@ def main():
     ap.add_argument("--warm-seed0", type=int, default=1000)
     ap.add_argument("--warm-heldout", type=int, default=20)
     ap.add_argument("--warm-heldout0", type=int, default=2000)
-    ap.add_argument("--warm-solve-iters", type=int, default=4000)
+    ap.add_argument("--warm-solve-iters", type=int, default=1500)
     ap.add_argument("--warm-ref-iters", type=int, default=8000)
     ap.add_argument("--warm-epochs", type=int, default=40)
     ap.add_argument("--warm-lr", type=float, default=1e-3)
     ap.add_argument("--warm-wd", type=float, default=1e-4)
-    ap.add_argument("--warm-max", type=int, default=4000)
+    ap.add_argument("--warm-max", type=int, default=8000, help="steps of the random-init (reference) run")
+    ap.add_argument("--warm-warm-max", type=int, default=3000, help="steps of each warm-started run")
     ap.add_argument("--warm-c3", action="store_true", help="also evaluate on the n=100000 |corr| workload")
     ap.add_argument("--warm-c3-max", type=int, default=6000)
     args = ap.parse_args()
@@ -439,7 +487,8 @@ def main():
                 v["speedup_vs_fp32"] = round(base / v["seconds"], 3)
         print(json.dumps({"metric": "time to relative objective tolerance", "unit": "s",
                           "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
-                          "config": {"workload": f"abs_corr_n{args.n}_k{args.k}_T{args.T}", "method": "AdaGrad"},
+                          "config": {"workload": f"{args.ttt_kind}_n{args.n}_k{args.k}_T{args.T}",
+                                     "reference_method": "AdaGrad"},
                           **res}), flush=True)
         return
 
@@ -468,16 +517,19 @@ def main():
 
     dev = torch.device("cuda:0")
     n, k = args.n, args.k
-    log(f"generating returns T={args.T} n={n} groups={args.groups}")
-    inst = synth.overlap_returns(args.seed, T=args.T, n=n, groups=args.groups, device=dev)
-    X = inst.X
+    rows = args.rows if args.rows > 0 else n
+    log(f"generating returns T={args.T} n={n} groups={args.groups} ({args.family})")
+    if args.family == "panel":
+        X = synth.panel_returns(args.seed, T=args.T, n=n, groups=args.groups, device=dev).X
+    else:
+        X = synth.overlap_returns(args.seed, T=args.T, n=n, groups=args.groups, device=dev).X
     ctx = sym.symnmf_create(0)
     dt = sym.DTYPES[args.dtype]
     torch.cuda.synchronize()
     t0 = time.time()
-    S = sym.symnmf_build_S(ctx, X, kind=sym.ABS_CORR, dtype=dt, fp8_panel_rows=256)
+    S = sym.symnmf_build_S(ctx, X, kind=sym.ABS_CORR, dtype=dt, rows=rows, fp8_panel_rows=256)
     build_s = time.time() - t0
-    log(f"S built in {build_s:.2f} s (fro2={S.desc.fro2:.6e} mean={S.desc.mean:.6f})")
+    log(f"S built in {build_s:.2f} s (rows={rows} fro2={S.desc.fro2:.6e} mean={S.desc.mean:.6f})")
     H0 = torch.empty(n, k, device=dev)
     sym.symnmf_init_H(ctx, S, k, 1, H0)
     eta = math.sqrt(S.desc.mean / k)
@@ -504,22 +556,40 @@ def main():
     sbytes = {"fp32": 4, "bf16": 2, "fp8": 1}[args.dtype]
     s_ms, s_cnt = prof["stream"]
     s_avg = s_ms / max(s_cnt, 1)
-    alg = stream_bytes(n, n, k, sbytes)
+    alg = stream_bytes(rows, n, k, sbytes)
     achieved = alg / (s_avg * 1e-3) / 1e9
-    workload = f"abs_corr_n{n}_k{k}_T{args.T}_{args.dtype}"
+    workload = (f"abs_corr_n{n}_k{k}_T{args.T}_{args.dtype}" if rows == n else
+                f"abs_corr_panel_rows{rows}_n{n}_k{k}_T{args.T}_{args.dtype}")
     traffic = load_traffic(workload)
     roof = {"kernel": "stream_mfma_" + ("f32" if args.dtype == "fp32" else ("lp_bf16" if args.dtype == "bf16" else "lp_fp8")),
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "avg_launch_ms": round(s_avg, 4), "alg_bytes_per_launch": alg}
-    step_gbs = step_bytes(n, n, k, sbytes) / (ms_step * 1e-3) / 1e9
+    step_gbs = step_bytes(rows, n, k, sbytes) / (ms_step * 1e-3) / 1e9
+    read_ceiling = None
+    if not args.no_read_probe:
+        nbytes = 8 << 30
+        src = torch.zeros(nbytes // 4, dtype=torch.float32, device=dev)
+        sink = torch.empty(1 << 16, dtype=torch.int32, device=dev)
+        sym.symnmf_probe_read(ctx, src, sink, nbytes)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            sym.symnmf_probe_read(ctx, src, sink, nbytes)
+        ev1.record()
+        torch.cuda.synchronize()
+        read_ceiling = round(nbytes * 5 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 1)
+        del src, sink
+        roof["read_ceiling_gbs"] = read_ceiling
+        roof["frac_of_read_ceiling"] = round(achieved / read_ceiling, 4)
+        log(f"plain read probe: {read_ceiling} GB/s")
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         Xh = X.double().cpu().numpy()
         H0h = H0.double().cpu().numpy()
-        cpu = cpu_baseline(Xh, k, H0h, eta, args.cpu_rows, args.cpu_steps)
+        cpu = cpu_baseline(Xh, k, H0h, eta, min(args.cpu_rows, rows), args.cpu_steps, rows)
         log(f"cpu baseline {cpu}")
 
     out = {
@@ -535,8 +605,8 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE_NAMES[args.dtype],
         "data": "synthetic",
-        "config": {"workload": workload, "kind": "abs_corr", "n": n, "k": k, "T": args.T,
-                   "groups": args.groups, "market_loading": 0.4, "S_storage": args.dtype,
+        "config": {"workload": workload, "kind": "abs_corr", "family": args.family, "n": n, "rows": rows, "k": k,
+                   "T": args.T, "groups": args.groups, "market_loading": 0.4, "S_storage": args.dtype,
                    "method": "projected AdaGrad", "eta": eta},
         "hbm_gb_s": round(step_gbs, 1),
         "build_S_s": round(build_s, 3),

@@ -241,6 +241,28 @@ symnmf_status symnmf_solve_to_tol(symnmf_ctx* ctx, const symnmf_S* S, symnmf_sta
                                   double f_target, double rel_tol, symnmf_stats* final_stats,
                                   void* H_out);
 
+/* Trace of a solve: ``steps`` iterations with every rule of symnmf_solve_to_tol
+ * applied at the checks (stop-rule statistics, Piecewise resets, Block-SVRG
+ * growth) but without stopping when the stop rule certifies an iterate.
+ * After every save_every-th iteration the current iterate is copied to the
+ * next slot of H_save (device, slots x n x k of the state's precision,
+ * slots >= steps / save_every) and ms_out[slot] (host) receives the time from
+ * the start of the call to that copy, from HIP events on the context stream.
+ * *certified_at (may be NULL) receives the first t the stop rule certified,
+ * or -1.  Synchronises at every check.  ENUMERIC on a non-finite gradient. */
+symnmf_status symnmf_solve_trace(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st, int64_t steps,
+                                 int64_t save_every, void* H_save, int64_t slots, double* ms_out,
+                                 int64_t* certified_at);
+
+/* Subspace error of two factors (solutions are defined up to column
+ * permutation and scaling): ||P_A - P_B||_F / sqrt(2k) with P_X the orthogonal
+ * projector onto the column span of X, from ||P_A - P_B||_F^2 =
+ * 2k - 2 ||Q_A^T Q_B||_F^2 and Q_X = X (X^T X)^-1/2; only k x k FP64 work
+ * after the products A^T A, B^T B, A^T B.  A, B: device n x k float32.
+ * ENUMERIC when a factor is rank deficient.  Synchronises. */
+symnmf_status symnmf_subspace_error(symnmf_ctx* ctx, const float* A, const float* B, int64_t n, int64_t k,
+                                    double* out);
+
 /* Lower median (element floor((m-1)/2) in sorted order) of g_i^2 over a device
  * float32 array of m values, by radix selection on the bit patterns.
  * Synchronises; the result goes to *out. */
@@ -261,6 +283,13 @@ void symnmf_sample_blocks(uint64_t seed, int64_t t, int32_t stream, int64_t nblo
  * (device): a kernel of known traffic, for calibrating hardware byte counters
  * against the S.H stream.  Asynchronous. */
 symnmf_status symnmf_probe_copy(symnmf_ctx* ctx, const void* src, void* dst, int64_t bytes);
+
+/* Plain read of ``bytes`` (a multiple of 16) from src (device) by 2048
+ * persistent work-groups (fewer when sink_words / 4 is smaller) with 16-byte
+ * nontemporal loads: the read-bandwidth ceiling the S.H stream competes
+ * against.  sink: device, sink_words 32-bit words (>= 4) receiving one folded
+ * word per wave.  Asynchronous. */
+symnmf_status symnmf_probe_read(symnmf_ctx* ctx, const void* src, void* sink, int64_t sink_words, int64_t bytes);
 
 /* HIP-event timing of the kernels a step launches, on the context's stream.
  * Reading (ms_out / launches_out non-NULL, 5 entries each: 0 = S.H stream,

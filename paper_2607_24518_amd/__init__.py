@@ -92,12 +92,16 @@ SIGNATURES = {
                                  ctypes.POINTER(c_dbl)]),
     "symnmf_solve_to_tol": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_dbl, c_dbl,
                                     ctypes.POINTER(symnmf_stats), c_vp]),
+    "symnmf_solve_trace": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, c_i64, c_vp, c_i64,
+                                   ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
+    "symnmf_subspace_error": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_i64, ctypes.POINTER(c_dbl)]),
     "symnmf_median_sq": (c_i32, [c_vp, c_vp, c_i64, ctypes.POINTER(ctypes.c_float)]),
     "symnmf_piecewise_reset": (c_i32, [c_vp, c_vp, c_dbl, ctypes.POINTER(ctypes.c_float)]),
     "symnmf_sample_blocks": (None, [c_u64, c_i64, c_i32, c_i64, c_i64, ctypes.POINTER(c_i32)]),
     "symnmf_selfcheck_fp8": (c_i32, [c_vp]),
     "symnmf_profile": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
     "symnmf_probe_copy": (c_i32, [c_vp, c_vp, c_vp, c_i64]),
+    "symnmf_probe_read": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_i64]),
     "symnmf_mlp_param_count": (c_i64, [c_i64, c_i64, c_i64]),
     "symnmf_mlp_init": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_u64, c_vp]),
     "symnmf_mlp_create": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_vp, ctypes.POINTER(c_vp)]),
@@ -304,6 +308,24 @@ def symnmf_solve_to_tol(ctx, S: Matrix, st: State, f_target: float = 0.0, rel_to
     return out, code == OK
 
 
+def symnmf_solve_trace(ctx, S: Matrix, st: State, steps: int, save_every: int, H_save):
+    """H_save: device tensor (slots, n, k).  Returns (ms per kept iterate, first
+    certified t or -1)."""
+    nsave = steps // save_every
+    ms = (c_dbl * max(nsave, 1))()
+    cert = c_i64()
+    _check(ctx, lib().symnmf_solve_trace(ctx, ctypes.byref(S.desc), st.handle, steps, save_every, _ptr(H_save),
+                                         H_save.shape[0], ms, ctypes.byref(cert)))
+    return [ms[i] for i in range(nsave)], cert.value
+
+
+def symnmf_subspace_error(ctx, A, B):
+    out = c_dbl()
+    n, k = A.shape
+    _check(ctx, lib().symnmf_subspace_error(ctx, _ptr(A), _ptr(B), n, k, ctypes.byref(out)))
+    return out.value
+
+
 def symnmf_median_sq(ctx, g, m=None):
     out = ctypes.c_float()
     m = g.numel() if m is None else m
@@ -337,6 +359,12 @@ def symnmf_profile(ctx, enable: bool, read: bool = True):
     cnt = (c_i64 * len(PROFILE_KERNELS))()
     _check(ctx, lib().symnmf_profile(ctx, int(enable), ms, cnt))
     return {name: (ms[i], cnt[i]) for i, name in enumerate(PROFILE_KERNELS)}
+
+
+def symnmf_probe_read(ctx, src, sink, nbytes=None):
+    """sink: device int32 tensor (>= 4 words)."""
+    nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
+    _check(ctx, lib().symnmf_probe_read(ctx, _ptr(src), _ptr(sink), sink.numel(), nbytes))
 
 
 def symnmf_probe_copy(ctx, src, dst, nbytes=None):

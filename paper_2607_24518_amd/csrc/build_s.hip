@@ -234,54 +234,17 @@ hipError_t launch_tpdm_omega(const float* X, int64_t T, int64_t n, int lower, vo
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// SYRK: S[i][j] = |sum_t Z[t][row0+i] Z[t][j]| for the panel rows, 128 x 128
-// output tile per work-group (2 x 2 waves of 64 x 64), K in steps of 16.
-// MODE 0 only finds the largest off-diagonal |S| of every FP8 scale panel;
-// MODE 1 stores and sums.
-// ---------------------------------------------------------------------------
-template <int MODE>
-__global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ Z, int64_t K, int64_t ldz, BuildOut o,
-                                                   double* __restrict__ wg_sums, uint32_t* __restrict__ panel_max) {
-    __shared__ float As[16][128 + 4];
-    __shared__ float Bs[16][128 + 4];
-    __shared__ uint32_t rowmax[128];
-    __shared__ double red[3][4];
-    const int64_t i0 = (int64_t)blockIdx.y * 128, j0 = (int64_t)blockIdx.x * 128;
+// Epilogue of the S-building GEMMs: |.|, unit diagonal, storage rounding into
+// the tiled layout, FP64 sums per work-group (MODE 1), or the FP8 panel
+// maxima (MODE 0).  acc[a][b][v] holds element (64 wr + 16 a + 4 lg + v,
+// 64 wc + 16 b + lr) of the work-group's 128 x 128 tile (the D layout of the
+// 16 x 16 MFMAs).
+template <int MODE, int DT>
+__device__ inline void syrk_epilogue(const floatx4 (&acc)[4][4], int64_t i0, int64_t j0, const BuildOut& o,
+                                     double* __restrict__ wg_sums, uint32_t* __restrict__ panel_max,
+                                     uint32_t* rowmax, double (*red)[4]) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1, lr = lane & 15, lg = lane >> 4;
-    floatx4 acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const float* Za = Z + o.row0 + i0;
-    const float* Zb = Z + j0;
-    for (int64_t k0 = 0; k0 < K; k0 += 16) {
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int f = t + 256 * q;
-            const int kk = f >> 7, ii = f & 127;
-            As[kk][ii] = Za[(k0 + kk) * ldz + ii];
-            Bs[kk][ii] = Zb[(k0 + kk) * ldz + ii];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int kk = 4 * s + lg;
-            float av[4], bv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = As[kk][64 * wr + 16 * a + lr];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][64 * wc + 16 * b + lr];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
-        }
-    }
     if (MODE == 0) {
         if (t < 128) rowmax[t] = 0;
         __syncthreads();
@@ -305,13 +268,13 @@ __global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ Z, 
                     if (valid && !diag) atomicMax(&rowmax[li], __builtin_bit_cast(uint32_t, val));
                     continue;
                 }
-                const int E = o.dtype == SYMNMF_S_FP32 ? 4 : (o.dtype == SYMNMF_S_BF16 ? 8 : 16);
+                constexpr int E = DT == SYMNMF_S_FP32 ? 4 : (DT == SYMNMF_S_BF16 ? 8 : 16);
                 const int64_t off = tiled_offset(i, j, o.ld / KC, E);
                 double stored;
-                if (o.dtype == SYMNMF_S_FP32) {
+                if constexpr (DT == SYMNMF_S_FP32) {
                     ((float*)o.data)[off] = val;
                     stored = val;
-                } else if (o.dtype == SYMNMF_S_BF16) {
+                } else if constexpr (DT == SYMNMF_S_BF16) {
                     const uint16_t bits = f32_to_bf16_bits(val);
                     ((uint16_t*)o.data)[off] = bits;
                     stored = bf16_bits_to_f32(bits);
@@ -353,6 +316,159 @@ __global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ Z, 
         const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
         wg_sums[wg * 3 + t] = red[t][0] + red[t][1] + red[t][2] + red[t][3];
     }
+}
+
+// ---------------------------------------------------------------------------
+// SYRK: S[i][j] = |sum_t Z[t][row0+i] Z[t][j]| for the panel rows, 128 x 128
+// output tile per work-group (2 x 2 waves of 64 x 64), K in steps of 16.
+// MODE 0 only finds the largest off-diagonal |S| of every FP8 scale panel;
+// MODE 1 stores and sums.
+// ---------------------------------------------------------------------------
+template <int MODE, int DT>
+__global__ __launch_bounds__(256, 2) void syrk_kernel(const float* __restrict__ Z, int64_t K, int64_t ldz, BuildOut o,
+                                                   double* __restrict__ wg_sums, uint32_t* __restrict__ panel_max) {
+    __shared__ float As[2][16][128 + 4];
+    __shared__ float Bs[2][16][128 + 4];
+    __shared__ uint32_t rowmax[128];
+    __shared__ double red[3][4];
+    const int64_t i0 = (int64_t)blockIdx.y * 128, j0 = (int64_t)blockIdx.x * 128;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wr = wv >> 1, wc = wv & 1, lr = lane & 15, lg = lane >> 4;
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float* Za = Z + o.row0 + i0;
+    const float* Zb = Z + j0;
+    // the next K slab is loaded into registers while the current one is
+    // multiplied; LDS is double buffered, so one barrier per slab suffices
+    float ra[8], rb[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int f = t + 256 * q;
+        const int kk = f >> 7, ii = f & 127;
+        ra[q] = Za[kk * ldz + ii];
+        rb[q] = Zb[kk * ldz + ii];
+    }
+    for (int64_t k0 = 0; k0 < K; k0 += 16) {
+        const int buf = (int)((k0 >> 4) & 1);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int f = t + 256 * q;
+            const int kk = f >> 7, ii = f & 127;
+            As[buf][kk][ii] = ra[q];
+            Bs[buf][kk][ii] = rb[q];
+        }
+        __syncthreads();
+        if (k0 + 16 < K) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int f = t + 256 * q;
+                const int kk = f >> 7, ii = f & 127;
+                ra[q] = Za[(k0 + 16 + kk) * ldz + ii];
+                rb[q] = Zb[(k0 + 16 + kk) * ldz + ii];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kk = 4 * s + lg;
+            float av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[buf][kk][64 * wr + 16 * a + lr];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk][64 * wc + 16 * b + lr];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    syrk_epilogue<MODE, DT>(acc, i0, j0, o, wg_sums, panel_max, rowmax, red);
+}
+
+// ---------------------------------------------------------------------------
+// Split-precision SYRK on the bf16 matrix cores (Henry, Tang & Heinecke 2019:
+// a float is the sum of bf16 "planes" z = h + m + l, h = bf16(z),
+// m = bf16(z - h), l = bf16(z - h - m); products of planes are exact in the
+// FP32 accumulator).  NPL = 3 keeps the six products of order >= 2^-16
+// (hh, hm, mh, hl, lh, mm), about FP32 accuracy, for FP32 storage; NPL = 2
+// keeps hh, hm, mh (relative error ~2^-16) for BF16 and FP8 storage, whose
+// rounding (2^-9 and coarser) dominates.
+// The planes are stored per column with the samples contiguous,
+// P[p][c][kk] (Kp = samples rounded up to 32, zero padded), so every lane of
+// v_mfma_f32_16x16x32_bf16 loads its 8 consecutive samples as one 16-byte
+// vector straight from memory: A[r][8g..8g+7] of row r = lane % 16 and
+// g = lane / 16, B the same for the columns.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void split_planes_kernel(const float* __restrict__ Z, int64_t K, int64_t ldz,
+                                                           int64_t Kp, int npl, uint16_t* __restrict__ P) {
+    __shared__ float tile[32][64 + 1];
+    const int64_t c0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * 32;
+    const int t = threadIdx.x;
+    for (int f = t; f < 32 * 64; f += 256) {
+        const int kk = f >> 6, c = f & 63;
+        tile[kk][c] = k0 + kk < K ? Z[(k0 + kk) * ldz + c0 + c] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t plane = ldz * Kp;
+    for (int f = t; f < 32 * 64; f += 256) {
+        const int c = f >> 5, kk = f & 31;
+        const float x = tile[kk][c];
+        const uint16_t h = f32_to_bf16_bits(x);
+        const float r1 = x - bf16_bits_to_f32(h);
+        const uint16_t m = f32_to_bf16_bits(r1);
+        const int64_t o = (c0 + c) * Kp + k0 + kk;
+        P[o] = h;
+        P[plane + o] = m;
+        if (npl == 3) P[2 * plane + o] = f32_to_bf16_bits(r1 - bf16_bits_to_f32(m));
+    }
+}
+
+template <int NPL, int MODE, int DT>
+__global__ __launch_bounds__(256, 2) void syrk_split_kernel(const uint16_t* __restrict__ P, int64_t Kp, int64_t ldz,
+                                                            BuildOut o, double* __restrict__ wg_sums,
+                                                            uint32_t* __restrict__ panel_max) {
+    __shared__ uint32_t rowmax[128];
+    __shared__ double red[3][4];
+    const int64_t i0 = (int64_t)blockIdx.y * 128, j0 = (int64_t)blockIdx.x * 128;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wr = wv >> 1, wc = wv & 1, lr = lane & 15, lg = lane >> 4;
+    const int64_t plane = ldz * Kp;
+    // row r of A / B fragment a: column (instrument) index, samples from 8 lg
+    const uint16_t* pa = P + (o.row0 + i0 + 64 * wr + lr) * Kp + 8 * lg;
+    const uint16_t* pb = P + (j0 + 64 * wc + lr) * Kp + 8 * lg;
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = 0; k0 < Kp; k0 += 32) {
+        bf16x8 av[NPL][4], bv[NPL][4];
+#pragma unroll
+        for (int p = 0; p < NPL; ++p)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                av[p][a] = *(const bf16x8*)(pa + p * plane + (int64_t)16 * a * Kp + k0);
+                bv[p][a] = *(const bf16x8*)(pb + p * plane + (int64_t)16 * a * Kp + k0);
+            }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                // small terms first
+                if constexpr (NPL == 3) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1][a], bv[1][b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[NPL - 1][a], bv[0][b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][a], bv[NPL - 1][b], acc[a][b], 0, 0, 0);
+                }
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1][a], bv[0][b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][a], bv[1][b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][a], bv[0][b], acc[a][b], 0, 0, 0);
+            }
+    }
+    syrk_epilogue<MODE, DT>(acc, i0, j0, o, wg_sums, panel_max, rowmax, red);
 }
 
 // FP64 S (parity runs): plain FP64 FMAs, 64 x 64 tile per work-group, each
@@ -453,11 +569,49 @@ hipError_t launch_syrk_store(const void* Zv, int z_f64, int64_t K, int64_t ldz, 
     double* wg_sums = sums + 4;
     if (o.dtype == SYMNMF_S_FP8) {
         const int64_t panels = (o.rows + o.panel_rows - 1) / o.panel_rows;
-        hipLaunchKernelGGL(syrk_kernel<0>, grid, block, 0, stream, Z, K, ldz, o, wg_sums, panel_max);
+        hipLaunchKernelGGL((syrk_kernel<0, SYMNMF_S_FP8>), grid, block, 0, stream, Z, K, ldz, o, wg_sums, panel_max);
         hipLaunchKernelGGL(fp8_scales_kernel, dim3((panels + 255) / 256), dim3(256), 0, stream,
                            (const uint32_t*)panel_max, panels, o.scale);
+        hipLaunchKernelGGL((syrk_kernel<1, SYMNMF_S_FP8>), grid, block, 0, stream, Z, K, ldz, o, wg_sums, panel_max);
+    } else if (o.dtype == SYMNMF_S_BF16) {
+        hipLaunchKernelGGL((syrk_kernel<1, SYMNMF_S_BF16>), grid, block, 0, stream, Z, K, ldz, o, wg_sums, panel_max);
+    } else {
+        hipLaunchKernelGGL((syrk_kernel<1, SYMNMF_S_FP32>), grid, block, 0, stream, Z, K, ldz, o, wg_sums, panel_max);
     }
-    hipLaunchKernelGGL(syrk_kernel<1>, grid, block, 0, stream, Z, K, ldz, o, wg_sums, panel_max);
+    return finish_sums(wg_sums, wgs, sums, stream);
+}
+
+int64_t syrk_split_planes(int32_t dtype) { return dtype == SYMNMF_S_FP32 ? 3 : 2; }
+
+int64_t syrk_split_ws_bytes(int64_t K, int64_t ldz, int32_t dtype) {
+    return syrk_split_planes(dtype) * ldz * round_up(K, 32) * 2;
+}
+
+hipError_t launch_syrk_split_store(const float* Z, int64_t K, int64_t ldz, const BuildOut& o, double* sums,
+                                   uint32_t* panel_max, void* ws, hipStream_t stream) {
+    if (o.dtype == SYMNMF_S_FP64) return hipErrorInvalidValue;
+    const int npl = (int)syrk_split_planes(o.dtype);
+    const int64_t Kp = round_up(K, 32);
+    uint16_t* P = (uint16_t*)ws;
+    hipLaunchKernelGGL(split_planes_kernel, dim3(ldz / 64, Kp / 32), dim3(256), 0, stream, Z, K, ldz, Kp, npl, P);
+    dim3 grid(o.ld / 128, o.rows_pad / 128), block(256);
+    const int64_t wgs = (int64_t)grid.x * grid.y;
+    double* wg_sums = sums + 4;
+    if (o.dtype == SYMNMF_S_FP8) {
+        const int64_t panels = (o.rows + o.panel_rows - 1) / o.panel_rows;
+        hipLaunchKernelGGL((syrk_split_kernel<2, 0, SYMNMF_S_FP8>), grid, block, 0, stream, (const uint16_t*)P, Kp,
+                           ldz, o, wg_sums, panel_max);
+        hipLaunchKernelGGL(fp8_scales_kernel, dim3((panels + 255) / 256), dim3(256), 0, stream,
+                           (const uint32_t*)panel_max, panels, o.scale);
+        hipLaunchKernelGGL((syrk_split_kernel<2, 1, SYMNMF_S_FP8>), grid, block, 0, stream, (const uint16_t*)P, Kp,
+                           ldz, o, wg_sums, panel_max);
+    } else if (o.dtype == SYMNMF_S_BF16) {
+        hipLaunchKernelGGL((syrk_split_kernel<2, 1, SYMNMF_S_BF16>), grid, block, 0, stream, (const uint16_t*)P, Kp,
+                           ldz, o, wg_sums, panel_max);
+    } else {
+        hipLaunchKernelGGL((syrk_split_kernel<3, 1, SYMNMF_S_FP32>), grid, block, 0, stream, (const uint16_t*)P, Kp,
+                           ldz, o, wg_sums, panel_max);
+    }
     return finish_sums(wg_sums, wgs, sums, stream);
 }
 

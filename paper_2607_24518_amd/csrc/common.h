@@ -202,6 +202,9 @@ int64_t h_image_words(int32_t stype, int64_t k, int64_t n_chunks);
 hipError_t launch_h_image(const float* H, int32_t stype, int64_t k, int64_t n_chunks, float wt, uint32_t* img,
                           hipStream_t stream);
 hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t stream);
+// plain read of bytes (multiple of 16); sink: sink_words words (>= 4), one per wave
+hipError_t launch_read_probe(const void* src, int64_t bytes, uint32_t* sink, int64_t sink_words,
+                             hipStream_t stream);
 // Objective pass on the MFMA path: FP32 sums within each 256-column chunk,
 // FP64 across chunks; FP64 partials.  img: chunk images of FP32 H.
 int stream_acc64_supported(int32_t stype, int64_t k);
@@ -303,6 +306,12 @@ int64_t tpdm_work_bytes(int64_t T, int64_t n);
 int64_t syrk_sum_words(const BuildOut& o);
 hipError_t launch_syrk_store(const void* Z, int z_f64, int64_t K, int64_t ldz, const BuildOut& o, double* sums,
                              uint32_t* panel_max, hipStream_t stream);
+// The same product on the bf16 matrix cores with Z split into bf16 planes
+// (3 planes / 6 products for FP32 storage, 2 / 3 for BF16 and FP8); ws holds
+// the planes (syrk_split_ws_bytes).  Z: Kpad x ldz FP32 with K valid rows.
+int64_t syrk_split_ws_bytes(int64_t K, int64_t ldz, int32_t dtype);
+hipError_t launch_syrk_split_store(const float* Z, int64_t K, int64_t ldz, const BuildOut& o, double* sums,
+                                   uint32_t* panel_max, void* ws, hipStream_t stream);
 // sums: 4 + 3 * rows_pad words
 hipError_t launch_store_dense(const void* src, int src_f64, const BuildOut& o, double* sums,
                               uint32_t* panel_max, hipStream_t stream);
@@ -343,5 +352,7 @@ hipError_t launch_gram_loss_grad(const float* A, const float* B, const double* A
                                  int64_t m, float ca, float cb, float* dA, hipStream_t stream);
 hipError_t launch_clip_cols(const float* X, int64_t m, int64_t w, int64_t k, float* out, hipStream_t stream);
 hipError_t launch_scale(float* x, int64_t m, float a, hipStream_t stream);
+hipError_t launch_span_overlap(const double* MA, const double* AtB, const double* MB, int64_t k, double* out,
+                               hipStream_t stream);
 
 }  // namespace symnmf

@@ -39,11 +39,6 @@ namespace {
 
 constexpr int HCAP = 128;   // ring of per-step device statistics
 
-struct DevBuf {
-    void* p = nullptr;
-};
-
-
 int64_t elem_bytes(int32_t dtype) {
     switch (dtype) {
         case SYMNMF_S_FP32: return 4;
@@ -290,10 +285,21 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
         cleanup();
         return fail(ctx, SYMNMF_EINVAL, "build_S: %d zero-variance column(s)", hbad);
     }
-    chk(launch_syrk_store(Z, z_f64, Kpad, ldz, o, (double*)sums, (uint32_t*)pmax, st));
+    // S-building GEMM: split-precision bf16 MFMA unless FP64 storage (or the
+    // FP32-MFMA kernel is asked for with SYMNMF_SYRK=f32)
+    const char* sel = std::getenv("SYMNMF_SYRK");
+    const bool split = !z_f64 && !(sel && std::strcmp(sel, "f32") == 0);
+    void* planes = nullptr;
+    if (split && e == hipSuccess) {
+        chk(hipMalloc(&planes, syrk_split_ws_bytes(K, ldz, p->dtype)));
+        chk(launch_syrk_split_store((const float*)Z, K, ldz, o, (double*)sums, (uint32_t*)pmax, planes, st));
+    } else {
+        chk(launch_syrk_store(Z, z_f64, Kpad, ldz, o, (double*)sums, (uint32_t*)pmax, st));
+    }
     double hs[3] = {0, 0, 0};
     chk(hipMemcpyAsync(hs, sums, 24, hipMemcpyDeviceToHost, st));
     chk(hipStreamSynchronize(st));
+    if (planes) (void)hipFree(planes);
     cleanup();
     if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "build_S: %s", hipGetErrorString(e));
     if (!std::isfinite(hs[0]) || !std::isfinite(hs[1])) return fail(ctx, SYMNMF_ENUMERIC, "build_S: non-finite S");
@@ -908,6 +914,80 @@ symnmf_status symnmf_solve_to_tol(symnmf_ctx* ctx, const symnmf_S* S, symnmf_sta
     st->last = sv;
     if (final_stats) *final_stats = sv;
     return SYMNMF_ENOTCONV;
+}
+
+symnmf_status symnmf_solve_trace(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st, int64_t steps,
+                                 int64_t save_every, void* H_save, int64_t slots, double* ms_out,
+                                 int64_t* certified_at) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!S || !st || st->ctx != ctx || !H_save || !ms_out || save_every < 1 || steps < 0 || slots < steps / save_every)
+        return fail(ctx, SYMNMF_EINVAL, "solve_trace: bad argument");
+    if (S->data != st->S.data) return fail(ctx, SYMNMF_EINVAL, "solve_trace: S does not match the state");
+    const symnmf_params& p = st->p;
+    const int64_t nsave = steps / save_every;
+    const int64_t hbytes = st->n * st->k * st->hsz;
+    std::vector<hipEvent_t> ev(nsave + 1, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    auto cleanup = [&]() {
+        for (auto& x : ev)
+            if (x) (void)hipEventDestroy(x);
+    };
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(ctx, SYMNMF_EDEVICE, "solve_trace: %s", hipGetErrorString(e));
+    }
+    if (certified_at) *certified_at = -1;
+    (void)hipEventRecord(ev[0], ctx->stream);
+    symnmf_status s = SYMNMF_OK;
+    for (int64_t i = 0; i < nsave * save_every && s == SYMNMF_OK; ++i) {
+        s = do_step(ctx, S, st);
+        if (s != SYMNMF_OK) break;
+        const int64_t t = st->t - 1;
+        if ((i + 1) % save_every == 0) {
+            const int64_t j = (i + 1) / save_every - 1;
+            if (hipMemcpyAsync((char*)H_save + j * hbytes, st->H[st->cur], hbytes, hipMemcpyDeviceToDevice,
+                               ctx->stream) != hipSuccess) {
+                s = fail(ctx, SYMNMF_EDEVICE, "solve_trace: copy failed");
+                break;
+            }
+            (void)hipEventRecord(ev[j + 1], ctx->stream);
+        }
+        if (t % p.delta != 0) continue;
+        symnmf_stats sv{};
+        s = read_stats(st, t, &sv);
+        if (s != SYMNMF_OK) break;
+        if (sv.nonfinite) {
+            s = fail(ctx, SYMNMF_ENUMERIC, "solve_trace: non-finite gradient at t=%lld", (long long)t);
+            break;
+        }
+        if (!sv.full) {
+            s = fail(ctx, SYMNMF_EINVAL, "solve_trace: check iteration %lld was not a full step", (long long)t);
+            break;
+        }
+        s = check_iteration(st, &sv);
+        st->last = sv;
+        if (s == SYMNMF_OK && sv.converged && certified_at && *certified_at < 0) *certified_at = t;
+    }
+    if (s == SYMNMF_OK) {
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess) s = fail(ctx, SYMNMF_EDEVICE, "solve_trace: sync");
+        for (int64_t j = 0; j < nsave && s == SYMNMF_OK; ++j) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[0], ev[j + 1]) != hipSuccess) s = fail(ctx, SYMNMF_EDEVICE, "solve_trace: event");
+            ms_out[j] = ms;
+        }
+    }
+    cleanup();
+    return s;
+}
+
+symnmf_status symnmf_probe_read(symnmf_ctx* ctx, const void* src, void* sink, int64_t sink_words, int64_t bytes) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!src || !sink || bytes < 16 || bytes % 16 || sink_words < 4)
+        return fail(ctx, SYMNMF_EINVAL, "probe_read: bad argument");
+    HIP_OK(ctx, launch_read_probe(src, bytes, (uint32_t*)sink, sink_words, ctx->stream));
+    return SYMNMF_OK;
 }
 
 symnmf_status symnmf_probe_copy(symnmf_ctx* ctx, const void* src, void* dst, int64_t bytes) {

@@ -548,6 +548,27 @@ __global__ __launch_bounds__(256) void copy_probe_kernel(const u32x4* __restrict
         dst[i] = __builtin_nontemporal_load(src + i);
 }
 
+// Plain read of ``bytes`` (a multiple of 16): grid-stride nontemporal 16-byte
+// loads, folded into one word per work-group so the loads stay live.
+__global__ __launch_bounds__(256) void read_probe_kernel(const u32x4* __restrict__ src, int64_t count,
+                                                         uint32_t* __restrict__ sink) {
+    uint32_t acc = 0;
+    for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) {
+        const u32x4 v = __builtin_nontemporal_load(src + i);
+        acc ^= v[0] ^ v[1] ^ v[2] ^ v[3];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc ^= __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sink[blockIdx.x * 4 + (threadIdx.x >> 6)] = acc;
+}
+
+hipError_t launch_read_probe(const void* src, int64_t bytes, uint32_t* sink, int64_t sink_words,
+                             hipStream_t stream) {
+    const int64_t blocks = sink_words / 4 < 2048 ? sink_words / 4 : 2048;
+    if (blocks < 1 || bytes % 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(read_probe_kernel, dim3(blocks), dim3(256), 0, stream, (const u32x4*)src, bytes / 16, sink);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t stream) {
     hipLaunchKernelGGL(copy_probe_kernel, dim3(4096), dim3(256), 0, stream, (const u32x4*)src, (u32x4*)dst, bytes / 16);
     return hipGetLastError();

@@ -700,4 +700,40 @@ hipError_t launch_scale(float* x, int64_t m, float a, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// ||M_A^T (A^T B) M_B||_F^2 for k x k FP64 matrices (one work-group); with
+// M_X^T (X^T X) M_X = I this is ||Q_A^T Q_B||_F^2 of orthonormal bases of the
+// column spans of A and B.
+__global__ __launch_bounds__(256) void span_overlap_kernel(const double* __restrict__ MA,
+                                                           const double* __restrict__ AtB,
+                                                           const double* __restrict__ MB, int k,
+                                                           double* __restrict__ out) {
+    __shared__ double T[KMAX * KMAX];
+    __shared__ double red[4];
+    for (int e = threadIdx.x; e < k * k; e += 256) {
+        const int i = e / k, j = e - i * k;
+        double s = 0.0;
+        for (int l = 0; l < k; ++l) s += AtB[i * k + l] * MB[l * k + j];
+        T[e] = s;   // (A^T B M_B)_ij
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < k * k; e += 256) {
+        const int i = e / k, j = e - i * k;
+        double q = 0.0;
+        for (int l = 0; l < k; ++l) q += MA[l * k + i] * T[l * k + j];
+        acc += q * q;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_span_overlap(const double* MA, const double* AtB, const double* MB, int64_t k, double* out,
+                               hipStream_t stream) {
+    if (k < 1 || k > KMAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(span_overlap_kernel, dim3(1), dim3(256), 0, stream, MA, AtB, MB, (int)k, out);
+    return hipGetLastError();
+}
+
 }  // namespace symnmf

@@ -387,4 +387,38 @@ symnmf_status symnmf_warm_start(symnmf_ctx* ctx, const symnmf_S* S, symnmf_mlp* 
     return SYMNMF_OK;
 }
 
+symnmf_status symnmf_subspace_error(symnmf_ctx* ctx, const float* A, const float* B, int64_t n, int64_t k,
+                                    double* out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!A || !B || !out || k < 1 || k > KMAX || n < k) return fail(ctx, SYMNMF_EINVAL, "subspace_error: bad argument");
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    hipStream_t sm = ctx->stream;
+    const int64_t kk = k * k;
+    double* d = nullptr;
+    // AtA, BtB, AtB, V, MA, MB, lam(k), overlap(1), work
+    const int64_t work = xty_work_doubles(n, k, k);
+    HIP_OK(ctx, hipMalloc((void**)&d, (6 * kk + k + 1 + work) * 8 + 16));
+    double *AtA = d, *BtB = d + kk, *AtB = d + 2 * kk, *V = d + 3 * kk, *MA = d + 4 * kk, *MB = d + 5 * kk;
+    double *lam = d + 6 * kk, *ov = lam + k, *wk = ov + 1;
+    int32_t* status = (int32_t*)(wk + work);
+    int32_t st[2] = {0, 0};
+    double overlap = 0.0;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(launch_xty(A, k, k, A, k, k, n, wk, AtA, sm));
+    chk(launch_xty(B, k, k, B, k, k, n, wk, BtB, sm));
+    chk(launch_xty(A, k, k, B, k, k, n, wk, AtB, sm));
+    chk(launch_jacobi_topk(AtA, k, k, V, MA, lam, status, sm));
+    chk(launch_jacobi_topk(BtB, k, k, V, MB, lam, status + 1, sm));
+    chk(launch_span_overlap(MA, AtB, MB, k, ov, sm));
+    chk(hipMemcpyAsync(&overlap, ov, 8, hipMemcpyDeviceToHost, sm));
+    chk(hipMemcpyAsync(st, status, 8, hipMemcpyDeviceToHost, sm));
+    chk(hipStreamSynchronize(sm));
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "subspace_error: %s", hipGetErrorString(e));
+    if (st[0] || st[1]) return fail(ctx, SYMNMF_ENUMERIC, "subspace_error: a factor does not have full column rank");
+    *out = std::sqrt(std::max(0.0, 2.0 * (double)k - 2.0 * overlap) / (2.0 * (double)k));
+    return SYMNMF_OK;
+}
+
 }  // extern "C"

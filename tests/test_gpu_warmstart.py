@@ -210,3 +210,23 @@ def test_warm_start_without_network_recovers_planted_subspace():
     H0 = torch.empty(900, 8, device=dev())
     sym.symnmf_warm_start(c, Sd, None, WIDTH, 8, 3, H0)
     assert o.subspace_error(from_dev(H0), Hs) < 1e-4
+
+
+def test_subspace_error_matches_oracle():
+    g = np.random.default_rng(5)
+    n, k = 1000, 10
+    A = g.random((n, k)).astype(np.float32).astype(np.float64)
+    B = g.random((n, k)).astype(np.float32).astype(np.float64)
+    c = ctx()
+    got = sym.symnmf_subspace_error(c, to_dev(A), to_dev(B))
+    assert got == pytest.approx(o.subspace_error(A, B), abs=1e-9)
+    # same span (B = A R): zero up to the cancellation floor of the formula
+    R = g.normal(size=(k, k))
+    AR = (A @ R).astype(np.float32).astype(np.float64)
+    assert sym.symnmf_subspace_error(c, to_dev(A), to_dev(AR)) < 1e-5
+    # orthogonal spans: 1
+    E = np.zeros((n, 4))
+    F = np.zeros((n, 4))
+    E[np.arange(4), np.arange(4)] = 1.0
+    F[4 + np.arange(4), np.arange(4)] = 1.0
+    assert sym.symnmf_subspace_error(c, to_dev(E), to_dev(F)) == pytest.approx(1.0, abs=1e-12)
