@@ -234,6 +234,26 @@ hipError_t launch_tpdm_omega(const float* X, int64_t T, int64_t n, int lower, vo
     return hipGetLastError();
 }
 
+// XCD-aware order of the 128 x 128 output tiles of the S-building GEMMs.
+// Work-groups are dispatched round-robin over the 8 XCDs, so the 64 work-groups
+// w = x + 8 (64 g + q), q = 0..63, all land on XCD x; they take the 8 x 8 block
+// of tiles number 8 g + x (in row-major order of 8 x 8 blocks), and per K slab
+// read 8 row blocks and 8 column blocks of Z through that XCD's L2 instead of
+// one row block and 64 column blocks.  False for the padding work-groups.
+__device__ inline bool syrk_tile(int64_t w, int64_t n_ti, int64_t n_tj, int64_t& ti, int64_t& tj) {
+    const int64_t x = w & 7, l = w >> 3;
+    const int64_t blk = (l >> 6) * 8 + x, q = l & 63;
+    const int64_t bcols = (n_tj + 7) >> 3;
+    const int64_t br = blk / bcols, bc = blk - br * bcols;
+    ti = br * 8 + (q >> 3);
+    tj = bc * 8 + (q & 7);
+    return ti < n_ti && tj < n_tj;
+}
+inline int64_t syrk_grid(int64_t n_ti, int64_t n_tj) {
+    const int64_t blocks = ((n_ti + 7) >> 3) * ((n_tj + 7) >> 3);
+    return (blocks + 7) / 8 * 8 * 64;
+}
+
 // Epilogue of the S-building GEMMs: |.|, unit diagonal, storage rounding into
 // the tiled layout, FP64 sums per work-group (MODE 1), or the FP8 panel
 // maxima (MODE 0).  acc[a][b][v] holds element (64 wr + 16 a + 4 lg + v,
@@ -242,7 +262,7 @@ hipError_t launch_tpdm_omega(const float* X, int64_t T, int64_t n, int lower, vo
 template <int MODE, int DT>
 __device__ inline void syrk_epilogue(const floatx4 (&acc)[4][4], int64_t i0, int64_t j0, const BuildOut& o,
                                      double* __restrict__ wg_sums, uint32_t* __restrict__ panel_max,
-                                     uint32_t* rowmax, double (*red)[4]) {
+                                     uint32_t* rowmax, double (*red)[4], int64_t slot) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1, lr = lane & 15, lg = lane >> 4;
     if (MODE == 0) {
@@ -312,10 +332,7 @@ __device__ inline void syrk_epilogue(const floatx4 (&acc)[4][4], int64_t i0, int
     }
     if (lane == 0) { red[0][wv] = s1; red[1][wv] = s2; red[2][wv] = s3; }
     __syncthreads();
-    if (t < 3) {
-        const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-        wg_sums[wg * 3 + t] = red[t][0] + red[t][1] + red[t][2] + red[t][3];
-    }
+    if (t < 3) wg_sums[slot * 3 + t] = red[t][0] + red[t][1] + red[t][2] + red[t][3];
 }
 
 // ---------------------------------------------------------------------------
@@ -326,12 +343,15 @@ __device__ inline void syrk_epilogue(const floatx4 (&acc)[4][4], int64_t i0, int
 // ---------------------------------------------------------------------------
 template <int MODE, int DT>
 __global__ __launch_bounds__(256, 2) void syrk_kernel(const float* __restrict__ Z, int64_t K, int64_t ldz, BuildOut o,
-                                                   double* __restrict__ wg_sums, uint32_t* __restrict__ panel_max) {
+                                                   int64_t n_ti, int64_t n_tj, double* __restrict__ wg_sums,
+                                                   uint32_t* __restrict__ panel_max) {
     __shared__ float As[2][16][128 + 4];
     __shared__ float Bs[2][16][128 + 4];
     __shared__ uint32_t rowmax[128];
     __shared__ double red[3][4];
-    const int64_t i0 = (int64_t)blockIdx.y * 128, j0 = (int64_t)blockIdx.x * 128;
+    int64_t ti, tj;
+    if (!syrk_tile(blockIdx.x, n_ti, n_tj, ti, tj)) return;
+    const int64_t i0 = ti * 128, j0 = tj * 128;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1, lr = lane & 15, lg = lane >> 4;
     floatx4 acc[4][4];
@@ -385,17 +405,16 @@ __global__ __launch_bounds__(256, 2) void syrk_kernel(const float* __restrict__ 
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
     }
-    syrk_epilogue<MODE, DT>(acc, i0, j0, o, wg_sums, panel_max, rowmax, red);
+    syrk_epilogue<MODE, DT>(acc, i0, j0, o, wg_sums, panel_max, rowmax, red, ti * n_tj + tj);
 }
 
 // ---------------------------------------------------------------------------
-// Split-precision SYRK on the bf16 matrix cores (Henry, Tang & Heinecke 2019:
-// a float is the sum of bf16 "planes" z = h + m + l, h = bf16(z),
-// m = bf16(z - h), l = bf16(z - h - m); products of planes are exact in the
-// FP32 accumulator).  NPL = 3 keeps the six products of order >= 2^-16
-// (hh, hm, mh, hl, lh, mm), about FP32 accuracy, for FP32 storage; NPL = 2
-// keeps hh, hm, mh (relative error ~2^-16) for BF16 and FP8 storage, whose
-// rounding (2^-9 and coarser) dominates.
+// Split-precision SYRK on the bf16 matrix cores for BF16 and FP8 storage
+// (Henry, Tang & Heinecke 2019): every float is split into two bf16 "planes"
+// z = h + m, h = bf16(z), m = bf16(z - h), and S = sum h h + h m + m h with the
+// plane products exact in the FP32 accumulator; the dropped m m term and the
+// residual are ~2^-16 relative, far below the BF16 (2^-9) or FP8 storage
+// rounding that follows.  (FP32 storage uses the FP32-MFMA kernel above.)
 // The planes are stored per column with the samples contiguous,
 // P[p][c][kk] (Kp = samples rounded up to 32, zero padded), so every lane of
 // v_mfma_f32_16x16x32_bf16 loads its 8 consecutive samples as one 16-byte
@@ -403,7 +422,7 @@ __global__ __launch_bounds__(256, 2) void syrk_kernel(const float* __restrict__ 
 // g = lane / 16, B the same for the columns.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void split_planes_kernel(const float* __restrict__ Z, int64_t K, int64_t ldz,
-                                                           int64_t Kp, int npl, uint16_t* __restrict__ P) {
+                                                           int64_t Kp, uint16_t* __restrict__ P) {
     __shared__ float tile[32][64 + 1];
     const int64_t c0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * 32;
     const int t = threadIdx.x;
@@ -417,37 +436,45 @@ __global__ __launch_bounds__(256) void split_planes_kernel(const float* __restri
         const int c = f >> 5, kk = f & 31;
         const float x = tile[kk][c];
         const uint16_t h = f32_to_bf16_bits(x);
-        const float r1 = x - bf16_bits_to_f32(h);
-        const uint16_t m = f32_to_bf16_bits(r1);
         const int64_t o = (c0 + c) * Kp + k0 + kk;
         P[o] = h;
-        P[plane + o] = m;
-        if (npl == 3) P[2 * plane + o] = f32_to_bf16_bits(r1 - bf16_bits_to_f32(m));
+        P[plane + o] = f32_to_bf16_bits(x - bf16_bits_to_f32(h));
     }
 }
 
-template <int NPL, int MODE, int DT>
+template <int MODE, int DT>
 __global__ __launch_bounds__(256, 2) void syrk_split_kernel(const uint16_t* __restrict__ P, int64_t Kp, int64_t ldz,
-                                                            BuildOut o, double* __restrict__ wg_sums,
+                                                            BuildOut o, int64_t n_ti, int64_t n_tj,
+                                                            double* __restrict__ wg_sums,
                                                             uint32_t* __restrict__ panel_max) {
     __shared__ uint32_t rowmax[128];
     __shared__ double red[3][4];
-    const int64_t i0 = (int64_t)blockIdx.y * 128, j0 = (int64_t)blockIdx.x * 128;
+    int64_t ti, tj;
+    if (!syrk_tile(blockIdx.x, n_ti, n_tj, ti, tj)) return;
+    const int64_t i0 = ti * 128, j0 = tj * 128;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1, lr = lane & 15, lg = lane >> 4;
     const int64_t plane = ldz * Kp;
     // row r of A / B fragment a: column (instrument) index, samples from 8 lg
     const uint16_t* pa = P + (o.row0 + i0 + 64 * wr + lr) * Kp + 8 * lg;
     const uint16_t* pb = P + (j0 + 64 * wc + lr) * Kp + 8 * lg;
-    floatx4 acc[4][4];
+    // hh products accumulate in acc; the cross terms of one 32-sample block
+    // are formed in two fresh MFMAs (x from the row's lower planes, y from the
+    // column's) and added as x + y, so that element (j, i) repeats the exact
+    // operations of (i, j) with x and y exchanged: S stays exactly symmetric.
+    floatx4 acc[4][4], crs[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < 4; ++b) {
+            acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+            crs[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
     for (int64_t k0 = 0; k0 < Kp; k0 += 32) {
-        bf16x8 av[NPL][4], bv[NPL][4];
+        bf16x8 av[2][4], bv[2][4];
 #pragma unroll
-        for (int p = 0; p < NPL; ++p)
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 av[p][a] = *(const bf16x8*)(pa + p * plane + (int64_t)16 * a * Kp + k0);
@@ -457,18 +484,17 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(const uint16_t* __re
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                // small terms first
-                if constexpr (NPL == 3) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1][a], bv[1][b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[NPL - 1][a], bv[0][b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][a], bv[NPL - 1][b], acc[a][b], 0, 0, 0);
-                }
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1][a], bv[0][b], acc[a][b], 0, 0, 0);
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][a], bv[1][b], acc[a][b], 0, 0, 0);
+                const floatx4 x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1][a], bv[0][b], zero, 0, 0, 0);
+                const floatx4 y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][a], bv[1][b], zero, 0, 0, 0);
+                crs[a][b] += x + y;
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][a], bv[0][b], acc[a][b], 0, 0, 0);
             }
     }
-    syrk_epilogue<MODE, DT>(acc, i0, j0, o, wg_sums, panel_max, rowmax, red);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += crs[a][b];
+    syrk_epilogue<MODE, DT>(acc, i0, j0, o, wg_sums, panel_max, rowmax, red, ti * n_tj + tj);
 }
 
 // FP64 S (parity runs): plain FP64 FMAs, 64 x 64 tile per work-group, each
@@ -564,53 +590,51 @@ hipError_t launch_syrk_store(const void* Zv, int z_f64, int64_t K, int64_t ldz, 
     }
     if (o.dtype == SYMNMF_S_FP64) return hipErrorInvalidValue;
     const float* Z = (const float*)Zv;
-    dim3 grid(o.ld / 128, o.rows_pad / 128), block(256);
-    const int64_t wgs = (int64_t)grid.x * grid.y;
+    const int64_t n_ti = o.rows_pad / 128, n_tj = o.ld / 128;
+    dim3 grid(syrk_grid(n_ti, n_tj)), block(256);
+    const int64_t wgs = n_ti * n_tj;
     double* wg_sums = sums + 4;
     if (o.dtype == SYMNMF_S_FP8) {
         const int64_t panels = (o.rows + o.panel_rows - 1) / o.panel_rows;
-        hipLaunchKernelGGL((syrk_kernel<0, SYMNMF_S_FP8>), grid, block, 0, stream, Z, K, ldz, o, wg_sums, panel_max);
+        hipLaunchKernelGGL((syrk_kernel<0, SYMNMF_S_FP8>), grid, block, 0, stream, Z, K, ldz, o, n_ti, n_tj, wg_sums,
+                           panel_max);
         hipLaunchKernelGGL(fp8_scales_kernel, dim3((panels + 255) / 256), dim3(256), 0, stream,
                            (const uint32_t*)panel_max, panels, o.scale);
-        hipLaunchKernelGGL((syrk_kernel<1, SYMNMF_S_FP8>), grid, block, 0, stream, Z, K, ldz, o, wg_sums, panel_max);
+        hipLaunchKernelGGL((syrk_kernel<1, SYMNMF_S_FP8>), grid, block, 0, stream, Z, K, ldz, o, n_ti, n_tj, wg_sums,
+                           panel_max);
     } else if (o.dtype == SYMNMF_S_BF16) {
-        hipLaunchKernelGGL((syrk_kernel<1, SYMNMF_S_BF16>), grid, block, 0, stream, Z, K, ldz, o, wg_sums, panel_max);
+        hipLaunchKernelGGL((syrk_kernel<1, SYMNMF_S_BF16>), grid, block, 0, stream, Z, K, ldz, o, n_ti, n_tj, wg_sums,
+                           panel_max);
     } else {
-        hipLaunchKernelGGL((syrk_kernel<1, SYMNMF_S_FP32>), grid, block, 0, stream, Z, K, ldz, o, wg_sums, panel_max);
+        hipLaunchKernelGGL((syrk_kernel<1, SYMNMF_S_FP32>), grid, block, 0, stream, Z, K, ldz, o, n_ti, n_tj, wg_sums,
+                           panel_max);
     }
     return finish_sums(wg_sums, wgs, sums, stream);
 }
 
-int64_t syrk_split_planes(int32_t dtype) { return dtype == SYMNMF_S_FP32 ? 3 : 2; }
-
-int64_t syrk_split_ws_bytes(int64_t K, int64_t ldz, int32_t dtype) {
-    return syrk_split_planes(dtype) * ldz * round_up(K, 32) * 2;
-}
+int64_t syrk_split_ws_bytes(int64_t K, int64_t ldz) { return 2 * ldz * round_up(K, 32) * 2; }
 
 hipError_t launch_syrk_split_store(const float* Z, int64_t K, int64_t ldz, const BuildOut& o, double* sums,
                                    uint32_t* panel_max, void* ws, hipStream_t stream) {
-    if (o.dtype == SYMNMF_S_FP64) return hipErrorInvalidValue;
-    const int npl = (int)syrk_split_planes(o.dtype);
+    if (o.dtype != SYMNMF_S_BF16 && o.dtype != SYMNMF_S_FP8) return hipErrorInvalidValue;
     const int64_t Kp = round_up(K, 32);
     uint16_t* P = (uint16_t*)ws;
-    hipLaunchKernelGGL(split_planes_kernel, dim3(ldz / 64, Kp / 32), dim3(256), 0, stream, Z, K, ldz, Kp, npl, P);
-    dim3 grid(o.ld / 128, o.rows_pad / 128), block(256);
-    const int64_t wgs = (int64_t)grid.x * grid.y;
+    hipLaunchKernelGGL(split_planes_kernel, dim3(ldz / 64, Kp / 32), dim3(256), 0, stream, Z, K, ldz, Kp, P);
+    const int64_t n_ti = o.rows_pad / 128, n_tj = o.ld / 128;
+    dim3 grid(syrk_grid(n_ti, n_tj)), block(256);
+    const int64_t wgs = n_ti * n_tj;
     double* wg_sums = sums + 4;
     if (o.dtype == SYMNMF_S_FP8) {
         const int64_t panels = (o.rows + o.panel_rows - 1) / o.panel_rows;
-        hipLaunchKernelGGL((syrk_split_kernel<2, 0, SYMNMF_S_FP8>), grid, block, 0, stream, (const uint16_t*)P, Kp,
-                           ldz, o, wg_sums, panel_max);
+        hipLaunchKernelGGL((syrk_split_kernel<0, SYMNMF_S_FP8>), grid, block, 0, stream, (const uint16_t*)P, Kp, ldz,
+                           o, n_ti, n_tj, wg_sums, panel_max);
         hipLaunchKernelGGL(fp8_scales_kernel, dim3((panels + 255) / 256), dim3(256), 0, stream,
                            (const uint32_t*)panel_max, panels, o.scale);
-        hipLaunchKernelGGL((syrk_split_kernel<2, 1, SYMNMF_S_FP8>), grid, block, 0, stream, (const uint16_t*)P, Kp,
-                           ldz, o, wg_sums, panel_max);
-    } else if (o.dtype == SYMNMF_S_BF16) {
-        hipLaunchKernelGGL((syrk_split_kernel<2, 1, SYMNMF_S_BF16>), grid, block, 0, stream, (const uint16_t*)P, Kp,
-                           ldz, o, wg_sums, panel_max);
+        hipLaunchKernelGGL((syrk_split_kernel<1, SYMNMF_S_FP8>), grid, block, 0, stream, (const uint16_t*)P, Kp, ldz,
+                           o, n_ti, n_tj, wg_sums, panel_max);
     } else {
-        hipLaunchKernelGGL((syrk_split_kernel<3, 1, SYMNMF_S_FP32>), grid, block, 0, stream, (const uint16_t*)P, Kp,
-                           ldz, o, wg_sums, panel_max);
+        hipLaunchKernelGGL((syrk_split_kernel<1, SYMNMF_S_BF16>), grid, block, 0, stream, (const uint16_t*)P, Kp, ldz,
+                           o, n_ti, n_tj, wg_sums, panel_max);
     }
     return finish_sums(wg_sums, wgs, sums, stream);
 }

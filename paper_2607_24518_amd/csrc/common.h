@@ -306,10 +306,10 @@ int64_t tpdm_work_bytes(int64_t T, int64_t n);
 int64_t syrk_sum_words(const BuildOut& o);
 hipError_t launch_syrk_store(const void* Z, int z_f64, int64_t K, int64_t ldz, const BuildOut& o, double* sums,
                              uint32_t* panel_max, hipStream_t stream);
-// The same product on the bf16 matrix cores with Z split into bf16 planes
-// (3 planes / 6 products for FP32 storage, 2 / 3 for BF16 and FP8); ws holds
-// the planes (syrk_split_ws_bytes).  Z: Kpad x ldz FP32 with K valid rows.
-int64_t syrk_split_ws_bytes(int64_t K, int64_t ldz, int32_t dtype);
+// The same product for BF16 / FP8 storage on the bf16 matrix cores with Z
+// split into two bf16 planes; ws holds the planes (syrk_split_ws_bytes).
+// Z: Kpad x ldz FP32 with K valid rows.
+int64_t syrk_split_ws_bytes(int64_t K, int64_t ldz);
 hipError_t launch_syrk_split_store(const float* Z, int64_t K, int64_t ldz, const BuildOut& o, double* sums,
                                    uint32_t* panel_max, void* ws, hipStream_t stream);
 // sums: 4 + 3 * rows_pad words

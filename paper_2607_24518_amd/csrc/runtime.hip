@@ -285,13 +285,12 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
         cleanup();
         return fail(ctx, SYMNMF_EINVAL, "build_S: %d zero-variance column(s)", hbad);
     }
-    // S-building GEMM: split-precision bf16 MFMA unless FP64 storage (or the
-    // FP32-MFMA kernel is asked for with SYMNMF_SYRK=f32)
-    const char* sel = std::getenv("SYMNMF_SYRK");
-    const bool split = !z_f64 && !(sel && std::strcmp(sel, "f32") == 0);
+    // S-building GEMM: split-precision bf16 MFMA for BF16 / FP8 storage, FP32
+    // MFMA for FP32, FP64 FMAs for FP64
+    const bool split = p->dtype == SYMNMF_S_BF16 || p->dtype == SYMNMF_S_FP8;
     void* planes = nullptr;
     if (split && e == hipSuccess) {
-        chk(hipMalloc(&planes, syrk_split_ws_bytes(K, ldz, p->dtype)));
+        chk(hipMalloc(&planes, syrk_split_ws_bytes(K, ldz)));
         chk(launch_syrk_split_store((const float*)Z, K, ldz, o, (double*)sums, (uint32_t*)pmax, planes, st));
     } else {
         chk(launch_syrk_store(Z, z_f64, Kpad, ldz, o, (double*)sums, (uint32_t*)pmax, st));

@@ -226,6 +226,8 @@ hipError_t launch_h_image(const float* H, int32_t stype, int64_t k, int64_t n_ch
 // ACC64: FP32 MFMA sums within each 256-column chunk, added into FP64
 // accumulators at every chunk boundary; the partials are written as doubles
 // (the objective pass).
+constexpr int RING_F32 = 8;
+
 template <int KIND, int NT, bool DB, bool PF, bool ACC64>
 __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ Sv, const u32x4* __restrict__ img1,
                                                       const u32x4* __restrict__ img2, void* __restrict__ part,
@@ -236,7 +238,9 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
     constexpr int CPT = NV / 256;                          // image vectors per thread
     constexpr int NS = KIND == 0 ? 16 : (KIND == 1 ? 8 : 4);
     constexpr int EB = KIND == 0 ? 4 : (KIND == 1 ? 2 : 1);
-    constexpr int RING = 4, D = 3;                         // S prefetch ring and distance (sub-steps)
+    // S prefetch ring and distance (sub-steps): deeper for FP32 S, whose sub-steps
+    // are the slowest, to keep more bytes in flight per wave
+    constexpr int RING = (KIND == 0 && NT <= 2 && !ACC64) ? RING_F32 : 4, D = RING - 1;
     static_assert(NS % RING == 0, "ring must divide the sub-steps of a unit");
     __shared__ u32x4 lds[(DB ? 2 : 1) * NV];
     int64_t U; int32_t na;
