@@ -120,6 +120,7 @@ template <> __device__ inline double load_as_f64<uint8_t>(const uint8_t* p) { re
 // ---------------------------------------------------------------------------
 struct PlanView {
     int32_t full;
+    int32_t tall;             // full plans only: units are (pair of row tiles, chunk), see below
     int32_t n_tiles;          // row tiles of the stored panel
     int32_t n_chunks;         // column chunks (ld / KC)
     int32_t P;                // launched persistent work-groups
@@ -139,7 +140,7 @@ inline int64_t plan_words(int64_t n_tiles, int64_t n_chunks) {
 }
 inline PlanView plan_view(int32_t* base, int32_t full, int32_t n_tiles, int32_t n_chunks, int32_t P) {
     PlanView v;
-    v.full = full; v.n_tiles = n_tiles; v.n_chunks = n_chunks; v.P = P;
+    v.full = full; v.tall = 0; v.n_tiles = n_tiles; v.n_chunks = n_chunks; v.P = P;
     v.hdr = base;
     v.active_tile = base + 8;
     v.active_class = v.active_tile + n_tiles;
@@ -149,6 +150,12 @@ inline PlanView plan_view(int32_t* base, int32_t full, int32_t n_tiles, int32_t 
     v.tile_active = v.class_weight + 3 * n_chunks;
     return v;
 }
+
+// Tall full plans: a unit is (pair q of row tiles 2q and 2q+1, chunk), streamed
+// by one 8-wave work-group whose two halves share the chunk image; the partial
+// of tile 2q + h from work-group w goes to index 2 (w + q) + h (one-to-one for
+// the same reason as above), so the buffer needs 2 (P + pairs) tiles.
+__host__ __device__ inline int64_t tall_pairs(int64_t n_tiles) { return (n_tiles + 1) / 2; }
 
 __host__ __device__ inline int64_t wg_start(int64_t w, int64_t U, int64_t Pe) { return w * U / Pe; }
 // the work-group whose range holds unit u
@@ -213,6 +220,8 @@ hipError_t launch_stream_acc64(const void* S, int32_t stype, int64_t k, const vo
 int stream_uses_mfma(int32_t stype, int h_f64, int acc_f64, int64_t k);
 // resident work-groups per CU of the stream kernel for this storage and rank
 int stream_wgs_per_cu(int32_t stype, int64_t k);
+// whether full steps of this storage and rank run the tall (8-wave) kernel
+int stream_tall_supported(int32_t stype, int h_f64, int64_t k);
 
 // plan.hip: build the device plan of a sub-sampled step.
 struct PlanRequest {

@@ -93,6 +93,8 @@ struct symnmf_state {
     void* sel = nullptr;
     void* img[2] = {nullptr, nullptr};   // chunk images of H and 2H (MFMA stream)
     bool mfma = false;
+    bool tall = false;               // full steps run the 8-wave stream kernel
+    int32_t P_tall = 0;
     double* scal = nullptr;          // device scalars (median, sums)
     int64_t t = 0;
     int ring_full[HCAP] = {};
@@ -440,7 +442,11 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
         ALLOC(st->img[0], iw * 4);
         if (p->method == SYMNMF_BLOCK_SVRG) ALLOC(st->img[1], iw * 4);
     }
-    ALLOC(st->part, ((int64_t)st->P + st->tiles) * TR * k * st->hsz);
+    st->tall = stream_tall_supported(S->dtype, h_f64, k) != 0 && std::getenv("SYMNMF_NO_TALL") == nullptr;
+    st->P_tall = ctx->cus;
+    const int64_t part_tiles = std::max<int64_t>((int64_t)st->P + st->tiles,
+                                                 st->tall ? 2 * ((int64_t)st->P_tall + tall_pairs(st->tiles)) : 0);
+    ALLOC(st->part, part_tiles * TR * k * st->hsz);
     ALLOC(st->tile_gram, st->tiles * k * k * 8);
     ALLOC(st->tile_tr, st->tiles * 8);
     ALLOC(st->tile_kkt, st->tiles * 8);
@@ -491,6 +497,10 @@ static symnmf_status do_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* s
     if (p.method == SYMNMF_ROW_SVRG) kind = (t % p.snapshot_s == 0) ? 0 : 1;
     if (p.method == SYMNMF_BLOCK_SVRG) kind = (st->phi >= 1.0 || t % p.snapshot_s == 0) ? 0 : 2;
     PlanView pv = plan_view(st->plan, kind == 0, (int32_t)st->tiles, (int32_t)st->chunks, st->P);
+    if (kind == 0 && st->tall) {
+        pv.tall = 1;
+        pv.P = st->P_tall;
+    }
     if (kind != 0) {
         PlanRequest r;
         r.mode = kind;

@@ -26,8 +26,8 @@ namespace symnmf {
 
 __device__ inline void plan_bounds(const PlanView& p, int64_t& U, int32_t& na) {
     if (p.full) {
-        na = p.n_tiles;
-        U = (int64_t)p.n_tiles * p.n_chunks;
+        na = p.tall ? (int32_t)tall_pairs(p.n_tiles) : p.n_tiles;
+        U = (int64_t)na * p.n_chunks;
     } else {
         na = p.hdr[0];
         U = (int64_t)(uint32_t)p.hdr[1] | ((int64_t)p.hdr[2] << 32);
@@ -228,19 +228,25 @@ hipError_t launch_h_image(const float* H, int32_t stype, int64_t k, int64_t n_ch
 // (the objective pass).
 constexpr int RING_F32 = 8;
 
-template <int KIND, int NT, bool DB, bool PF, bool ACC64>
-__global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ Sv, const u32x4* __restrict__ img1,
-                                                      const u32x4* __restrict__ img2, void* __restrict__ part,
-                                                      PlanView p) {
+// TALL (full plans): 8 waves, the two halves stream row tiles 2q and 2q+1 of a
+// (tile pair, chunk) unit against one chunk image, halving image traffic per
+// byte of S.
+template <int KIND, int NT, bool DB, bool PF, bool ACC64, bool TALL>
+__global__ __launch_bounds__(TALL ? 512 : 256, TALL ? 1 : 2) void stream_mfma(const void* __restrict__ Sv,
+                                                                             const u32x4* __restrict__ img1,
+                                                                             const u32x4* __restrict__ img2,
+                                                                             void* __restrict__ part, PlanView p) {
     constexpr int K = 16 * NT;
+    constexpr int NTHR = TALL ? 512 : 256;
     using IS = ImageShape<KIND, K>;
     constexpr int NV = IS::NV;
-    constexpr int CPT = NV / 256;                          // image vectors per thread
+    constexpr int CPT = NV / NTHR;                         // image vectors per thread
+    static_assert(NV % NTHR == 0, "image vectors must split evenly over the threads");
     constexpr int NS = KIND == 0 ? 16 : (KIND == 1 ? 8 : 4);
     constexpr int EB = KIND == 0 ? 4 : (KIND == 1 ? 2 : 1);
     // S prefetch ring and distance (sub-steps): deeper for FP32 S, whose sub-steps
     // are the slowest, to keep more bytes in flight per wave
-    constexpr int RING = (KIND == 0 && NT <= 2 && !ACC64) ? RING_F32 : 4, D = RING - 1;
+    constexpr int RING = (KIND <= 1 && NT <= 2 && !ACC64) ? RING_F32 : 4, D = RING - 1;
     static_assert(NS % RING == 0, "ring must divide the sub-steps of a unit");
     __shared__ u32x4 lds[(DB ? 2 : 1) * NV];
     int64_t U; int32_t na;
@@ -251,13 +257,16 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
     if (w >= Pe) return;
     const int64_t u0 = wg_start(w, U, Pe);
     const int64_t u1 = wg_start(w + 1, U, Pe);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3;
+    const int half = TALL ? (int)(threadIdx.x >> 8) : 0;   // tile of the pair (tall)
     const int lr = lane & 15, lg = lane >> 4;
     const int tid = threadIdx.x;
 
-    // this wave's contiguous run of a unit's tile, in 16-byte vectors, plus the lane
+    // this wave's contiguous run of a unit's tile, in 16-byte vectors, plus the
+    // lane (tall: the odd last pair has no second tile; that half re-reads the
+    // first tile and writes nothing)
     auto s_run = [&](int32_t aa, int32_t ch) -> const u32x4* {
-        const int64_t tile = tile_of(p, aa);
+        const int64_t tile = TALL ? min((int64_t)2 * aa + half, (int64_t)p.n_tiles - 1) : (int64_t)tile_of(p, aa);
         return (const u32x4*)((const uint8_t*)Sv + ((int64_t)tile * p.n_chunks + ch) * TILE_ELEMS * EB +
                               (int64_t)wv * (TILE_ELEMS * EB / 4)) + lane;
     };
@@ -271,7 +280,7 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
     unit_decode(p, u0, a, chunk, wt);
     {
         const u32x4* src = image(chunk, wt);
-        for (int i = tid; i < NV; i += 256) lds[i] = src[i];
+        for (int i = tid; i < NV; i += NTHR) lds[i] = src[i];
     }
     const u32x4* sp = s_run(a, chunk);
     u32x4 ring[RING][4];
@@ -310,7 +319,7 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
             if (PF) {
                 const u32x4* src = image(chunk_n, wt_n);
 #pragma unroll
-                for (int i = 0; i < CPT; ++i) hreg[i] = src[tid + 256 * i];
+                for (int i = 0; i < CPT; ++i) hreg[i] = src[tid + NTHR * i];
             }
         }
         const u32x4* hb = lds + cur * NV;
@@ -391,13 +400,16 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
         }
         // end of this tile's run: write the partial and start the next tile
         if (!more || a_next != a) {
+            const int64_t slot = TALL ? 2 * (w + a) + half : (w + a);
+            const bool store = !TALL || 2 * (int64_t)a + half < p.n_tiles;
 #pragma unroll
             for (int rg = 0; rg < 4; ++rg)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int64_t o = (w + a) * (int64_t)TR * K + (64 * wv + 16 * rg + 4 * lg + v) * K + 16 * nt + lr;
+                        if (!store) continue;
+                        const int64_t o = slot * (int64_t)TR * K + (64 * wv + 16 * rg + 4 * lg + v) * K + 16 * nt + lr;
                         if (ACC64) {
                             ((double*)part)[o] = acc64[ACC64 ? rg : 0][ACC64 ? nt : 0][ACC64 ? v : 0];
                             acc64[ACC64 ? rg : 0][ACC64 ? nt : 0][ACC64 ? v : 0] = 0.0;
@@ -413,10 +425,10 @@ __global__ __launch_bounds__(256, 2) void stream_mfma(const void* __restrict__ S
             if (!DB) __syncthreads();                 // single buffer: everyone done reading
             if (PF) {
 #pragma unroll
-                for (int i = 0; i < CPT; ++i) dstb[tid + 256 * i] = hreg[i];
+                for (int i = 0; i < CPT; ++i) dstb[tid + NTHR * i] = hreg[i];
             } else {
                 const u32x4* src = image(chunk_n, wt_n);
-                for (int i = tid; i < NV; i += 256) dstb[i] = src[i];
+                for (int i = tid; i < NV; i += NTHR) dstb[i] = src[i];
             }
             __syncthreads();
             a = a_next;
@@ -461,21 +473,37 @@ static hipError_t launch_generic_s(const void* S, int64_t ld, const void* H, int
 // LDS per work-group (image buffers): FP32 k=16/32 double-buffered (32/64 KB),
 // k=64 single (64 KB); BF16/FP8 keep three bf16 planes: k=16 double (48 KB),
 // k=32 single (48 KB), k=64 single (96 KB, one work-group per CU).
+// Tall kernels (one 8-wave work-group per CU) double-buffer the images up to
+// k = 32 (FP32 64 KB, BF16 / FP8 96 KB) and FP32 at k = 64 (128 KB); BF16 / FP8
+// at k = 64 keep one 96 KB image.
 template <int KIND>
 static void launch_mfma_kind(const void* S, const u32x4* img1, const u32x4* img2, void* part, int64_t k,
                              const PlanView& p, hipStream_t stream) {
-    dim3 grid(p.P), block(256);
-    if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true, true, false>), grid, block, 0, stream, S, img1, img2, part, p);
-    else if (k == 32) hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0, true, false>), grid, block, 0, stream, S, img1, img2, part, p);
-    else hipLaunchKernelGGL((stream_mfma<KIND, 4, false, false, false>), grid, block, 0, stream, S, img1, img2, part, p);
+    dim3 grid(p.P);
+    if (p.tall) {
+        dim3 block(512);
+        if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true, true, false, true>), grid, block, 0, stream, S, img1, img2, part, p);
+        else if (k == 32) hipLaunchKernelGGL((stream_mfma<KIND, 2, true, true, false, true>), grid, block, 0, stream, S, img1, img2, part, p);
+        else hipLaunchKernelGGL((stream_mfma<KIND, 4, KIND == 0, false, false, true>), grid, block, 0, stream, S, img1, img2, part, p);
+        return;
+    }
+    dim3 block(256);
+    if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true, true, false, false>), grid, block, 0, stream, S, img1, img2, part, p);
+    else if (k == 32) hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0, true, false, false>), grid, block, 0, stream, S, img1, img2, part, p);
+    else hipLaunchKernelGGL((stream_mfma<KIND, 4, false, false, false, false>), grid, block, 0, stream, S, img1, img2, part, p);
+}
+
+int stream_tall_supported(int32_t stype, int h_f64, int64_t k) {
+    return stream_uses_mfma(stype, h_f64, 0, k);
 }
 
 template <int KIND>
 static void launch_mfma_kind_acc64(const void* S, const u32x4* img, void* part, int64_t k, const PlanView& p,
                                    hipStream_t stream) {
     dim3 grid(p.P), block(256);
-    if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true, false, true>), grid, block, 0, stream, S, img, img, part, p);
-    else hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0, false, true>), grid, block, 0, stream, S, img, img, part, p);
+    if (p.tall) return;   // the objective pass always runs the 4-wave kernel
+    if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true, false, true, false>), grid, block, 0, stream, S, img, img, part, p);
+    else hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0, false, true, false>), grid, block, 0, stream, S, img, img, part, p);
 }
 
 int stream_acc64_supported(int32_t stype, int64_t k) {

@@ -63,15 +63,25 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
     for (int f = t; f < TR * k; f += UT) Hs[(f / k) * KB + f % k] = Ht[g0 * k + f];
     __syncthreads();
 
-    int64_t w_lo = 0, w_hi = -1, U = 0;
+    // partial tiles of this tile: index (w + act), or 2 (w + pair) + half for
+    // tall full plans, over the work-groups w_lo..w_hi that streamed its units
+    int64_t w_lo = 0, w_hi = -1, U = 0, slot_base = act, slot_mul = 1;
     if (act >= 0) {
-        int64_t na;
-        if (p.full) { na = p.n_tiles; U = (int64_t)p.n_tiles * p.n_chunks; }
-        else { na = p.hdr[0]; U = (int64_t)(uint32_t)p.hdr[1] | ((int64_t)p.hdr[2] << 32); }
-        (void)na;
-        const int64_t Pe = U < p.P ? U : p.P;
-        w_lo = wg_owner(upd_unit_off(p, act), U, Pe);
-        w_hi = wg_owner(upd_unit_off(p, act + 1) - 1, U, Pe);
+        if (p.full && p.tall) {
+            const int64_t q = act >> 1;
+            U = tall_pairs(p.n_tiles) * p.n_chunks;
+            const int64_t Pe = U < p.P ? U : p.P;
+            w_lo = wg_owner(q * p.n_chunks, U, Pe);
+            w_hi = wg_owner((q + 1) * p.n_chunks - 1, U, Pe);
+            slot_base = 2 * q + (act & 1);
+            slot_mul = 2;
+        } else {
+            if (p.full) U = (int64_t)p.n_tiles * p.n_chunks;
+            else U = (int64_t)(uint32_t)p.hdr[1] | ((int64_t)p.hdr[2] << 32);
+            const int64_t Pe = U < p.P ? U : p.P;
+            w_lo = wg_owner(upd_unit_off(p, act), U, Pe);
+            w_hi = wg_owner(upd_unit_off(p, act + 1) - 1, U, Pe);
+        }
     }
     const HT* part = (const HT*)a.part;
     HT* G = (HT*)a.G;
@@ -93,7 +103,7 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
             HT g;
             if (act >= 0) {
                 HT sh = 0;
-                for (int64_t w = w_lo; w <= w_hi; ++w) sh += part[((w + act) * TR + r) * (int64_t)k + c];
+                for (int64_t w = w_lo; w <= w_hi; ++w) sh += part[((slot_mul * w + slot_base) * TR + r) * (int64_t)k + c];
                 if (a.fp8)   // codes carry S * scale off the diagonal; S_ii is kept exactly
                     sh = sh / (HT)a.panel_scale[prow / a.panel_rows] + (HT)a.diag[prow] * h;
                 HT hg = 0;

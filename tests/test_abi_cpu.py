@@ -90,3 +90,36 @@ def test_tiled_storage_offsets_match_the_documented_layout(binding):
         assert sorted(M.ravel().astype(np.int64).tolist()) == list(range(rows_pad * ld))
     assert binding.symnmf_S_offset(3, 5, 512, 768, binding.S_FP64) == 3 * 768 + 5
     assert binding.symnmf_S_offset(512, 0, 512, 768, binding.S_FP32) == -1
+
+
+@pytest.mark.parametrize("tiles,chunks,P", [(1, 1, 256), (2, 3, 256), (3, 3, 256), (391, 391, 256),
+                                            (392, 391, 256), (49, 3907, 256), (7, 5, 512)])
+def test_partial_slots_are_one_to_one(tiles, chunks, P):
+    """Host check of the stream-K partial indexing: work-group w owns units
+    [w U / Pe, (w+1) U / Pe); each maximal run of one tile (pair of tiles for
+    the 8-wave kernel) writes slot w + a (2 (w + q) + h); the slots are
+    distinct, fit the allocated buffer, and the update kernel's owner range of
+    each tile is exactly its set of writers."""
+    def owner(u, U, Pe):
+        return ((u + 1) * Pe - 1) // U
+
+    for tall in (False, True):
+        na = (tiles + 1) // 2 if tall else tiles
+        U = na * chunks
+        Pe = min(U, P)
+        slots, writers = {}, {}
+        for w in range(Pe):
+            lo, hi = w * U // Pe, (w + 1) * U // Pe
+            assert hi > lo
+            for a in range(lo // chunks, (hi - 1) // chunks + 1):
+                halves = [(2 * a + h, 2 * (w + a) + h) for h in (0, 1) if 2 * a + h < tiles] if tall else [(a, w + a)]
+                for tile, slot in halves:
+                    assert slot not in slots
+                    slots[slot] = tile
+                    writers.setdefault(tile, set()).add(w)
+        cap = 2 * (P + na) if tall else P + tiles
+        assert max(slots) < cap
+        for tile in range(tiles):
+            a = tile // 2 if tall else tile
+            w_lo, w_hi = owner(a * chunks, U, Pe), owner((a + 1) * chunks - 1, U, Pe)
+            assert writers[tile] == set(range(w_lo, w_hi + 1))
