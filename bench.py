@@ -359,9 +359,11 @@ def warm_start_study(args):
     torch.cuda.empty_cache()
 
     # 3. evaluation
-    def evaluate(S, k_eval, model, label, seed, rand_steps, warm_steps):
+    def evaluate(S, k_eval, model, label, seed, rand_steps, warm_steps, extra=None):
         """random init run first (it is also the reference: f_ref is its
-        certified iterate, or its last one), then the two warm starts."""
+        certified iterate, or its last one), then the two warm starts; with
+        ``extra`` ({name: S stored otherwise}) the three initialisations are
+        also run on those stores, judged on S."""
         nn = S.desc.n
         eta = math.sqrt(S.desc.mean / k_eval)
         params = variant_params("fp32", eta)
@@ -398,6 +400,20 @@ def warm_start_study(args):
                     e["seconds_with_fallback"] = e["seconds"]
                 e["speedup_vs_random"] = round(r_s / e["seconds_with_fallback"], 3)
             res[name] = e
+        for xname, Sx in (extra or {}).items():
+            xinits = {
+                "random": lambda H: sym.symnmf_init_H(ctx, Sx, k_eval, seed, H),
+                "coords": lambda H: sym.symnmf_warm_start(ctx, Sx, None, W, k_eval, WARM_OMEGA_SEED, H),
+                "mlp": lambda H: sym.symnmf_warm_start(ctx, Sx, model, W, k_eval, WARM_OMEGA_SEED, H),
+            }
+            for name, init in xinits.items():
+                steps = rand_steps if name == "random" else warm_steps
+                wt, _, w_init = ttt_trace(ctx, Sx, k_eval, params, init, steps, every, store)
+                e = ttt_scan(judge, store, steps // every, f_ref, args.ttt_tol, every, wt)
+                e["init_seconds"] = round(w_init, 4)
+                if r_s is not None and e.get("seconds"):
+                    e["speedup_vs_fp32_random"] = round(r_s / e["seconds"], 3)
+                res[f"{xname}-{name}"] = e
         del store
         log(f"{label}: " + json.dumps(res))
         return res
@@ -419,8 +435,11 @@ def warm_start_study(args):
     if args.warm_c3:
         X = synth.overlap_returns(0, T=2500, n=100000, groups=32, device=dev).X
         S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
+        extra = {dt: sym.symnmf_build_S(ctx, X, dtype=sym.DTYPES[dt], fp8_panel_rows=256)
+                 for dt in args.warm_c3_dtypes.split(",") if dt and dt != "fp32"}
         del X
-        out["c3_abs_corr_n100000"] = evaluate(S, k, net, "n=100000 |corr|", 1, args.warm_c3_max, args.warm_c3_max)
+        out["c3_abs_corr_n100000"] = evaluate(S, k, net, "n=100000 |corr|", 1, args.warm_c3_max, args.warm_c3_max,
+                                              extra)
     return out
 
 
@@ -470,6 +489,7 @@ def main():
     ap.add_argument("--warm-warm-max", type=int, default=3000, help="steps of each warm-started run")
     ap.add_argument("--warm-c3", action="store_true", help="also evaluate on the n=100000 |corr| workload")
     ap.add_argument("--warm-c3-max", type=int, default=6000)
+    ap.add_argument("--warm-c3-dtypes", default="fp32", help="storage types of the n=100000 evaluation, e.g. fp32,bf16")
     args = ap.parse_args()
 
     if args.warm:

@@ -16,6 +16,11 @@ namespace symnmf {
 constexpr int TR = 256;
 constexpr int KC = 256;
 constexpr int KMAX = 64;
+// The update kernel works on row slices of SR = TR / SUBT rows (one
+// work-group each); per-slice FP64 partials (Gram, trace, KKT) are indexed
+// slice = SUBT * tile + sub.
+constexpr int SUBT = 4;
+constexpr int SR = TR / SUBT;
 constexpr int64_t PAD = 256;
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -262,7 +267,7 @@ struct UpdateArgs {
 };
 hipError_t launch_update(const UpdateArgs& a, int h_f64, const PlanView& plan, hipStream_t stream);
 
-// Per-tile FP64 Gram partials of rows [row0, row0 + tiles*TR) of H.
+// Per-slice FP64 Gram partials (SUBT per tile) of rows [row0, row0 + tiles*TR) of H.
 hipError_t launch_tile_gram(const void* H, int h_f64, int64_t row0, int64_t rows, int64_t tiles, int64_t k,
                             double* tile_gram, hipStream_t stream);
 // FP64 Gram of the rows of [0, n) outside [skip_lo, skip_hi).

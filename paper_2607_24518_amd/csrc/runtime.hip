@@ -447,10 +447,10 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
     const int64_t part_tiles = std::max<int64_t>((int64_t)st->P + st->tiles,
                                                  st->tall ? 2 * ((int64_t)st->P_tall + tall_pairs(st->tiles)) : 0);
     ALLOC(st->part, part_tiles * TR * k * st->hsz);
-    ALLOC(st->tile_gram, st->tiles * k * k * 8);
-    ALLOC(st->tile_tr, st->tiles * 8);
-    ALLOC(st->tile_kkt, st->tiles * 8);
-    ALLOC(st->tile_bad, st->tiles * 4);
+    ALLOC(st->tile_gram, st->tiles * SUBT * k * k * 8);
+    ALLOC(st->tile_tr, st->tiles * SUBT * 8);
+    ALLOC(st->tile_kkt, st->tiles * SUBT * 8);
+    ALLOC(st->tile_bad, st->tiles * SUBT * 4);
     ALLOC(st->gram64[0], k * k * 8);
     ALLOC(st->gram64[1], k * k * 8);
     ALLOC(st->gram_eff, 3 * k * k * st->hsz);
@@ -477,7 +477,7 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
         e = launch_gram_rows(st->H[0], h_f64, st->n, st->row0, st->row0 + st->rows, k, st->gram_fixed, sm);
     if (e == hipSuccess) e = launch_tile_gram(st->H[0], h_f64, st->row0, st->rows, st->tiles, k, st->tile_gram, sm);
     if (e == hipSuccess)
-        e = launch_finalize(st->tiles, k, st->tile_gram, st->tile_tr, st->tile_kkt, st->tile_bad, st->gram_fixed,
+        e = launch_finalize(st->tiles * SUBT, k, st->tile_gram, st->tile_tr, st->tile_kkt, st->tile_bad, st->gram_fixed,
                             nullptr, st->gram64[0], st->gram_eff, h_f64, st->scal, sm);
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
     if (e != hipSuccess) {
@@ -571,7 +571,7 @@ static symnmf_status do_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* s
     }
     const int slot = (int)(t % HCAP);
     ProfScope psf(ctx, PK_FINALIZE);
-    HIP_OK(ctx, launch_finalize(st->tiles, st->k, st->tile_gram, st->tile_tr, st->tile_kkt, st->tile_bad,
+    HIP_OK(ctx, launch_finalize(st->tiles * SUBT, st->k, st->tile_gram, st->tile_tr, st->tile_kkt, st->tile_bad,
                                 st->gram_fixed, st->gram64[st->cur], st->gram64[1 - st->cur], st->gram_eff, st->h_f64,
                                 st->ring + slot * 4, sm));
     st->ring_full[slot] = kind == 0;

@@ -501,7 +501,6 @@ template <int KIND>
 static void launch_mfma_kind_acc64(const void* S, const u32x4* img, void* part, int64_t k, const PlanView& p,
                                    hipStream_t stream) {
     dim3 grid(p.P), block(256);
-    if (p.tall) return;   // the objective pass always runs the 4-wave kernel
     if (k == 16) hipLaunchKernelGGL((stream_mfma<KIND, 1, true, false, true, false>), grid, block, 0, stream, S, img, img, part, p);
     else hipLaunchKernelGGL((stream_mfma<KIND, 2, KIND == 0, false, true, false>), grid, block, 0, stream, S, img, img, part, p);
 }
@@ -512,7 +511,7 @@ int stream_acc64_supported(int32_t stype, int64_t k) {
 
 hipError_t launch_stream_acc64(const void* S, int32_t stype, int64_t k, const void* img, double* part,
                                const PlanView& p, hipStream_t stream) {
-    if (!stream_acc64_supported(stype, k) || !img) return hipErrorInvalidValue;
+    if (!stream_acc64_supported(stype, k) || !img || p.tall) return hipErrorInvalidValue;   // 4-wave kernel only
     const u32x4* i1 = (const u32x4*)img;
     if (stype == SYMNMF_S_FP32) launch_mfma_kind_acc64<0>(S, i1, part, k, p, stream);
     else if (stype == SYMNMF_S_BF16) launch_mfma_kind_acc64<1>(S, i1, part, k, p, stream);

@@ -43,24 +43,26 @@ __device__ inline int64_t upd_unit_off(const PlanView& p, int32_t a) {
     return p.full ? (int64_t)a * p.n_chunks : (int64_t)p.unit_offset[a];
 }
 
-constexpr int UT = 1024;   // threads of the update work-group
+constexpr int UT = 256;   // threads of the update work-group (one row slice of SR rows)
 
 template <typename HT, int KB>
 __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
-    __shared__ HT Hs[TR * KB];
-    __shared__ HT Hns[TR * KB];
+    __shared__ HT Hs[SR * KB];
+    __shared__ HT Hns[SR * KB];
     __shared__ HT Gs[KB * KB];
     __shared__ double red[UT / 64];
     const int t = threadIdx.x;
-    const int64_t tile = blockIdx.x;
+    const int64_t slice = blockIdx.x;
+    const int64_t tile = slice / SUBT;
+    const int r0 = (int)(slice % SUBT) * SR;           // first tile row of the slice
     const int k = (int)a.k;
     const int32_t act = p.full ? (int32_t)tile : p.tile_active[tile];
     const int cls = (act >= 0 && !p.full) ? p.active_class[act] : 0;
     const HT* gram = (const HT*)a.gram_eff + (int64_t)cls * k * k;
     for (int e = t; e < k * k; e += UT) Gs[(e / k) * KB + e % k] = gram[e];
-    const int64_t g0 = a.row0 + tile * TR;            // global row of tile row 0
+    const int64_t g0 = a.row0 + tile * TR + r0;       // global row of slice row 0
     const HT* Ht = (const HT*)a.H;
-    for (int f = t; f < TR * k; f += UT) Hs[(f / k) * KB + f % k] = Ht[g0 * k + f];
+    for (int f = t; f < SR * k; f += UT) Hs[(f / k) * KB + f % k] = Ht[g0 * k + f];
     __syncthreads();
 
     // partial tiles of this tile: index (w + act), or 2 (w + pair) + half for
@@ -93,9 +95,9 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
     const HT eta = (HT)a.eta, eps = (HT)a.eps, alpha = (HT)a.alpha, mom = (HT)a.mu, cg = (HT)a.cgrad;
     double tr = 0.0, kkt = 0.0;
     int bad = 0;
-    for (int f = t; f < TR * k; f += UT) {
-        const int r = f / k, c = f - r * k;
-        const int64_t prow = tile * TR + r;
+    for (int f = t; f < SR * k; f += UT) {
+        const int r = f / k, c = f - r * k;             // slice row, column
+        const int64_t prow = tile * TR + r0 + r;
         HT hn = 0;
         if (prow < a.rows) {
             const HT h = Hs[r * KB + c];
@@ -103,7 +105,8 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
             HT g;
             if (act >= 0) {
                 HT sh = 0;
-                for (int64_t w = w_lo; w <= w_hi; ++w) sh += part[((slot_mul * w + slot_base) * TR + r) * (int64_t)k + c];
+                for (int64_t w = w_lo; w <= w_hi; ++w)
+                    sh += part[((slot_mul * w + slot_base) * TR + r0 + r) * (int64_t)k + c];
                 if (a.fp8)   // codes carry S * scale off the diagonal; S_ii is kept exactly
                     sh = sh / (HT)a.panel_scale[prow / a.panel_rows] + (HT)a.diag[prow] * h;
                 HT hg = 0;
@@ -152,26 +155,26 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
         Hns[r * KB + c] = hn;
     }
     __syncthreads();
-    double* tg = a.tile_gram + tile * (int64_t)k * k;
+    double* tg = a.tile_gram + slice * (int64_t)k * k;
     for (int e = t; e < k * k; e += UT) {
         const int ia = e / k, ib = e - ia * k;
         double s = 0.0;
-        for (int r = 0; r < TR; ++r) s += (double)Hns[r * KB + ia] * (double)Hns[r * KB + ib];
+        for (int r = 0; r < SR; ++r) s += (double)Hns[r * KB + ia] * (double)Hns[r * KB + ib];
         tg[e] = s;
     }
     const double str = block_sum(tr, red);
     const double skk = block_sum(kkt, red);
     const double sbad = block_sum((double)bad, red);
     if (t == 0) {
-        a.tile_tr[tile] = str;
-        a.tile_kkt[tile] = skk;
-        a.tile_bad[tile] = (int32_t)sbad;
+        a.tile_tr[slice] = str;
+        a.tile_kkt[slice] = skk;
+        a.tile_bad[slice] = (int32_t)sbad;
     }
 }
 
 hipError_t launch_update(const UpdateArgs& a, int h_f64, const PlanView& p, hipStream_t stream) {
     const int64_t tiles = a.rows_pad / TR;
-    dim3 grid(tiles), block(UT);
+    dim3 grid(tiles * SUBT), block(UT);
     if (h_f64) {
         if (a.k <= 8) hipLaunchKernelGGL((update_kernel<double, 8>), grid, block, 0, stream, a, p);
         else if (a.k <= 16) hipLaunchKernelGGL((update_kernel<double, 16>), grid, block, 0, stream, a, p);
@@ -190,14 +193,14 @@ hipError_t launch_update(const UpdateArgs& a, int h_f64, const PlanView& p, hipS
 template <typename HT>
 __global__ __launch_bounds__(256) void tile_gram_kernel(const HT* __restrict__ H, int64_t row0, int64_t rows,
                                                         int k, double* __restrict__ out) {
-    const int64_t tile = blockIdx.x;
+    const int64_t slice = blockIdx.x;
     const int t = threadIdx.x;
-    double* dst = out + tile * (int64_t)k * k;
+    double* dst = out + slice * (int64_t)k * k;
     for (int e = t; e < k * k; e += 256) {
         const int ia = e / k, ib = e - ia * k;
         double s = 0.0;
-        for (int r = 0; r < TR; ++r) {
-            const int64_t prow = tile * TR + r;
+        for (int r = 0; r < SR; ++r) {
+            const int64_t prow = slice * SR + r;
             if (prow < rows) s += (double)H[(row0 + prow) * k + ia] * (double)H[(row0 + prow) * k + ib];
         }
         dst[e] = s;
@@ -207,11 +210,11 @@ __global__ __launch_bounds__(256) void tile_gram_kernel(const HT* __restrict__ H
 hipError_t launch_tile_gram(const void* H, int h_f64, int64_t row0, int64_t rows, int64_t tiles, int64_t k,
                             double* tile_gram, hipStream_t stream) {
     if (h_f64)
-        hipLaunchKernelGGL(tile_gram_kernel<double>, dim3(tiles), dim3(256), 0, stream, (const double*)H, row0,
-                           rows, (int)k, tile_gram);
+        hipLaunchKernelGGL(tile_gram_kernel<double>, dim3(tiles * SUBT), dim3(256), 0, stream, (const double*)H,
+                           row0, rows, (int)k, tile_gram);
     else
-        hipLaunchKernelGGL(tile_gram_kernel<float>, dim3(tiles), dim3(256), 0, stream, (const float*)H, row0,
-                           rows, (int)k, tile_gram);
+        hipLaunchKernelGGL(tile_gram_kernel<float>, dim3(tiles * SUBT), dim3(256), 0, stream, (const float*)H,
+                           row0, rows, (int)k, tile_gram);
     return hipGetLastError();
 }
 
@@ -306,7 +309,7 @@ hipError_t launch_finalize(int64_t tiles, int64_t k, const double* tile_gram, co
     return hipGetLastError();
 }
 
-// Block step: Gram_J, Gram_I and their sum from the tile partials of H_t.
+// Block step: Gram_J, Gram_I and their sum from the slice partials of H_t.
 template <typename HT>
 __global__ __launch_bounds__(256) void gram_select_kernel(int k, const double* __restrict__ tile_gram,
                                                           const int32_t* __restrict__ tI,
@@ -317,8 +320,10 @@ __global__ __launch_bounds__(256) void gram_select_kernel(int k, const double* _
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= kk) return;
     double gi = 0.0, gj = 0.0;
-    for (int i = 0; i < counts[0]; ++i) gi += tile_gram[(int64_t)tI[i] * kk + e];
-    for (int i = 0; i < counts[1]; ++i) gj += tile_gram[(int64_t)tJ[i] * kk + e];
+    for (int i = 0; i < counts[0]; ++i)
+        for (int sub = 0; sub < SUBT; ++sub) gi += tile_gram[((int64_t)tI[i] * SUBT + sub) * kk + e];
+    for (int i = 0; i < counts[1]; ++i)
+        for (int sub = 0; sub < SUBT; ++sub) gj += tile_gram[((int64_t)tJ[i] * SUBT + sub) * kk + e];
     out[e] = (HT)gj;
     out[kk + e] = (HT)gi;
     out[2 * kk + e] = (HT)(gi + gj);
