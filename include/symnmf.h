@@ -176,6 +176,11 @@ int64_t symnmf_S_offset(int64_t r, int64_t c, int64_t rows_pad, int64_t ld, int3
  *   sample), Pareto(2) margins x = (1 - r/(T+1))^-1/2, FP64 radial norms, the
  *   floor(qT) largest kept (ties to the lower sample), angular rows Omega,
  *   S = D^-1/2 Omega^T Omega D^-1/2 by the same GEMM, S_ii = 1.
+ * The GEMM accumulates in FP32: FP32 storage multiplies on the FP32 matrix
+ * cores; BF16 / FP8 storage splits the operand into two bf16 planes
+ * (z = h + m, products h h + h m + m h, relative error ~2^-16 before the
+ * storage rounding); FP64 storage uses FP64 FMAs.  The stored S is exactly
+ * symmetric in every format.
  * buf: device, >= symnmf_S_bytes(...) bytes, caller owned.  Temporary device
  * memory is allocated and freed inside the call.  Synchronises (fills the FP64
  * sums of ``out``).  EINVAL: T < 2, n < 1, bad row range, zero-variance
