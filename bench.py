@@ -125,15 +125,15 @@ def ttt_trace(ctx, S, k, params, init, max_steps, every, store):
     return [t_init + m / 1000.0 for m in ms], certified, t_init
 
 
-def ttt_scan(judge, store, nsave, f_ref, tol, every, times):
-    """First kept iterate with (judge(H) - f_ref) / f_ref <= tol: a coarse scan
+def ttt_scan(objective_of, store, nsave, f_ref, tol, every, times):
+    """First kept iterate with (objective_of(H) - f_ref) / f_ref <= tol: a coarse scan
     every 32 kept iterates, then bisection inside the first bracket (the
     objective of these runs decreases except for small oscillations)."""
     cache = {}
 
     def rel(j):
         if j not in cache:
-            cache[j] = (judge(store[j]) - f_ref) / f_ref
+            cache[j] = (objective_of(store[j]) - f_ref) / f_ref
         return cache[j]
 
     hit = None
@@ -156,10 +156,10 @@ def ttt_scan(judge, store, nsave, f_ref, tol, every, times):
     return entry
 
 
-def ttt_run(ctx, S, k, params, init, judge, f_ref, tol, max_steps, every, store):
-    """Trace from init(H), then the time to (judge(H_t) - f_ref) / f_ref <= tol."""
+def ttt_run(ctx, S, k, params, init, objective_of, f_ref, tol, max_steps, every, store):
+    """Trace from init(H), then the time to (objective_of(H_t) - f_ref) / f_ref <= tol."""
     times, certified, t_init = ttt_trace(ctx, S, k, params, init, max_steps, every, store)
-    entry = ttt_scan(judge, store, max_steps // every, f_ref, tol, every, times)
+    entry = ttt_scan(objective_of, store, max_steps // every, f_ref, tol, every, times)
     entry.update(init_seconds=round(t_init, 4), certified_at=certified, times=times)
     return entry
 
@@ -199,7 +199,7 @@ def time_to_tolerance(args):
     f_S is the objective on the FP32-stored S (MFMA products, FP64 sums across
     chunks) whatever S the variant iterates on; f_ref is the objective of the
     FP32 AdaGrad reference run certified by the stop rule (or stopped at
-    --ttt-ref-iters).  Every variant's iterates are kept in HBM and judged
+    --ttt-ref-iters).  Every variant's iterates are kept in HBM and evaluated
     after its timed run; the time of iterate H_t runs from the start of its
     initialisation to the copy of H_t (HIP events on the solver stream), with
     every check-time rule of the method applied.
@@ -222,7 +222,7 @@ def time_to_tolerance(args):
     S32 = stores["fp32"]
     eta = math.sqrt(S32.desc.mean / k)
 
-    def judge(H):
+    def objective_of(H):
         return sym.symnmf_objective(ctx, S32, H, k)[0]
 
     f_ref, rs, conv = reference_solve(ctx, S32, k, eta, 1, args.ttt_ref_iters)
@@ -232,7 +232,7 @@ def time_to_tolerance(args):
     store = torch.empty(args.ttt_max // every, n, k, device=dev)
     for v in variants:
         S = stores[v.split("-")[0]]
-        entry = ttt_run(ctx, S, k, variant_params(v, eta), lambda H: sym.symnmf_init_H(ctx, S, k, 1, H), judge,
+        entry = ttt_run(ctx, S, k, variant_params(v, eta), lambda H: sym.symnmf_init_H(ctx, S, k, 1, H), objective_of,
                         f_ref, args.ttt_tol, args.ttt_max, every, store)
         entry.pop("times")
         results["variants"][v] = entry
@@ -363,12 +363,12 @@ def warm_start_study(args):
         """random init run first (it is also the reference: f_ref is its
         certified iterate, or its last one), then the two warm starts; with
         ``extra`` ({name: S stored otherwise}) the three initialisations are
-        also run on those stores, judged on S."""
+        also run on those stores, evaluated on S."""
         nn = S.desc.n
         eta = math.sqrt(S.desc.mean / k_eval)
         params = variant_params("fp32", eta)
 
-        def judge(H):
+        def objective_of(H):
             return sym.symnmf_objective(ctx, S, H, k_eval)[0]
 
         every = 2
@@ -376,9 +376,9 @@ def warm_start_study(args):
         times, cert, t_init = ttt_trace(ctx, S, k_eval, params, lambda H: sym.symnmf_init_H(ctx, S, k_eval, seed, H),
                                         rand_steps, every, store)
         ref_slot = (cert + 1) // every - 1 if cert >= 0 else rand_steps // every - 1
-        f_ref = judge(store[ref_slot])
+        f_ref = objective_of(store[ref_slot])
         res = {"f_ref": f_ref, "ref_iters": (ref_slot + 1) * every, "ref_certified": cert >= 0}
-        res["random"] = ttt_scan(judge, store, rand_steps // every, f_ref, args.ttt_tol, every, times)
+        res["random"] = ttt_scan(objective_of, store, rand_steps // every, f_ref, args.ttt_tol, every, times)
         inits = {
             "coords": lambda H: sym.symnmf_warm_start(ctx, S, None, W, k_eval, WARM_OMEGA_SEED, H),
             "mlp": lambda H: sym.symnmf_warm_start(ctx, S, model, W, k_eval, WARM_OMEGA_SEED, H),
@@ -386,7 +386,7 @@ def warm_start_study(args):
         r_it, r_s = res["random"].get("iters"), res["random"].get("seconds")
         for name, init in inits.items():
             wt, wcert, w_init = ttt_trace(ctx, S, k_eval, params, init, warm_steps, every, store)
-            e = ttt_scan(judge, store, warm_steps // every, f_ref, args.ttt_tol, every, wt)
+            e = ttt_scan(objective_of, store, warm_steps // every, f_ref, args.ttt_tol, every, wt)
             e["init_seconds"] = round(w_init, 4)
             if r_it is not None:
                 if e.get("iters") is None or e["iters"] > 2 * r_it:
@@ -409,7 +409,7 @@ def warm_start_study(args):
             for name, init in xinits.items():
                 steps = rand_steps if name == "random" else warm_steps
                 wt, _, w_init = ttt_trace(ctx, Sx, k_eval, params, init, steps, every, store)
-                e = ttt_scan(judge, store, steps // every, f_ref, args.ttt_tol, every, wt)
+                e = ttt_scan(objective_of, store, steps // every, f_ref, args.ttt_tol, every, wt)
                 e["init_seconds"] = round(w_init, 4)
                 if r_s is not None and e.get("seconds"):
                     e["speedup_vs_fp32_random"] = round(r_s / e["seconds"], 3)

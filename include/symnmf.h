@@ -229,7 +229,7 @@ symnmf_status symnmf_state_stats(symnmf_ctx* ctx, symnmf_state* st, symnmf_stats
 symnmf_status symnmf_state_set_phi(symnmf_state* st, double phi);
 
 /* f(H) and E = f/||S_stored||^2 for any H (device n x k, float32 or float64),
- * the judge of results.  S H is accumulated in FP64: for FP32/BF16/FP8 storage
+ * the measure every result is compared by.  S H is accumulated in FP64: for FP32/BF16/FP8 storage
  * with float32 H and k in {16, 32} the MFMA products are summed in FP32 within
  * each 256-column chunk and in FP64 across chunks; otherwise every product is
  * accumulated in FP64.  The trace and Gram terms are FP64.  Synchronises. */
