@@ -526,8 +526,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU row sharding is a design "
-                                   "(DESIGN.md), not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this library runs on one GPU; row sharding over several GPUs is designed "
+                                   "but not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
