@@ -67,3 +67,19 @@ def test_trace_certification_matches_oracle_stop_rule():
     store = torch.empty(300, n, k, dtype=torch.float64, device=dev())
     _, cert = sym.symnmf_solve_trace(c, S, st, 3000, 10, store)
     assert res.converged and cert == res.t
+
+
+def test_probes_copy_and_read():
+    """The bandwidth probes: the copy reproduces its input; the read folds
+    every 16-byte vector with XOR (all-zero input gives all-zero words)."""
+    c = ctx()
+    n = 1 << 20
+    src = torch.arange(n, dtype=torch.float32, device=dev())
+    dst = torch.empty_like(src)
+    sym.symnmf_probe_copy(c, src, dst)
+    assert torch.equal(src, dst)
+    zeros = torch.zeros(n, dtype=torch.float32, device=dev())
+    sink = torch.full((4096,), -1, dtype=torch.int32, device=dev())
+    sym.symnmf_probe_read(c, zeros, sink)
+    torch.cuda.synchronize()
+    assert int(sink.abs().sum()) == 0

@@ -48,7 +48,7 @@ def _params32(k, seed, width=WIDTH, hidden=HIDDEN):
 @pytest.fixture(scope="module")
 def corr600():
     X = synth.c1_instance(3, T=2000, n=600, groups=8).X.numpy()
-    return o.abs_corr(o.standardise_columns(X))
+    return o.abs_corr(X)
 
 
 @pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp8"])
