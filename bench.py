@@ -304,29 +304,31 @@ def warm_start_study(args):
         sym.symnmf_canonical(ctx, Y, k, Xc)
         return Xc
 
-    out = {"family": args.warm_family, "n_train": n, "k": k, "T": args.warm_T, "groups": args.warm_groups,
-           "width": W, "hidden": HID}
+    out = {"family": args.warm_family, "n_train": args.warm_sizes or n, "n_heldout": n, "k": k, "T": args.warm_T,
+           "groups": args.warm_groups, "width": W, "hidden": HID}
     # 1. training pairs
     t0 = time.time()
     pairs = []
     train_seeds = list(range(args.warm_seed0, args.warm_seed0 + args.warm_train))
     ref_iters = []
+    sizes = [int(v) for v in args.warm_sizes.split(",")] if args.warm_sizes else [n]
     for i, seed in enumerate(train_seeds):
-        X = returns(seed, n)
+        ni = sizes[i % len(sizes)]
+        X = returns(seed, ni)
         S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
         del X
         eta = math.sqrt(S.desc.mean / k)
         # target: the solver's factorization from the network-free warm start
         # (it reaches lower objectives than random initialisation)
-        H0 = torch.empty(n, k, device=dev)
+        H0 = torch.empty(ni, k, device=dev)
         sym.symnmf_warm_start(ctx, S, None, W, k, WARM_OMEGA_SEED, H0)
         st = sym.symnmf_state_create(ctx, S, k, sym.symnmf_params_default(eta=eta, max_iter=args.warm_solve_iters),
                                      H0)
-        Hs = torch.empty(n, k, device=dev)
+        Hs = torch.empty(ni, k, device=dev)
         rs, conv = sym.symnmf_solve_to_tol(ctx, S, st, H_out=Hs)
         del st
         ref_iters.append(int(rs.t))
-        pairs.append((features(S, n), Hs))
+        pairs.append((features(S, ni), Hs))
         del S
         if (i + 1) % 10 == 0 or i + 1 == len(train_seeds):
             log(f"training instance {i + 1}/{len(train_seeds)} solved (t={rs.t} conv={conv} E={rs.E:.4e}) "
@@ -473,6 +475,7 @@ def main():
     ap.add_argument("--warm", action="store_true", help="learned warm start study instead of the step rate")
     ap.add_argument("--warm-family", default="panel", choices=["panel", "overlap"])
     ap.add_argument("--warm-n", type=int, default=20000)
+    ap.add_argument("--warm-sizes", default="", help="training instance sizes, cycled (default: --warm-n)")
     ap.add_argument("--warm-k", type=int, default=64)
     ap.add_argument("--warm-T", type=int, default=1000)
     ap.add_argument("--warm-groups", type=int, default=64)
