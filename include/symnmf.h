@@ -184,7 +184,7 @@ int64_t symnmf_S_offset(int64_t r, int64_t c, int64_t rows_pad, int64_t ld, int3
  * buf: device, >= symnmf_S_bytes(...) bytes, caller owned.  Temporary device
  * memory is allocated and freed inside the call.  Synchronises (fills the FP64
  * sums of ``out``).  EINVAL: T < 2, n < 1, bad row range, zero-variance
- * column, floor(qT) < 1. */
+ * column, floor(qT) < 1.  ENUMERIC: X holds a NaN or an infinity. */
 symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuild_params* p,
                              void* buf, int64_t buf_bytes, symnmf_S* out);
 

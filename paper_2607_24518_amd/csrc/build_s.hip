@@ -44,11 +44,30 @@ __global__ __launch_bounds__(256) void standardise_kernel(const float* __restric
     __syncthreads();
     const double c = sqrt(red[0][lc] + red[1][lc] + red[2][lc] + red[3][lc]);
     if (!valid) return;
+    if (!isfinite(c)) {                      // a NaN or infinity in the column
+        if (ph == 0) atomicOr(bad, BAD_NONFINITE);
+        return;
+    }
     if (!(c > 0.0)) {
         if (ph == 0) atomicAdd(bad, 1);
         return;
     }
     for (int64_t t = ph; t < T; t += 4) Z[t * ldz + col] = (ZT)(((double)X[t * n + col] - mean) / c);
+}
+
+// Raises BAD_NONFINITE in *flag when any of the count values is NaN or infinite.
+__global__ __launch_bounds__(256) void nonfinite_kernel(const float* __restrict__ X, int64_t count,
+                                                        int32_t* __restrict__ flag) {
+    bool hit = false;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+        hit |= !isfinite(X[i]);
+    if (hit) atomicOr(flag, BAD_NONFINITE);
+}
+
+hipError_t launch_check_finite(const float* X, int64_t count, int32_t* flag, hipStream_t stream) {
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+    if (blocks > 0) hipLaunchKernelGGL(nonfinite_kernel, dim3(blocks), dim3(256), 0, stream, X, count, flag);
+    return hipGetLastError();
 }
 
 hipError_t launch_standardise(const float* X, int64_t T, int64_t n, void* Z, int z_f64, int64_t ldz, int32_t* bad,

@@ -309,6 +309,10 @@ struct BuildOut {
     void* data; float* scale; float* diag;
     int64_t rows, rows_pad, ld, n, row0; int32_t dtype; int64_t panel_rows;
 };
+// Flag bit set by the input checks of the S build for a non-finite X entry;
+// the low bits count zero-variance columns.
+constexpr int32_t BAD_NONFINITE = 1 << 30;
+hipError_t launch_check_finite(const float* X, int64_t count, int32_t* flag, hipStream_t stream);
 hipError_t launch_standardise(const float* X, int64_t T, int64_t n, void* Z, int z_f64, int64_t ldz, int32_t* bad,
                               hipStream_t stream);
 // TPDM: Omega (n_exc x ldz, FP32 or FP64) = column-normalised angular rows.

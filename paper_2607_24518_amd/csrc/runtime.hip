@@ -279,10 +279,17 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
     chk(hipMemsetAsync(bad, 0, 4, st));
     chk(hipMemsetAsync(buf, 0, L.total, st));
     if (p->kind == SYMNMF_ABS_CORR) chk(launch_standardise(X, T, n, Z, z_f64, ldz, (int32_t*)bad, st));
-    else chk(launch_tpdm_omega(X, T, n, p->lower_tail, Z, z_f64, ldz, K, work, st));
+    else {
+        chk(launch_check_finite(X, T * n, (int32_t*)bad, st));
+        chk(launch_tpdm_omega(X, T, n, p->lower_tail, Z, z_f64, ldz, K, work, st));
+    }
     int32_t hbad = 0;
     chk(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
     chk(hipStreamSynchronize(st));
+    if (e == hipSuccess && (hbad & BAD_NONFINITE)) {
+        cleanup();
+        return fail(ctx, SYMNMF_ENUMERIC, "build_S: X holds a non-finite value");
+    }
     if (e == hipSuccess && hbad) {
         cleanup();
         return fail(ctx, SYMNMF_EINVAL, "build_S: %d zero-variance column(s)", hbad);

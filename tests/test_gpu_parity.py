@@ -103,6 +103,26 @@ def test_build_rejects_constant_column_and_bad_shapes():
         sym.symnmf_build_S(ctx(), to_dev(X[:10, :4] + 1.0), kind=sym.TPDM, q=0.05)   # floor(qT) = 0
 
 
+def test_build_and_load_report_nonfinite_input():
+    """A NaN or infinity in X (either kind of S) or in a loaded S is a numeric
+    error, not a zero-variance column."""
+    c = ctx()
+    X = np.random.default_rng(0).random((60, 30)).astype(np.float32)
+    for bad in (float("nan"), float("inf")):
+        Xb = X.copy()
+        Xb[17, 11] = bad
+        for kw in (dict(kind=sym.ABS_CORR), dict(kind=sym.TPDM, q=0.2)):
+            with pytest.raises(sym.SymnmfError) as e:
+                sym.symnmf_build_S(c, to_dev(Xb), **kw)
+            assert e.value.code == sym.ENUMERIC, (bad, kw)
+    Snp = o.abs_corr(X.astype(np.float64))
+    Snp[4, 9] = float("nan")
+    for dtype in (sym.S_FP64, sym.S_FP32, sym.S_BF16, sym.S_FP8):
+        with pytest.raises(sym.SymnmfError) as e:
+            sym.symnmf_S_load(c, to_dev(Snp, torch.float64), dtype=dtype, fp8_panel_rows=16)
+        assert e.value.code == sym.ENUMERIC
+
+
 def test_init_H_matches_oracle(S600):
     c = ctx()
     S = sym.symnmf_S_load(c, to_dev(S600, torch.float64), dtype=sym.S_FP32)
@@ -329,6 +349,37 @@ def test_solve_to_tol_certifies_planted_factorisation():
     assert conv and ost.converged and stats.t == ost.t
     assert stats.E < 1e-12 and stats.kkt < 1e-10 * 1e4 / 300
     assert o.subspace_error(from_dev(H), Hs) < 1e-6
+
+
+def test_stop_rule_rejects_zero_factor_through_the_loss_gate():
+    """From H = 0 the gradient, the KKT measure and the progress are all zero;
+    the loss gate alone keeps the stop rule from certifying it, as in the
+    oracle (opened gate: certified at the first check past the warm-up)."""
+    c = ctx()
+    Snp = o.abs_corr(_corr_instance(n=300, T=200, groups=3, seed=4))
+    S = sym.symnmf_S_load(c, to_dev(Snp, torch.float64), dtype=sym.S_FP32)
+    H0 = torch.zeros(300, 4, device=dev())
+    st = sym.symnmf_state_create(c, S, 4, sym.symnmf_params_default(eta=0.05, max_iter=300), H0)
+    stats, conv = sym.symnmf_solve_to_tol(c, S, st)
+    assert not conv and stats.t == 300 and stats.E == pytest.approx(1.0, rel=1e-12) and stats.kkt == 0.0
+    st = sym.symnmf_state_create(c, S, 4, sym.symnmf_params_default(eta=0.05, max_iter=300, tau_E=1.5), H0)
+    stats, conv = sym.symnmf_solve_to_tol(c, S, st)
+    _, ost = o.Solver(Snp, 4, o.Params(eta=0.05, max_iter=300, tau_E=1.5), np.zeros((300, 4))).solve()
+    assert conv and ost.converged and stats.t == ost.t == 50
+
+
+def test_objective_near_exact_factorisation():
+    """E ~ 1e-6: the trace terms cancel to six digits, and the FP64-accumulating
+    objective still matches the explicit n x n residual."""
+    Hs = synth.planted_factor(5, 700, 6).numpy()
+    Snp = Hs @ Hs.T
+    H = Hs * (1.0 + 1e-3 * np.random.default_rng(3).standard_normal(Hs.shape))
+    c = ctx()
+    S = sym.symnmf_S_load(c, to_dev(Snp, torch.float64), dtype=sym.S_FP64)
+    f, E = sym.symnmf_objective(c, S, to_dev(H, torch.float64), 6)
+    f_ex = o.objective_explicit(Snp, H)
+    assert 1e-7 < f_ex / (Snp * Snp).sum() < 1e-5
+    assert f == pytest.approx(f_ex, rel=1e-8)
 
 
 def test_objective_fp64_accumulation(S600):

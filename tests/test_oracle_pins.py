@@ -57,6 +57,38 @@ def test_zero_factor_is_critical_with_unit_error():
     assert o.objective_trace(S, H) / (S * S).sum() == 1.0
 
 
+def test_stop_rule_rejects_zero_factor_through_the_loss_gate():
+    """H = 0 is a critical point (zero gradient, zero KKT measure, no progress),
+    so only the loss gate E < tau_E keeps the stop rule from certifying it
+    (section "Convergence certification")."""
+    S = o.abs_corr(synth.c1_instance(0, T=300, n=40, groups=4).X.numpy())
+    H0 = np.zeros((40, 4))
+    _, st = o.Solver(S, 4, o.Params(eta=0.05, max_iter=300), H0).solve()
+    assert not st.converged and st.E == 1.0 and st.kkt == 0.0
+    # the same run with the loss gate opened is certified at the first check past the warm-up (t = 50)
+    _, st = o.Solver(S, 4, o.Params(eta=0.05, max_iter=300, tau_E=1.5), H0).solve()
+    assert st.converged and st.t == 50
+
+
+def test_trace_form_cancellation_magnitude():
+    """Near an exact factorization the three trace terms cancel: evaluated in
+    FP32 the loss carries a relative error of order 2 eps / E (section
+    "Memory-Efficient Loss Reformulation", numerical consideration), while the
+    oracle's FP64 evaluation agrees with the explicit n x n residual."""
+    Hs = synth.planted_factor(5, 400, 6).numpy()
+    S = Hs @ Hs.T
+    H = Hs * (1.0 + 1e-3 * np.random.default_rng(3).standard_normal(Hs.shape))
+    f_ex = o.objective_explicit(S, H)
+    E = f_ex / (S * S).sum()
+    assert 1e-7 < E < 1e-5
+    assert abs(o.objective_trace(S, H) - f_ex) / f_ex < 20 * 2.2e-16 / E
+    S32, H32 = S.astype(np.float32), H.astype(np.float32)
+    G32 = H32.T @ H32
+    f32 = float((S32 * S32).sum() - np.float32(2) * (H32 * (S32 @ H32)).sum() + (G32 * G32).sum())
+    rel32 = abs(f32 - f_ex) / f_ex
+    assert 0.05 * 2 * 1.19e-7 / E < rel32 < 20 * 2 * 1.19e-7 / E
+
+
 def test_permutation_invariance_and_no_diagonal_scaling():
     r = np.random.default_rng(2)
     S = _rand_sym(30, 5)
