@@ -89,7 +89,11 @@ typedef struct {
     int64_t rows;            /* rows to build: n for the full matrix, fewer for a row panel */
     double q;                /* TPDM: exceedance fraction, n_exc = floor(q T) >= 1 */
     int32_t lower_tail;      /* TPDM: 1 = lower tail (transform -X), 0 = upper   */
-    int32_t reserved0;
+    int32_t raw_marginals;   /* TPDM: 0 = rank transform to Pareto(2) margins;
+                              * 1 = X used as given (it must already have
+                              * Pareto-type margins and be >= 0 in the chosen
+                              * tail orientation), the construction of the
+                              * appendix's benchmark matrices               */
     int64_t fp8_panel_rows;  /* FP8: rows per scale panel (>= 1)                 */
 } symnmf_sbuild_params;
 
@@ -175,7 +179,9 @@ int64_t symnmf_S_offset(int64_t r, int64_t c, int64_t rows_pad, int64_t ld, int3
  * TPDM (section "Empirical Estimation"): per-column ranks (ties to the lower
  *   sample), Pareto(2) margins x = (1 - r/(T+1))^-1/2, FP64 radial norms, the
  *   floor(qT) largest kept (ties to the lower sample), angular rows Omega,
- *   S = D^-1/2 Omega^T Omega D^-1/2 by the same GEMM, S_ii = 1.
+ *   S = D^-1/2 Omega^T Omega D^-1/2 by the same GEMM, S_ii = 1.  With
+ *   raw_marginals the rank step is skipped and the polar transform is taken
+ *   of (+-)X itself (appendix "Benchmark Data Generation", TPDM construction).
  * The GEMM accumulates in FP32: FP32 storage multiplies on the FP32 matrix
  * cores; BF16 / FP8 storage splits the operand into two bf16 planes
  * (z = h + m, products h h + h m + m h, relative error ~2^-16 before the
@@ -184,7 +190,9 @@ int64_t symnmf_S_offset(int64_t r, int64_t c, int64_t rows_pad, int64_t ld, int3
  * buf: device, >= symnmf_S_bytes(...) bytes, caller owned.  Temporary device
  * memory is allocated and freed inside the call.  Synchronises (fills the FP64
  * sums of ``out``).  EINVAL: T < 2, n < 1, bad row range, zero-variance
- * column, floor(qT) < 1.  ENUMERIC: X holds a NaN or an infinity. */
+ * column, floor(qT) < 1, raw_marginals not 0/1, a raw-marginal X < 0 in the
+ * tail orientation.  EUNSUPPORTED: the rank transform with T > 32768.
+ * ENUMERIC: X holds a NaN or an infinity. */
 symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuild_params* p,
                              void* buf, int64_t buf_bytes, symnmf_S* out);
 

@@ -141,12 +141,14 @@ def pareto2_from_ranks(R, T):
     return (1.0 - np.asarray(R, dtype=np.float64) / (T + 1.0)) ** -0.5
 
 
-def tpdm(X, q: float, lower_tail: bool = True, return_parts: bool = False):
+def tpdm(X, q: float, lower_tail: bool = True, return_parts: bool = False, raw_marginals: bool = False):
     """Empirical TPDM, unit-diagonal normalised.
 
     Steps (section "Empirical Estimation"; appendix TPDM construction):
     1. one-sided tail: the lower tail of X is the upper tail of -X;
-    2. rank-transform each column to Pareto(2) margins;
+    2. rank-transform each column to Pareto(2) margins (skipped when
+       raw_marginals: the appendix's benchmark matrices apply the polar
+       transform to the Pareto(2) factor-model samples as generated);
     3. polar coordinates of every sample: r_t = ||x_t||_2, w_t = x_t / r_t;
     4. keep the n_exc = floor(q T) samples with the largest r_t (ties go to
        the lower sample index); their w_t are the rows of Omega;
@@ -155,7 +157,7 @@ def tpdm(X, q: float, lower_tail: bool = True, return_parts: bool = False):
     X = np.asarray(X, dtype=np.float64)
     T, n = X.shape
     Y = -X if lower_tail else X
-    P = pareto2_from_ranks(rank_columns(Y), T)
+    P = Y if raw_marginals else pareto2_from_ranks(rank_columns(Y), T)
     r = np.sqrt((P * P).sum(axis=1))
     n_exc = int(math.floor(q * T))
     if n_exc < 1:

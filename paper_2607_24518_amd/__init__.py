@@ -26,7 +26,7 @@ c_i32, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint
 
 class symnmf_sbuild_params(ctypes.Structure):
     _fields_ = [("kind", c_i32), ("dtype", c_i32), ("n", c_i64), ("T", c_i64), ("row0", c_i64),
-                ("rows", c_i64), ("q", c_dbl), ("lower_tail", c_i32), ("reserved0", c_i32),
+                ("rows", c_i64), ("q", c_dbl), ("lower_tail", c_i32), ("raw_marginals", c_i32),
                 ("fp8_panel_rows", c_i64)]
 
 
@@ -209,12 +209,13 @@ def _alloc_bytes(nbytes, device):
 
 
 def symnmf_build_S(ctx, X, kind=ABS_CORR, dtype=S_FP32, row0=0, rows=None, q=0.05, lower_tail=1,
-                   fp8_panel_rows=256) -> Matrix:
+                   fp8_panel_rows=256, raw_marginals=0) -> Matrix:
     """X: device float32 tensor T x n (contiguous)."""
     T, n = X.shape
     rows = n - row0 if rows is None else rows
     p = symnmf_sbuild_params(kind=kind, dtype=dtype, n=n, T=T, row0=row0, rows=rows, q=q,
-                             lower_tail=lower_tail, fp8_panel_rows=fp8_panel_rows)
+                             lower_tail=lower_tail, raw_marginals=raw_marginals,
+                             fp8_panel_rows=fp8_panel_rows)
     nbytes = symnmf_S_bytes(rows, n, dtype, fp8_panel_rows)
     if nbytes < 0:
         raise SymnmfError(EINVAL, "bad S shape")

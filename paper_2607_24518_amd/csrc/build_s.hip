@@ -55,18 +55,23 @@ __global__ __launch_bounds__(256) void standardise_kernel(const float* __restric
     for (int64_t t = ph; t < T; t += 4) Z[t * ldz + col] = (ZT)(((double)X[t * n + col] - mean) / c);
 }
 
-// Raises BAD_NONFINITE in *flag when any of the count values is NaN or infinite.
-__global__ __launch_bounds__(256) void nonfinite_kernel(const float* __restrict__ X, int64_t count,
-                                                        int32_t* __restrict__ flag) {
-    bool hit = false;
-    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
-        hit |= !isfinite(X[i]);
-    if (hit) atomicOr(flag, BAD_NONFINITE);
+// Raises BAD_NONFINITE in *flag when any of the count values is NaN or
+// infinite and, when sign != 0, BAD_NEGATIVE when some sign * X[i] < 0.
+__global__ __launch_bounds__(256) void check_input_kernel(const float* __restrict__ X, int64_t count, float sign,
+                                                          int32_t* __restrict__ flag) {
+    bool nonfinite = false, negative = false;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) {
+        const float v = X[i];
+        nonfinite |= !isfinite(v);
+        negative |= sign * v < 0.0f;
+    }
+    if (nonfinite) atomicOr(flag, BAD_NONFINITE);
+    if (negative) atomicOr(flag, BAD_NEGATIVE);
 }
 
-hipError_t launch_check_finite(const float* X, int64_t count, int32_t* flag, hipStream_t stream) {
+hipError_t launch_check_input(const float* X, int64_t count, float sign, int32_t* flag, hipStream_t stream) {
     const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
-    if (blocks > 0) hipLaunchKernelGGL(nonfinite_kernel, dim3(blocks), dim3(256), 0, stream, X, count, flag);
+    if (blocks > 0) hipLaunchKernelGGL(check_input_kernel, dim3(blocks), dim3(256), 0, stream, X, count, sign, flag);
     return hipGetLastError();
 }
 
@@ -206,18 +211,65 @@ __global__ __launch_bounds__(256) void omega_kernel(const int32_t* __restrict__ 
     }
 }
 
-int64_t tpdm_work_bytes(int64_t T, int64_t n) {
-    return round_up(T * n * 4, 256) * 2 + round_up(T * 8, 256) + round_up(T * 4, 256) + round_up(select_tmp_bytes(), 256) + 256;
+// Raw marginals: radial norm of sample t straight from row t of X, FP64.
+__global__ __launch_bounds__(256) void norms_raw_kernel(const float* __restrict__ X, int64_t n,
+                                                        double* __restrict__ norms) {
+    __shared__ double red[4];
+    const int64_t t = blockIdx.x;
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const double x = (double)X[t * n + j];
+        s += x * x;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) norms[t] = sqrt(red[0] + red[1] + red[2] + red[3]);
 }
 
-hipError_t launch_tpdm_omega(const float* X, int64_t T, int64_t n, int lower, void* Omega, int z_f64,
+// Raw marginals: Omega_aj = sign * X[t_a][j] / ||x_{t_a}||, column j scaled to unit norm.
+template <typename ZT>
+__global__ __launch_bounds__(256) void omega_raw_kernel(const float* __restrict__ X, int64_t n, float sign,
+                                                        const double* __restrict__ norms,
+                                                        const int32_t* __restrict__ idx, int64_t n_exc,
+                                                        ZT* __restrict__ Om, int64_t ldz) {
+    __shared__ double red[4][64];
+    const int lc = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int64_t col = blockIdx.x * 64 + lc;
+    double ss = 0.0;
+    if (col < n)
+        for (int64_t a = ph; a < n_exc; a += 4) {
+            const int64_t t = idx[a];
+            const double w = (double)X[t * n + col] / norms[t];
+            ss += w * w;
+        }
+    red[ph][lc] = ss;
+    __syncthreads();
+    const double c = sqrt(red[0][lc] + red[1][lc] + red[2][lc] + red[3][lc]);
+    if (col >= n) return;
+    for (int64_t a = ph; a < n_exc; a += 4) {
+        const int64_t t = idx[a];
+        const double w = (double)sign * (double)X[t * n + col] / norms[t];
+        Om[a * ldz + col] = (ZT)(w / c);
+    }
+}
+
+int64_t tpdm_work_bytes(int64_t T, int64_t n, int raw) {
+    const int64_t planes = raw ? 0 : round_up(T * n * 4, 256) * 2;
+    return planes + round_up(T * 8, 256) + round_up(T * 4, 256) + round_up(select_tmp_bytes(), 256) + 256;
+}
+
+hipError_t launch_tpdm_omega(const float* X, int64_t T, int64_t n, int lower, int raw, void* Omega, int z_f64,
                              int64_t ldz, int64_t n_exc, void* work, hipStream_t stream) {
-    if (T > RANK_MAX_T) return hipErrorInvalidValue;
+    if (!raw && T > RANK_MAX_T) return hipErrorInvalidValue;
     char* w = (char*)work;
     float* Xt = (float*)w;                       // n x T, later reused for Rt (T x n)
-    w += round_up(T * n * 4, 256);
-    int32_t* R = (int32_t*)w;                    // n x T
-    w += round_up(T * n * 4, 256);
+    int32_t* R = nullptr;                        // n x T
+    if (!raw) {
+        w += round_up(T * n * 4, 256);
+        R = (int32_t*)w;
+        w += round_up(T * n * 4, 256);
+    }
     double* norms = (double*)w;
     w += round_up(T * 8, 256);
     int32_t* idx = (int32_t*)w;
@@ -226,6 +278,21 @@ hipError_t launch_tpdm_omega(const float* X, int64_t T, int64_t n, int lower, vo
     w += round_up(select_tmp_bytes(), 256);
     double* vstar = (double*)w;
     dim3 tb(256);
+    if (raw) {
+        const float sign = lower ? -1.0f : 1.0f;
+        hipLaunchKernelGGL(norms_raw_kernel, dim3(T), tb, 0, stream, X, n, norms);
+        hipError_t e = launch_select(norms, 1, 0, T, T - n_exc, sel, vstar, stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(64), 0, stream, (const double*)norms, T, n_exc,
+                           (const double*)vstar, idx);
+        if (z_f64)
+            hipLaunchKernelGGL(omega_raw_kernel<double>, dim3((n + 63) / 64), tb, 0, stream, X, n, sign,
+                               (const double*)norms, (const int32_t*)idx, n_exc, (double*)Omega, ldz);
+        else
+            hipLaunchKernelGGL(omega_raw_kernel<float>, dim3((n + 63) / 64), tb, 0, stream, X, n, sign,
+                               (const double*)norms, (const int32_t*)idx, n_exc, (float*)Omega, ldz);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(transpose_kernel<float>, dim3((n + 63) / 64, (T + 63) / 64), tb, 0, stream, X, T, n, Xt,
                        lower ? -1.0f : 1.0f);
     int P2 = 1;

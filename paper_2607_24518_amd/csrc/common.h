@@ -309,16 +309,18 @@ struct BuildOut {
     void* data; float* scale; float* diag;
     int64_t rows, rows_pad, ld, n, row0; int32_t dtype; int64_t panel_rows;
 };
-// Flag bit set by the input checks of the S build for a non-finite X entry;
-// the low bits count zero-variance columns.
+// Flag bits set by the input checks of the S build: a non-finite X entry, a
+// negative entry where raw TPDM marginals need X >= 0; the low bits count
+// zero-variance columns.
 constexpr int32_t BAD_NONFINITE = 1 << 30;
-hipError_t launch_check_finite(const float* X, int64_t count, int32_t* flag, hipStream_t stream);
+constexpr int32_t BAD_NEGATIVE = 1 << 29;
+hipError_t launch_check_input(const float* X, int64_t count, float sign, int32_t* flag, hipStream_t stream);
 hipError_t launch_standardise(const float* X, int64_t T, int64_t n, void* Z, int z_f64, int64_t ldz, int32_t* bad,
                               hipStream_t stream);
 // TPDM: Omega (n_exc x ldz, FP32 or FP64) = column-normalised angular rows.
-hipError_t launch_tpdm_omega(const float* X, int64_t T, int64_t n, int lower, void* Omega, int z_f64,
+hipError_t launch_tpdm_omega(const float* X, int64_t T, int64_t n, int lower, int raw, void* Omega, int z_f64,
                              int64_t ldz, int64_t n_exc, void* work, hipStream_t stream);
-int64_t tpdm_work_bytes(int64_t T, int64_t n);
+int64_t tpdm_work_bytes(int64_t T, int64_t n, int raw);
 // sums: device FP64 array of syrk_sum_words(o) words; [0..2] = sum S, sum S^2,
 // sum S_stored^2 on return.  panel_max: FP8 only, zeroed, one word per panel.
 int64_t syrk_sum_words(const BuildOut& o);

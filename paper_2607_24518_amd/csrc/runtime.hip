@@ -240,7 +240,10 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
         if (!(p->q > 0.0 && p->q <= 1.0)) return fail(ctx, SYMNMF_EINVAL, "build_S: q must be in (0, 1]");
         K = (int64_t)std::floor(p->q * (double)T);
         if (K < 1) return fail(ctx, SYMNMF_EINVAL, "build_S: floor(q T) = 0 exceedances");
-        if (T > 32768) return fail(ctx, SYMNMF_EUNSUPPORTED, "build_S: TPDM supports T <= 32768");
+        if (p->raw_marginals != 0 && p->raw_marginals != 1)
+            return fail(ctx, SYMNMF_EINVAL, "build_S: raw_marginals must be 0 or 1");
+        if (!p->raw_marginals && T > 32768)
+            return fail(ctx, SYMNMF_EUNSUPPORTED, "build_S: the rank transform supports T <= 32768");
     }
     const Layout L = s_layout(p->rows, n, p->dtype, p->fp8_panel_rows);
     if (buf_bytes < L.total)
@@ -269,7 +272,7 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
     chk(hipMalloc(&sums, nsum * 8));
     chk(hipMalloc(&pmax, panels * 4));
     chk(hipMalloc(&bad, 4));
-    if (p->kind == SYMNMF_TPDM) chk(hipMalloc(&work, tpdm_work_bytes(T, n)));
+    if (p->kind == SYMNMF_TPDM) chk(hipMalloc(&work, tpdm_work_bytes(T, n, p->raw_marginals)));
     if (e != hipSuccess) {
         cleanup();
         return fail(ctx, SYMNMF_ENOMEM, "build_S: device allocation failed: %s", hipGetErrorString(e));
@@ -280,8 +283,9 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
     chk(hipMemsetAsync(buf, 0, L.total, st));
     if (p->kind == SYMNMF_ABS_CORR) chk(launch_standardise(X, T, n, Z, z_f64, ldz, (int32_t*)bad, st));
     else {
-        chk(launch_check_finite(X, T * n, (int32_t*)bad, st));
-        chk(launch_tpdm_omega(X, T, n, p->lower_tail, Z, z_f64, ldz, K, work, st));
+        const float sign = p->raw_marginals ? (p->lower_tail ? -1.0f : 1.0f) : 0.0f;
+        chk(launch_check_input(X, T * n, sign, (int32_t*)bad, st));
+        chk(launch_tpdm_omega(X, T, n, p->lower_tail, p->raw_marginals, Z, z_f64, ldz, K, work, st));
     }
     int32_t hbad = 0;
     chk(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
@@ -289,6 +293,10 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
     if (e == hipSuccess && (hbad & BAD_NONFINITE)) {
         cleanup();
         return fail(ctx, SYMNMF_ENUMERIC, "build_S: X holds a non-finite value");
+    }
+    if (e == hipSuccess && (hbad & BAD_NEGATIVE)) {
+        cleanup();
+        return fail(ctx, SYMNMF_EINVAL, "build_S: raw TPDM marginals need X >= 0 in the chosen tail orientation");
     }
     if (e == hipSuccess && hbad) {
         cleanup();

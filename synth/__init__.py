@@ -24,6 +24,10 @@ instance families used by the tests and the benchmark are:
   factor of loading 0.4; Gaussian factors and noise scaled by 0.5.
 * ``panel_returns`` - the same recipe generated in column blocks with one seed
   per block, so any column range can be regenerated on its own.
+* ``paper_benchmark`` - the appendix's own benchmark matrices: floor(sqrt(n))
+  groups plus the common factor, 40000 samples; Gaussian factors and unit
+  Gaussian noise for the correlation type, i.i.d. Pareto(2) factors and
+  0.3 * Pareto(2) noise for the TPDM type.
 
 Randomness comes from torch's generators inside ``torch.random.fork_rng`` so
 the global RNG state is untouched; a given (seed, device type) pair always
@@ -38,7 +42,7 @@ import torch
 
 __all__ = [
     "Instance", "c1_instance", "tpdm_returns", "overlap_returns",
-    "panel_returns", "planted_factor", "random_state",
+    "panel_returns", "paper_benchmark", "planted_factor", "random_state",
 ]
 
 
@@ -197,6 +201,31 @@ def panel_returns(seed: int = 0, T: int = 1000, n: int = 1_000_000, groups: int 
         labels[s0 - col0:s1 - col0] = lab[s0 - lo:s1 - lo]
         A[s0 - col0:s1 - col0] = Ab[s0 - lo:s1 - lo]
     return Instance(X, labels, torch.arange(col0, col0 + cols), A)
+
+
+def _pareto2(shape, device) -> torch.Tensor:
+    """Standard Pareto(alpha=2) draws, P(X > x) = x^-2 for x >= 1."""
+    return (1.0 - torch.rand(shape, dtype=torch.float64, device=device)) ** -0.5
+
+
+def paper_benchmark(seed: int, n: int, kind: str, T: int = 40000, device="cpu") -> Instance:
+    """X = Z A^T + noise with the appendix's mixing matrix (common factor plus
+    floor(sqrt(n)) groups).  kind "corr": Z ~ N(0, 1), noise ~ N(0, 1);
+    kind "tpdm": Z ~ Pareto(2), noise ~ 0.3 Pareto(2), all i.i.d."""
+    if kind not in ("corr", "tpdm"):
+        raise ValueError(kind)
+    ctx, dev = _fork(device, seed)
+    with ctx:
+        torch.manual_seed(seed)
+        A, labels, perm = _paper_mixing(n, int(math.isqrt(n)), True)
+        Ad = A.to(dev, torch.float64)
+        if kind == "corr":
+            X = torch.randn(T, A.shape[1], dtype=torch.float64, device=dev) @ Ad.T
+            X += torch.randn(T, n, dtype=torch.float64, device=dev)
+        else:
+            X = _pareto2((T, A.shape[1]), dev) @ Ad.T
+            X += 0.3 * _pareto2((T, n), dev)
+    return Instance(X.float().contiguous(), labels, perm, A)
 
 
 def planted_factor(seed: int, n: int, k: int, anchor_scale: float = 1.0) -> torch.Tensor:

@@ -89,6 +89,40 @@ def test_build_tpdm(dtype, tol):
     assert np.all(np.diag(M) == 1.0)
 
 
+@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-12), ("fp32", 3e-6)])
+def test_build_tpdm_raw_marginals(dtype, tol):
+    """The appendix's benchmark construction: polar transform of the Pareto
+    factor-model samples as generated (no rank step); the lower tail of -X is
+    the upper tail of X."""
+    X = synth.paper_benchmark(3, 300, "tpdm", T=8000).X.numpy()
+    ref = o.tpdm(X, q=0.01, lower_tail=False, raw_marginals=True)
+    c = ctx()
+    S = sym.symnmf_build_S(c, to_dev(X), kind=sym.TPDM, dtype=sym.DTYPES[dtype], q=0.01, lower_tail=0,
+                           raw_marginals=1)
+    M = stored_numpy(S)
+    assert np.max(np.abs(M - ref)) < tol
+    assert np.all(np.diag(M) == 1.0)
+    S2 = sym.symnmf_build_S(c, to_dev(-X), kind=sym.TPDM, dtype=sym.DTYPES[dtype], q=0.01, lower_tail=1,
+                            raw_marginals=1)
+    assert np.array_equal(stored_numpy(S2), M)
+
+
+def test_build_tpdm_raw_marginals_paper_sample_count():
+    """40000 samples (beyond the rank transform's limit), n = 1000, top 1 %:
+    the matrix of the paper's spectral table at n = 1000."""
+    X = synth.paper_benchmark(7, 1000, "tpdm").X.numpy()
+    ref = o.tpdm(X, q=0.01, lower_tail=False, raw_marginals=True)
+    c = ctx()
+    S = sym.symnmf_build_S(c, to_dev(X), kind=sym.TPDM, dtype=sym.S_FP32, q=0.01, lower_tail=0, raw_marginals=1)
+    assert np.max(np.abs(stored_numpy(S) - ref)) < 3e-6
+    with pytest.raises(sym.SymnmfError) as e:            # the rank transform stops at T = 32768
+        sym.symnmf_build_S(c, to_dev(X), kind=sym.TPDM, q=0.01, lower_tail=0)
+    assert e.value.code == sym.EUNSUPPORTED
+    with pytest.raises(sym.SymnmfError) as e:            # raw marginals need X >= 0 in the tail orientation
+        sym.symnmf_build_S(c, to_dev(X), kind=sym.TPDM, q=0.01, lower_tail=1, raw_marginals=1)
+    assert e.value.code == sym.EINVAL
+
+
 def test_build_rejects_constant_column_and_bad_shapes():
     X = np.random.default_rng(0).random((50, 20)).astype(np.float32)
     X[:, 3] = 2.0
