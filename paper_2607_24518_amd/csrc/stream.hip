@@ -220,8 +220,12 @@ hipError_t launch_h_image(const float* H, int32_t stype, int64_t k, int64_t n_ch
 //   applies the panel scale) and the diagonal is stored as 0 (added back from
 //   the FP32 diagonal).
 // DB: two LDS image buffers (the next image is written while the current one
-// is read).  PF: the next image is fetched into registers at the start of a
-// unit (otherwise it is copied at the unit boundary).
+// is read); PF: the next image is then fetched into registers at the start of
+// a unit (otherwise it is copied at the unit boundary).  Without DB the one
+// buffer is refilled in QP parts: every (plane, 16-column) block of the image
+// holds its sub-steps in order, so once all waves are past the sub-steps of
+// part r (a barrier) the next image's part r is written over it (the last part
+// at the unit's end); each part is fetched into registers one part ahead.
 // ---------------------------------------------------------------------------
 // ACC64: FP32 MFMA sums within each 256-column chunk, added into FP64
 // accumulators at every chunk boundary; the partials are written as doubles
@@ -242,12 +246,19 @@ __global__ __launch_bounds__(TALL ? 512 : 256, TALL ? 1 : 2) void stream_mfma(co
     constexpr int NV = IS::NV;
     constexpr int CPT = NV / NTHR;                         // image vectors per thread
     static_assert(NV % NTHR == 0, "image vectors must split evenly over the threads");
+    constexpr bool SPLIT = !DB;                            // single buffer, refilled in parts
+    constexpr int QP = 4;                                  // parts per image
+    constexpr int NSV = NV / ((KIND == 0 ? 1 : 3) * NT);   // vectors per (plane, 16-column) block
+    constexpr int HSV = NSV / QP;                          // ... in one part of its sub-steps
+    constexpr int CPH = CPT / QP;                          // image vectors per thread and part
+    static_assert(!SPLIT || (CPT % QP == 0 && NSV % QP == 0), "image parts must split evenly");
     constexpr int NS = KIND == 0 ? 16 : (KIND == 1 ? 8 : 4);
     constexpr int EB = KIND == 0 ? 4 : (KIND == 1 ? 2 : 1);
     // S prefetch ring and distance (sub-steps): deeper for FP32 S, whose sub-steps
     // are the slowest, to keep more bytes in flight per wave
     constexpr int RING = (KIND <= 1 && NT <= 2 && !ACC64) ? RING_F32 : 4, D = RING - 1;
     static_assert(NS % RING == 0, "ring must divide the sub-steps of a unit");
+    static_assert(!SPLIT || NS % QP == 0, "image parts must hold whole sub-steps");
     __shared__ u32x4 lds[(DB ? 2 : 1) * NV];
     int64_t U; int32_t na;
     plan_bounds(p, U, na);
@@ -305,7 +316,12 @@ __global__ __launch_bounds__(TALL ? 512 : 256, TALL ? 1 : 2) void stream_mfma(co
                 for (int v = 0; v < 4; ++v) acc64[ACC64 ? rg : 0][ACC64 ? nt : 0][ACC64 ? v : 0] = 0.0;
     }
 
-    u32x4 hreg[PF ? CPT : 1];
+    // vector index of the j-th vector of this thread's share of image part r
+    auto part_index = [&](int j, int r) -> int {
+        const int q = tid + NTHR * j;
+        return (q / HSV) * NSV + r * HSV + q % HSV;
+    };
+    u32x4 hreg[SPLIT ? CPH : (PF ? CPT : 1)];
     int32_t a_next = a;
     for (int64_t u = u0; u < u1; ++u) {
         const int cur = DB ? (int)((u - u0) & 1) : 0;
@@ -316,8 +332,11 @@ __global__ __launch_bounds__(TALL ? 512 : 256, TALL ? 1 : 2) void stream_mfma(co
         if (more) {
             unit_decode(p, u + 1, a_next, chunk_n, wt_n);
             sp_n = s_run(a_next, chunk_n);
-            if (PF) {
-                const u32x4* src = image(chunk_n, wt_n);
+            const u32x4* src = image(chunk_n, wt_n);
+            if (SPLIT) {
+#pragma unroll
+                for (int j = 0; j < CPH; ++j) hreg[j] = src[part_index(j, 0)];
+            } else if (PF) {
 #pragma unroll
                 for (int i = 0; i < CPT; ++i) hreg[i] = src[tid + NTHR * i];
             }
@@ -325,6 +344,20 @@ __global__ __launch_bounds__(TALL ? 512 : 256, TALL ? 1 : 2) void stream_mfma(co
         const u32x4* hb = lds + cur * NV;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
+            if (SPLIT && s > 0 && s % (NS / QP) == 0 && (more || u > u0)) {
+                // all waves are done with part r - 1 of the current image, and
+                // the last part written at the previous unit's end is visible
+                __syncthreads();
+                if (more) {
+                    const int r = s / (NS / QP);
+                    const u32x4* src = image(chunk_n, wt_n);
+#pragma unroll
+                    for (int j = 0; j < CPH; ++j) {
+                        lds[part_index(j, r - 1)] = hreg[j];
+                        hreg[j] = src[part_index(j, r)];
+                    }
+                }
+            }
             // keep D sub-steps of S in flight, crossing into the next unit
             const int sd = s + D;
             if (sd < NS) {
@@ -420,9 +453,18 @@ __global__ __launch_bounds__(TALL ? 512 : 256, TALL ? 1 : 2) void stream_mfma(co
                     acc[rg][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
         }
-        if (more) {
-            u32x4* dstb = lds + (DB ? (cur ^ 1) : 0) * NV;
-            if (!DB) __syncthreads();                 // single buffer: everyone done reading
+        if (more && SPLIT) {
+            // all waves are done with the last part; the other parts of the
+            // next image are visible now, the last one becomes visible at the
+            // next unit's first part barrier
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < CPH; ++j) lds[part_index(j, QP - 1)] = hreg[j];
+            a = a_next;
+            chunk = chunk_n;
+            sp = sp_n;
+        } else if (more) {
+            u32x4* dstb = lds + (cur ^ 1) * NV;
             if (PF) {
 #pragma unroll
                 for (int i = 0; i < CPT; ++i) dstb[tid + NTHR * i] = hreg[i];

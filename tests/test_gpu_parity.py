@@ -395,7 +395,8 @@ def test_stop_rule_rejects_zero_factor_through_the_loss_gate():
     H0 = torch.zeros(300, 4, device=dev())
     st = sym.symnmf_state_create(c, S, 4, sym.symnmf_params_default(eta=0.05, max_iter=300), H0)
     stats, conv = sym.symnmf_solve_to_tol(c, S, st)
-    assert not conv and stats.t == 300 and stats.E == pytest.approx(1.0, rel=1e-12) and stats.kkt == 0.0
+    # 300 steps evaluate H_0 .. H_299: the last check is t = 290
+    assert not conv and stats.t == 290 and stats.E == pytest.approx(1.0, rel=1e-12) and stats.kkt == 0.0
     st = sym.symnmf_state_create(c, S, 4, sym.symnmf_params_default(eta=0.05, max_iter=300, tau_E=1.5), H0)
     stats, conv = sym.symnmf_solve_to_tol(c, S, st)
     _, ost = o.Solver(Snp, 4, o.Params(eta=0.05, max_iter=300, tau_E=1.5), np.zeros((300, 4))).solve()
