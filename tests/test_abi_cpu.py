@@ -93,7 +93,8 @@ def test_tiled_storage_offsets_match_the_documented_layout(binding):
 
 
 @pytest.mark.parametrize("tiles,chunks,P", [(1, 1, 256), (2, 3, 256), (3, 3, 256), (391, 391, 256),
-                                            (392, 391, 256), (49, 3907, 256), (7, 5, 512)])
+                                            (392, 391, 256), (49, 3907, 256), (49, 3907, 250), (50, 3907, 250),
+                                            (7, 5, 512)])
 def test_partial_slots_are_one_to_one(tiles, chunks, P):
     """Host check of the stream-K partial indexing: work-group w owns units
     [w U / Pe, (w+1) U / Pe); each maximal run of one tile (pair of tiles for

@@ -443,6 +443,18 @@ def test_objective_float32_H(S600, dtype, k):
 
 
 # --- edge cases ----------------------------------------------------------------
+@pytest.mark.parametrize("n", [1300, 2600])
+@pytest.mark.parametrize("dtype,k", [("fp32", 32), ("bf16", 64), ("fp8", 64)])
+def test_full_step_with_aligned_pair_segments(n, dtype, k):
+    """3 and 6 tile pairs: the full-step stream then launches 255 and 252
+    work-groups, each a whole chunk segment of one pair (ragged last tile)."""
+    Snp = o.abs_corr(_corr_instance(n=n, T=300, groups=5, seed=2))
+    Sq, H0, stats, g, _, _, _, _ = _one_step(Snp, k, dtype, sym.symnmf_params_default(eta=0.05))
+    g_ref = o.gradient(Sq, H0)
+    assert np.max(np.abs(g - g_ref)) <= 2e-5 * np.max(np.abs(g_ref))
+    assert stats.f == pytest.approx(o.objective_trace(Sq, H0), rel=1e-6)
+
+
 def test_tiny_and_degenerate_shapes():
     c = ctx()
     X = _corr_instance(n=37, T=50, groups=3, seed=9)
