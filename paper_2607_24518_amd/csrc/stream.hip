@@ -136,18 +136,21 @@ __device__ inline void split3_bf16(float x, uint16_t& hi, uint16_t& mid, uint16_
     lo = f32_to_bf16_bits(r2);
 }
 
+// First chunk row kk0 and H column of image vector v (16 bytes: 4 floats for
+// KIND 0, 8 bf16 of one plane otherwise); the vector holds rows kk0, kk0 + 1, ...
+// of that column, in the order given above.
 template <int KIND>
-__device__ inline int h_lds_index(int kk, int col) {
-    const int nt = col >> 4, c = col & 15;
+__device__ inline void image_vector_origin(int v, int& kk0, int& col) {
+    const int c = v & 15, g = (v >> 4) & 3;
     if (KIND == 0) {
-        const int s = kk >> 4, g = (kk >> 2) & 3, m = kk & 3;
-        return ((((nt * 16 + s) * 4 + g) * 16 + c) << 2) + m;
+        kk0 = 16 * ((v >> 6) & 15) + 4 * g;
+        col = 16 * (v >> 10) + c;
     } else if (KIND == 1) {
-        const int s = kk >> 5, g = (kk >> 3) & 3, i = kk & 7;
-        return ((((nt * 8 + s) * 4 + g) * 16 + c) << 3) + i;
+        kk0 = 32 * ((v >> 6) & 7) + 8 * g;
+        col = 16 * (v >> 9) + c;
     } else {
-        const int s = kk >> 6, g = (kk >> 4) & 3, h = (kk >> 3) & 1, i = kk & 7;
-        return (((((nt * 4 + s) * 2 + h) * 4 + g) * 16 + c) << 3) + i;
+        kk0 = 64 * ((v >> 7) & 3) + 16 * g + 8 * ((v >> 6) & 1);
+        col = 16 * (v >> 9) + c;
     }
 }
 
@@ -158,27 +161,54 @@ struct ImageShape {
     static constexpr int PLANE = KC * K;                                // bf16 elements per plane
 };
 
+// One work-group per chunk: the chunk's 256 x K rows of H (scaled by wt) are
+// staged in LDS with coalesced 16-byte loads, then every thread assembles
+// whole 16-byte image vectors (all three bf16 planes at once for KIND 1, 2)
+// and writes them in order.
 template <int KIND, int K>
-__global__ __launch_bounds__(256) void h_image_kernel(const float* __restrict__ H, int64_t n_chunks, float wt,
-                                                      uint32_t* __restrict__ img) {
+__global__ __launch_bounds__(256) void h_image_kernel(const float* __restrict__ H, float wt,
+                                                      u32x4* __restrict__ img) {
     using IS = ImageShape<KIND, K>;
-    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= n_chunks * KC * K) return;
-    const int64_t chunk = e / (KC * K);
-    const int f = (int)(e - chunk * (KC * K));
-    const int kk = f / K, col = f % K;
-    const int idx = h_lds_index<KIND>(kk, col);
-    uint32_t* base = img + chunk * IS::BUFW;
-    const float v = H[e] * wt;
-    if (KIND == 0) {
-        ((float*)base)[idx] = v;
-    } else {
-        uint16_t hi, mid, lo;
-        split3_bf16(v, hi, mid, lo);
-        uint16_t* hb = (uint16_t*)base;
-        hb[idx] = hi;
-        hb[IS::PLANE + idx] = mid;
-        hb[2 * IS::PLANE + idx] = lo;
+    constexpr int LDH = K + 1;                            // padded row: column reads spread over banks
+    constexpr int EPV = KIND == 0 ? 4 : 8;                // H values per image vector
+    constexpr int VP = KC * K / EPV;                      // vectors per plane
+    __shared__ float Hs[KC * LDH];
+    const int64_t chunk = blockIdx.x;
+    const float4* src = (const float4*)(H + chunk * KC * K);
+    for (int q = threadIdx.x; q < KC * K / 4; q += 256) {
+        const float4 x = src[q];
+        const int r = (4 * q) / K, c = (4 * q) % K;
+        float* d = Hs + r * LDH + c;
+        d[0] = x.x * wt;
+        d[1] = x.y * wt;
+        d[2] = x.z * wt;
+        d[3] = x.w * wt;
+    }
+    __syncthreads();
+    u32x4* out = img + chunk * IS::NV;
+    for (int v = threadIdx.x; v < VP; v += 256) {
+        int kk0, col;
+        image_vector_origin<KIND>(v, kk0, col);
+        if (KIND == 0) {
+            u32x4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = __builtin_bit_cast(uint32_t, Hs[(kk0 + e) * LDH + col]);
+            out[v] = o;
+        } else {
+            uint16_t hi[8], mid[8], lo[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) split3_bf16(Hs[(kk0 + e) * LDH + col], hi[e], mid[e], lo[e]);
+            u32x4 a, b, c;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                a[e] = (uint32_t)hi[2 * e] | ((uint32_t)hi[2 * e + 1] << 16);
+                b[e] = (uint32_t)mid[2 * e] | ((uint32_t)mid[2 * e + 1] << 16);
+                c[e] = (uint32_t)lo[2 * e] | ((uint32_t)lo[2 * e + 1] << 16);
+            }
+            out[v] = a;
+            out[VP + v] = b;
+            out[2 * VP + v] = c;
+        }
     }
 }
 
@@ -189,9 +219,8 @@ int64_t h_image_words(int32_t stype, int64_t k, int64_t n_chunks) {
 
 hipError_t launch_h_image(const float* H, int32_t stype, int64_t k, int64_t n_chunks, float wt, uint32_t* img,
                           hipStream_t stream) {
-    const int64_t count = n_chunks * KC * k;
-    dim3 grid((count + 255) / 256), block(256);
-#define IMG(KIND, KK) hipLaunchKernelGGL((h_image_kernel<KIND, KK>), grid, block, 0, stream, H, n_chunks, wt, img)
+    dim3 grid(n_chunks), block(256);
+#define IMG(KIND, KK) hipLaunchKernelGGL((h_image_kernel<KIND, KK>), grid, block, 0, stream, H, wt, (u32x4*)img)
     if (stype == SYMNMF_S_FP32) {
         if (k == 16) IMG(0, 16); else if (k == 32) IMG(0, 32); else if (k == 64) IMG(0, 64); else return hipErrorInvalidValue;
     } else if (stype == SYMNMF_S_BF16) {
