@@ -268,7 +268,11 @@ template <int KIND, int NT, bool DB, bool PF, bool ACC64, bool TALL>
 __global__ __launch_bounds__(TALL ? 512 : 256, TALL ? 1 : 2) void stream_mfma(const void* __restrict__ Sv,
                                                                              const u32x4* __restrict__ img1,
                                                                              const u32x4* __restrict__ img2,
-                                                                             void* __restrict__ part, PlanView p) {
+                                                                             void* __restrict__ part, PlanView plan) {
+    // tall kernels only stream full plans: with full fixed at compile time the
+    // plan-table lookups (global loads with their waits) drop out of the loop
+    PlanView p = plan;
+    if (TALL) p.full = 1;
     constexpr int K = 16 * NT;
     constexpr int NTHR = TALL ? 512 : 256;
     using IS = ImageShape<KIND, K>;
@@ -361,30 +365,33 @@ __global__ __launch_bounds__(TALL ? 512 : 256, TALL ? 1 : 2) void stream_mfma(co
         if (more) {
             unit_decode(p, u + 1, a_next, chunk_n, wt_n);
             sp_n = s_run(a_next, chunk_n);
-            const u32x4* src = image(chunk_n, wt_n);
-            if (SPLIT) {
+        }
+        // Every load below is issued whether or not a next unit exists (on the
+        // last unit they re-read this unit's own image and S run, in bounds and
+        // unused): loads under a branch would leave the compiler's wait counts
+        // at the joins of the unrolled loop set for the path without them,
+        // draining the S prefetch ring near every unit boundary.
+        const u32x4* src_n = image(chunk_n, wt_n);
+        if (SPLIT) {
 #pragma unroll
-                for (int j = 0; j < CPH; ++j) hreg[j] = src[part_index(j, 0)];
-            } else if (PF) {
+            for (int j = 0; j < CPH; ++j) hreg[j] = src_n[part_index(j, 0)];
+        } else if (PF) {
 #pragma unroll
-                for (int i = 0; i < CPT; ++i) hreg[i] = src[tid + NTHR * i];
-            }
+            for (int i = 0; i < CPT; ++i) hreg[i] = src_n[tid + NTHR * i];
         }
         const u32x4* hb = lds + cur * NV;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            if (SPLIT && s > 0 && s % (NS / QP) == 0 && (more || u > u0)) {
+            if (SPLIT && s > 0 && s % (NS / QP) == 0) {
                 // all waves are done with part r - 1 of the current image, and
-                // the last part written at the previous unit's end is visible
+                // the last part written at the previous unit's end is visible;
+                // on the last unit the write lands in a consumed part, unread
                 __syncthreads();
-                if (more) {
-                    const int r = s / (NS / QP);
-                    const u32x4* src = image(chunk_n, wt_n);
+                const int r = s / (NS / QP);
 #pragma unroll
-                    for (int j = 0; j < CPH; ++j) {
-                        lds[part_index(j, r - 1)] = hreg[j];
-                        hreg[j] = src[part_index(j, r)];
-                    }
+                for (int j = 0; j < CPH; ++j) {
+                    lds[part_index(j, r - 1)] = hreg[j];
+                    hreg[j] = src_n[part_index(j, r)];
                 }
             }
             // keep D sub-steps of S in flight, crossing into the next unit
@@ -393,11 +400,14 @@ __global__ __launch_bounds__(TALL ? 512 : 256, TALL ? 1 : 2) void stream_mfma(co
 #pragma unroll
                 for (int rg = 0; rg < 4; ++rg)
                     ring[sd % RING][rg] = __builtin_nontemporal_load(sp + (sd * 4 + rg) * 64);
-            } else if (more) {
+            } else {
 #pragma unroll
                 for (int rg = 0; rg < 4; ++rg)
                     ring[sd % RING][rg] = __builtin_nontemporal_load(sp_n + ((sd - NS) * 4 + rg) * 64);
             }
+            // keep the loads here: the scheduler would otherwise sink them
+            // towards their use and shorten the prefetch distance
+            __builtin_amdgcn_sched_barrier(0);
             if (KIND == 0) {
                 floatx4 bv[NT];
 #pragma unroll
