@@ -5,5 +5,5 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 """
 from .symnmf_oracle import *  # noqa: F401,F403
 from .symnmf_oracle import (  # noqa: F401
-    ADAGRAD, RMSPROP, PIECEWISE_ADAGRAD, ROW_SVRG, BLOCK_SVRG, Params, Stats, Solver,
+    ADAGRAD, RMSPROP, PIECEWISE_ADAGRAD, ROW_SVRG, BLOCK_SVRG, ADMM, Params, Stats, Solver, admm_update,
 )

@@ -17,7 +17,8 @@ numpy primitives (matmul, sort) as the only library steps:
   (section "Memory-Efficient Loss Reformulation").
 * Update rules of appendix "Detailed Algorithm Descriptions", family 3:
   AdaGrad, RMSprop, their softplus (LogSpace) forms (eq. logspace_grad),
-  Piecewise AdaGrad, Row-Stochastic SVRG, Block-SVRG AdaptGrow.
+  Piecewise AdaGrad, Row-Stochastic SVRG, Block-SVRG AdaptGrow; and
+  family 6, ADMM (eqs. admm_H, admm_W, admm_U).
 * The three-criterion stop rule (eqs. proj_grad, loss_gate, kkt_stop,
   kkt_scaled, obj_stag, conv_and).
 
@@ -359,6 +360,19 @@ def rmsprop_update(X, v, m, g, eta, eps, alpha, mu, project=True):
     return (np.maximum(X, 0.0) if project else X), v, m
 
 
+def admm_update(S, W, U, rho, SW=None):
+    """One ADMM iteration (appendix family 6): the least-squares H of the
+    bilinear surrogate ||S - H W^T||^2 with consensus penalty (eq. admm_H),
+    the projection of H + U onto the non-negative orthant (eq. admm_W) and the
+    scaled dual ascent (eq. admm_U).  Returns (W_next, U_next)."""
+    SW = S @ W if SW is None else SW
+    k = W.shape[1]
+    M = 2.0 * (W.T @ W) + rho * np.eye(k)
+    H = np.linalg.solve(M, (2.0 * SW + rho * (W - U)).T).T   # H M = 2 S W + rho (W - U)
+    W_next = np.maximum(H + U, 0.0)
+    return W_next, U + H - W_next
+
+
 def lower_median(x):
     """Lower middle order statistic: element floor((m-1)/2) of the sorted values."""
     x = np.asarray(x, dtype=np.float64).ravel()
@@ -375,7 +389,7 @@ def piecewise_reset(g, c):
 # ---------------------------------------------------------------------------
 # Solver (state machine shared by every method).
 # ---------------------------------------------------------------------------
-ADAGRAD, RMSPROP, PIECEWISE_ADAGRAD, ROW_SVRG, BLOCK_SVRG = range(5)
+ADAGRAD, RMSPROP, PIECEWISE_ADAGRAD, ROW_SVRG, BLOCK_SVRG, ADMM = range(6)
 
 
 @dataclass
@@ -404,6 +418,7 @@ class Params:
     n_ref: float = 1e4
     tau_stag: float = 1e-5
     seed: int = 0
+    rho: float = 500.0         # ADMM consensus penalty
 
 
 @dataclass
@@ -445,6 +460,10 @@ class Solver:
       (rows in both get the sum), rows in neither take mu.  phi doubles (capped
       at 1) after ``grow_checks`` consecutive stagnating checks while the KKT
       measure is above c_grow * tau_g.
+    * ADMM: W is the iterate (H_t above), U the scaled dual, both starting at
+      (H0, 0); step t records the statistics of W_t (the paper tracks
+      convergence on the feasible factor) and applies eqs. admm_H, admm_W,
+      admm_U in that order.
     """
 
     def __init__(self, S, k: int, params: Params, H0):
@@ -459,6 +478,7 @@ class Solver:
             self.H = softplus(self.theta)
         self.G = np.zeros_like(self.H)       # AdaGrad accumulator (or RMSprop v)
         self.m = np.zeros_like(self.H)       # RMSprop momentum
+        self.U = np.zeros_like(self.H)       # ADMM scaled dual
         self.mu_snap = None
         self.t = 0
         self.phi = params.phi0 if params.method == BLOCK_SVRG else 1.0
@@ -535,7 +555,9 @@ class Solver:
             if p.method in (ROW_SVRG, BLOCK_SVRG):
                 self.mu_snap = g.copy()
         self.last_g = g
-        if p.softplus:
+        if p.method == ADMM:
+            self.H, self.U = admm_update(self.S, self.H, self.U, p.rho, SH)
+        elif p.softplus:
             g_theta = g * sigmoid(self.theta)                 # eq. logspace_grad
             if p.method == RMSPROP:
                 self.theta, self.G, self.m = rmsprop_update(self.theta, self.G, self.m, g_theta,

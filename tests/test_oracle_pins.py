@@ -396,6 +396,43 @@ def test_block_svrg_partial_step_uses_snapshot_on_untouched_rows():
 
 
 # --- stop rule (section "Convergence Criterion") --------------------------
+# --- ADMM (appendix family 6) --------------------------------------------------
+def test_admm_h_step_is_the_penalised_least_squares_solution():
+    """eq. admm_H is the minimiser over H of ||S - H W^T||^2 + (rho/2) ||H - W + U||^2;
+    solved here row by row as a stacked least-squares problem (no normal
+    equations), then eqs. admm_W and admm_U applied to that H."""
+    r = np.random.default_rng(4)
+    S = _rand_sym(7, 3)
+    W = r.random((7, 3))
+    U = -0.1 * r.random((7, 3))
+    rho = 0.7
+    A = np.vstack([W, math.sqrt(rho / 2) * np.eye(3)])
+    H = np.stack([np.linalg.lstsq(A, np.concatenate([S[i], math.sqrt(rho / 2) * (W - U)[i]]), rcond=None)[0]
+                  for i in range(7)])
+    W1, U1 = o.admm_update(S, W, U, rho)
+    W_ref = np.maximum(H + U, 0.0)
+    assert np.max(np.abs(W1 - W_ref)) < 1e-12
+    assert np.max(np.abs(U1 - (U + H - W_ref))) < 1e-12
+
+
+def test_admm_fixed_point_complementarity_and_planted_recovery():
+    Hs = synth.planted_factor(3, 64, 4).numpy()
+    S = Hs @ Hs.T
+    # an exact factorisation with zero dual is a fixed point
+    W1, U1 = o.admm_update(S, Hs, np.zeros_like(Hs), 5.0)
+    assert np.max(np.abs(W1 - Hs)) < 1e-12 and np.max(np.abs(U1)) < 1e-12
+    # after every step the dual is the negative part of H + U: U <= 0 and W U = 0
+    H0 = o.init_H(S.mean(), 64, 4, seed=1)
+    sv = o.Solver(S, 4, o.Params(method=o.ADMM, rho=2.0, max_iter=3000, tau_g_inf=1e-14, tau_stag=0.0), H0)
+    for _ in range(20):
+        sv.step()
+        assert np.all(sv.U <= 0.0) and np.all(sv.H * sv.U == 0.0) and np.all(sv.H >= 0.0)
+    # and the planted factorisation is recovered (certified by the stop rule)
+    H, st = sv.solve()
+    assert st.converged and st.E < 1e-12
+    assert o.subspace_error(H, Hs) < 1e-6
+
+
 def test_tau_g_scaled_values_from_the_paper(golden_dir):
     for line in open(f"{golden_dir}/kkt_scaled.txt"):
         if line.startswith("#") or not line.strip():
