@@ -164,16 +164,24 @@ def ttt_run(ctx, S, k, params, init, objective_of, f_ref, tol, max_steps, every,
     return entry
 
 
-METHODS = {"adagrad": 0, "rmsprop": 1, "piecewise": 2, "rowsvrg": 3, "blocksvrg": 4}
+METHODS = {"adagrad": 0, "rmsprop": 1, "piecewise": 2, "rowsvrg": 3, "blocksvrg": 4, "admm": 5}
 
 
 def variant_params(variant, eta_base, seed=0):
-    """Solver parameters of a variant name "<storage>[-<method>][-softplus]"."""
+    """Solver parameters of a variant name "<storage>[-<method>][-softplus]";
+    "admm<rho>" selects ADMM with that penalty (plain "admm": rho = 500)."""
     import paper_2607_24518_amd as sym
 
     parts = variant.split("-")
+    rho = 500.0
+    for q in parts[1:]:
+        if q.startswith("admm") and q[4:]:
+            rho = float(q[4:])
+    parts = ["admm" if q.startswith("admm") else q for q in parts]
     method = next((q for q in parts[1:] if q in METHODS), "adagrad")
     kw = dict(method=METHODS[method], eta=eta_base, softplus=int("softplus" in parts), max_iter=10 ** 9, seed=seed)
+    if method == "admm":
+        kw.update(rho=rho)
     if method == "rmsprop":
         kw.update(eta=0.03 * eta_base, eps=1e-8, alpha=0.99, mu=0.5)
     if method in ("rowsvrg", "blocksvrg"):

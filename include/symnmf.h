@@ -67,13 +67,16 @@ typedef enum {
     SYMNMF_TPDM = 1          /* empirical tail pairwise dependence (section "Empirical Estimation") */
 } symnmf_skind;
 
-/* Solver families of appendix "Detailed Algorithm Descriptions", family 3. */
+/* Solver families of appendix "Detailed Algorithm Descriptions": family 3
+ * (AdaGrad to Block-SVRG) and family 6 (ADMM). */
 typedef enum {
     SYMNMF_ADAGRAD = 0,
     SYMNMF_RMSPROP = 1,
     SYMNMF_PIECEWISE_ADAGRAD = 2,
     SYMNMF_ROW_SVRG = 3,
-    SYMNMF_BLOCK_SVRG = 4    /* Block-SVRG AdaptGrow */
+    SYMNMF_BLOCK_SVRG = 4,   /* Block-SVRG AdaptGrow */
+    SYMNMF_ADMM = 5          /* eqs. admm_H, admm_W, admm_U; the iterate is W, the
+                                dual U starts at 0; projected form only */
 } symnmf_method;
 
 typedef struct symnmf_ctx symnmf_ctx;
@@ -139,6 +142,7 @@ typedef struct {
     double n_ref;            /* n_ref of eq. kkt_scaled                           */
     double tau_stag;         /* stagnation tolerance (eq. obj_stag)               */
     uint64_t seed;           /* key of the index-set sampler                      */
+    double rho;              /* ADMM consensus penalty rho > 0                    */
 } symnmf_params;
 
 /* Statistics of one iteration, of the iterate H_t that the step read. */
@@ -223,13 +227,17 @@ void symnmf_state_destroy(symnmf_state* st);
  * phi growth and the stop rule live in symnmf_solve_to_tol).  Reads H_t,
  * forms g_t = grad f(H_t) from S H_t (or its sampled blocks), updates the
  * optimiser state, writes H_{t+1}, and reduces in FP64 the statistics of H_t.
+ * ADMM (family 6): the iterate is the feasible factor W; the step forms
+ * (2 W^T W + rho I)^-1 from the FP64 Gram of W_t, then H, W_{t+1} and U from
+ * S W_t (eqs. admm_H, admm_W, admm_U); the statistics are those of W_t.
  * ``out`` NULL: nothing waits; otherwise the call synchronises and fills it. */
 symnmf_status symnmf_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st, symnmf_stats* out);
 
 /* Copy a state buffer to ``dst`` (device, n x k elements of the state's
  * precision: float32, or float64 for FP64 S).  which: 0 = current iterate,
- * 1 = previous iterate, 2 = accumulator G (RMSprop v), 3 = RMSprop momentum,
- * 4 = Theta (softplus), 5 = snapshot gradient mu, 6 = gradient of the last step. */
+ * 1 = previous iterate, 2 = accumulator G (RMSprop v), 3 = RMSprop momentum
+ * (ADMM: the scaled dual U), 4 = Theta (softplus), 5 = snapshot gradient mu,
+ * 6 = gradient of the last step. */
 symnmf_status symnmf_state_read(symnmf_ctx* ctx, symnmf_state* st, int32_t which, void* dst);
 /* Host copy of the statistics of the last step (synchronises). */
 symnmf_status symnmf_state_stats(symnmf_ctx* ctx, symnmf_state* st, symnmf_stats* out);

@@ -264,8 +264,14 @@ struct UpdateArgs {
     double* tile_tr;      // [tiles] sum H_t * SH_t
     double* tile_kkt;     // [tiles] sum proj(g)^2
     int32_t* tile_bad;    // [tiles] non-finite gradient count
+    double rho;           // ADMM consensus penalty
+    void* minv;           // ADMM: (2 W^T W + rho I)^-1, k x k (state precision)
 };
 hipError_t launch_update(const UpdateArgs& a, int h_f64, const PlanView& plan, hipStream_t stream);
+// ADMM step (full plans): the k x k inverse from the FP64 Gram of W_t, then the
+// fused statistics + H / W / U update (a.M holds U).
+hipError_t launch_admm(const UpdateArgs& a, const double* gram64, int h_f64, const PlanView& plan,
+                       hipStream_t stream);
 
 // Per-slice FP64 Gram partials (SUBT per tile) of rows [row0, row0 + tiles*TR) of H.
 hipError_t launch_tile_gram(const void* H, int h_f64, int64_t row0, int64_t rows, int64_t tiles, int64_t k,

@@ -83,6 +83,7 @@ struct symnmf_state {
     void* H[2] = {nullptr, nullptr};
     int cur = 0;
     void *G = nullptr, *M = nullptr, *Theta = nullptr, *Mu = nullptr, *Gout = nullptr, *part = nullptr;
+    void* minv = nullptr;            // ADMM: (2 W^T W + rho I)^-1 (M holds the dual U)
     double *tile_gram = nullptr, *tile_tr = nullptr, *tile_kkt = nullptr;
     int32_t* tile_bad = nullptr;
     double* gram64[2] = {nullptr, nullptr};
@@ -113,7 +114,7 @@ struct symnmf_state {
 
 extern "C" {
 
-int32_t symnmf_abi_version(void) { return 1; }
+int32_t symnmf_abi_version(void) { return 2; }
 
 void symnmf_params_default(symnmf_params* p) {
     std::memset(p, 0, sizeof(*p));
@@ -141,6 +142,7 @@ void symnmf_params_default(symnmf_params* p) {
     p->n_ref = 1e4;
     p->tau_stag = 1e-5;
     p->seed = 0;
+    p->rho = 500.0;
 }
 
 symnmf_status symnmf_create(symnmf_ctx** out, int32_t device, void* hip_stream) {
@@ -396,8 +398,10 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
     const int h_f64 = S->dtype == SYMNMF_S_FP64;
     if (h_f64 && !h0_is_f64) return fail(ctx, SYMNMF_EINVAL, "state_create: FP64 S needs an FP64 H0");
     if (h_f64 && k > 32) return fail(ctx, SYMNMF_EUNSUPPORTED, "state_create: FP64 state supports k <= 32");
-    if (p->method < SYMNMF_ADAGRAD || p->method > SYMNMF_BLOCK_SVRG)
+    if (p->method < SYMNMF_ADAGRAD || p->method > SYMNMF_ADMM)
         return fail(ctx, SYMNMF_EINVAL, "state_create: bad method");
+    if (p->method == SYMNMF_ADMM && (!(p->rho > 0.0) || p->softplus))
+        return fail(ctx, SYMNMF_EINVAL, "state_create: ADMM needs rho > 0 and the projected form");
     if (!(p->eta > 0.0) || !(p->eps >= 0.0) || p->delta < 1 || p->max_iter < 0)
         return fail(ctx, SYMNMF_EINVAL, "state_create: bad eta/eps/delta/max_iter");
     const bool svrg = p->method == SYMNMF_ROW_SVRG || p->method == SYMNMF_BLOCK_SVRG;
@@ -447,7 +451,8 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
     ALLOC(st->H[0], hbytes);
     ALLOC(st->H[1], hbytes);
     ALLOC(st->G, pbytes);
-    if (p->method == SYMNMF_RMSPROP) ALLOC(st->M, pbytes);
+    if (p->method == SYMNMF_RMSPROP || p->method == SYMNMF_ADMM) ALLOC(st->M, pbytes);
+    if (p->method == SYMNMF_ADMM) ALLOC(st->minv, k * k * st->hsz);
     if (p->softplus) ALLOC(st->Theta, pbytes);
     if (svrg) ALLOC(st->Mu, pbytes);
     ALLOC(st->Gout, pbytes);
@@ -595,7 +600,13 @@ static symnmf_status do_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* s
     a.tile_bad = st->tile_bad;
     {
         ProfScope ps(ctx, PK_UPDATE);
-        HIP_OK(ctx, launch_update(a, st->h_f64, pv, sm));
+        if (p.method == SYMNMF_ADMM) {
+            a.rho = p.rho;
+            a.minv = st->minv;
+            HIP_OK(ctx, launch_admm(a, st->gram64[st->cur], st->h_f64, pv, sm));
+        } else {
+            HIP_OK(ctx, launch_update(a, st->h_f64, pv, sm));
+        }
     }
     const int slot = (int)(t % HCAP);
     ProfScope psf(ctx, PK_FINALIZE);

@@ -45,6 +45,34 @@ __device__ inline int64_t upd_unit_off(const PlanView& p, int32_t a) {
 
 constexpr int UT = 256;   // threads of the update work-group (one row slice of SR rows)
 
+// The S.H partial tiles of active tile act: index (w + act), or 2 (w + pair) +
+// half for tall full plans, over the work-groups w_lo..w_hi that streamed its
+// units (none when act < 0).
+__device__ inline void partial_slots(const PlanView& p, int32_t act, int64_t& w_lo, int64_t& w_hi,
+                                     int64_t& slot_base, int64_t& slot_mul) {
+    w_lo = 0;
+    w_hi = -1;
+    slot_base = act;
+    slot_mul = 1;
+    if (act < 0) return;
+    int64_t U;
+    if (p.full && p.tall) {
+        const int64_t q = act >> 1;
+        U = tall_pairs(p.n_tiles) * p.n_chunks;
+        const int64_t Pe = U < p.P ? U : p.P;
+        w_lo = wg_owner(q * p.n_chunks, U, Pe);
+        w_hi = wg_owner((q + 1) * p.n_chunks - 1, U, Pe);
+        slot_base = 2 * q + (act & 1);
+        slot_mul = 2;
+    } else {
+        if (p.full) U = (int64_t)p.n_tiles * p.n_chunks;
+        else U = (int64_t)(uint32_t)p.hdr[1] | ((int64_t)p.hdr[2] << 32);
+        const int64_t Pe = U < p.P ? U : p.P;
+        w_lo = wg_owner(upd_unit_off(p, act), U, Pe);
+        w_hi = wg_owner(upd_unit_off(p, act + 1) - 1, U, Pe);
+    }
+}
+
 template <typename HT, int KB>
 __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
     __shared__ HT Hs[SR * KB];
@@ -65,26 +93,8 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
     for (int f = t; f < SR * k; f += UT) Hs[(f / k) * KB + f % k] = Ht[g0 * k + f];
     __syncthreads();
 
-    // partial tiles of this tile: index (w + act), or 2 (w + pair) + half for
-    // tall full plans, over the work-groups w_lo..w_hi that streamed its units
-    int64_t w_lo = 0, w_hi = -1, U = 0, slot_base = act, slot_mul = 1;
-    if (act >= 0) {
-        if (p.full && p.tall) {
-            const int64_t q = act >> 1;
-            U = tall_pairs(p.n_tiles) * p.n_chunks;
-            const int64_t Pe = U < p.P ? U : p.P;
-            w_lo = wg_owner(q * p.n_chunks, U, Pe);
-            w_hi = wg_owner((q + 1) * p.n_chunks - 1, U, Pe);
-            slot_base = 2 * q + (act & 1);
-            slot_mul = 2;
-        } else {
-            if (p.full) U = (int64_t)p.n_tiles * p.n_chunks;
-            else U = (int64_t)(uint32_t)p.hdr[1] | ((int64_t)p.hdr[2] << 32);
-            const int64_t Pe = U < p.P ? U : p.P;
-            w_lo = wg_owner(upd_unit_off(p, act), U, Pe);
-            w_hi = wg_owner(upd_unit_off(p, act + 1) - 1, U, Pe);
-        }
-    }
+    int64_t w_lo, w_hi, slot_base, slot_mul;
+    partial_slots(p, act, w_lo, w_hi, slot_base, slot_mul);
     const HT* part = (const HT*)a.part;
     HT* G = (HT*)a.G;
     HT* M = (HT*)a.M;
@@ -185,6 +195,157 @@ hipError_t launch_update(const UpdateArgs& a, int h_f64, const PlanView& p, hipS
         else if (a.k <= 16) hipLaunchKernelGGL((update_kernel<float, 16>), grid, block, 0, stream, a, p);
         else if (a.k <= 32) hipLaunchKernelGGL((update_kernel<float, 32>), grid, block, 0, stream, a, p);
         else hipLaunchKernelGGL((update_kernel<float, 64>), grid, block, 0, stream, a, p);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ADMM (appendix family 6).  Per step: the inverse of M = 2 W^T W + rho I (k x k,
+// FP64 Gauss-Jordan in one work-group; M is symmetric positive definite, so
+// no pivoting), then one fused pass over the rows of the panel that sums the
+// S.W partials and, per row,
+//   * records the statistics of W_t: tr partial W . SW, the projected gradient
+//     of g = 4 (W (W^T W) - S W) (the stop rule is taken on W),
+//   * a = 2 SW + rho (W - U) and H = a M^-1 (eq. admm_H),
+//   * W_{t+1} = [H + U]_+ (eq. admm_W), U <- U + H - W_{t+1} (eq. admm_U),
+//   * the FP64 Gram partials of W_{t+1}.
+// ---------------------------------------------------------------------------
+template <typename HT>
+__global__ __launch_bounds__(256) void admm_minv_kernel(const double* __restrict__ gram, int k, double rho,
+                                                        HT* __restrict__ minv) {
+    __shared__ double A[KMAX * 2 * KMAX];
+    __shared__ double fac[KMAX];
+    const int t = threadIdx.x, w2 = 2 * k;
+    for (int e = t; e < k * w2; e += 256) {
+        const int i = e / w2, j = e - i * w2;
+        A[e] = j < k ? 2.0 * gram[i * k + j] + (i == j ? rho : 0.0) : (j - k == i ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int piv = 0; piv < k; ++piv) {
+        const double d = A[piv * w2 + piv];
+        __syncthreads();
+        for (int j = t; j < w2; j += 256) A[piv * w2 + j] /= d;
+        __syncthreads();
+        for (int i = t; i < k; i += 256) fac[i] = A[i * w2 + piv];
+        __syncthreads();
+        for (int e = t; e < k * w2; e += 256) {
+            const int i = e / w2, j = e - i * w2;
+            if (i != piv) A[e] -= fac[i] * A[piv * w2 + j];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < k * k; e += 256) minv[e] = (HT)A[(e / k) * w2 + k + e % k];
+}
+
+template <typename HT, int KB>
+__global__ __launch_bounds__(UT) void admm_update_kernel(UpdateArgs a, PlanView p) {
+    __shared__ HT Ws[SR * KB];
+    __shared__ HT Wns[SR * KB];
+    __shared__ HT As[SR * KB];
+    __shared__ HT Gs[KB * KB];
+    __shared__ HT Ms[KB * KB];
+    __shared__ double red[UT / 64];
+    const int t = threadIdx.x;
+    const int64_t slice = blockIdx.x;
+    const int64_t tile = slice / SUBT;
+    const int r0 = (int)(slice % SUBT) * SR;
+    const int k = (int)a.k;
+    const int32_t act = (int32_t)tile;                  // full steps only
+    const HT* gram = (const HT*)a.gram_eff;
+    const HT* minv = (const HT*)a.minv;
+    for (int e = t; e < k * k; e += UT) {
+        Gs[(e / k) * KB + e % k] = gram[e];
+        Ms[(e / k) * KB + e % k] = minv[e];
+    }
+    const int64_t g0 = a.row0 + tile * TR + r0;
+    const HT* Wt = (const HT*)a.H;
+    for (int f = t; f < SR * k; f += UT) Ws[(f / k) * KB + f % k] = Wt[g0 * k + f];
+    __syncthreads();
+    int64_t w_lo, w_hi, slot_base, slot_mul;
+    partial_slots(p, act, w_lo, w_hi, slot_base, slot_mul);
+    const HT* part = (const HT*)a.part;
+    HT* Ud = (HT*)a.M;
+    HT* Go = (HT*)a.Gout;
+    HT* Wn = (HT*)a.Hn;
+    const HT rho = (HT)a.rho;
+    double tr = 0.0, kkt = 0.0;
+    int bad = 0;
+    for (int f = t; f < SR * k; f += UT) {
+        const int r = f / k, c = f - r * k;
+        const int64_t prow = tile * TR + r0 + r;
+        HT av = 0;
+        if (prow < a.rows) {
+            const HT w = Ws[r * KB + c];
+            const int64_t idx = prow * k + c;
+            HT sw = 0;
+            for (int64_t wg = w_lo; wg <= w_hi; ++wg)
+                sw += part[((slot_mul * wg + slot_base) * TR + r0 + r) * (int64_t)k + c];
+            if (a.fp8) sw = sw / (HT)a.panel_scale[prow / a.panel_rows] + (HT)a.diag[prow] * w;
+            HT wg = 0;
+            for (int b = 0; b < k; ++b) wg += Ws[r * KB + b] * Gs[b * KB + c];
+            const HT g = (HT)4 * (wg - sw);
+            tr += (double)w * (double)sw;
+            const HT pg = w > (HT)0 ? g : (g < (HT)0 ? g : (HT)0);
+            kkt += (double)pg * (double)pg;
+            if (!(g == g) || g - g != (HT)0) ++bad;
+            if (Go) Go[idx] = g;
+            av = (HT)2 * sw + rho * (w - Ud[idx]);
+        }
+        As[r * KB + c] = av;
+    }
+    __syncthreads();
+    for (int f = t; f < SR * k; f += UT) {
+        const int r = f / k, c = f - r * k;
+        const int64_t prow = tile * TR + r0 + r;
+        HT wn = 0;
+        if (prow < a.rows) {
+            const int64_t idx = prow * k + c;
+            HT h = 0;
+            for (int j = 0; j < k; ++j) h += As[r * KB + j] * Ms[j * KB + c];
+            const HT u = Ud[idx];
+            wn = h + u > (HT)0 ? h + u : (HT)0;
+            Ud[idx] = u + h - wn;
+            Wn[(g0 + r) * k + c] = wn;
+        }
+        Wns[r * KB + c] = wn;
+    }
+    __syncthreads();
+    double* tg = a.tile_gram + slice * (int64_t)k * k;
+    for (int e = t; e < k * k; e += UT) {
+        const int ia = e / k, ib = e - ia * k;
+        double s = 0.0;
+        for (int r = 0; r < SR; ++r) s += (double)Wns[r * KB + ia] * (double)Wns[r * KB + ib];
+        tg[e] = s;
+    }
+    const double str = block_sum(tr, red);
+    const double skk = block_sum(kkt, red);
+    const double sbad = block_sum((double)bad, red);
+    if (t == 0) {
+        a.tile_tr[slice] = str;
+        a.tile_kkt[slice] = skk;
+        a.tile_bad[slice] = (int32_t)sbad;
+    }
+}
+
+hipError_t launch_admm(const UpdateArgs& a, const double* gram64, int h_f64, const PlanView& p, hipStream_t stream) {
+    if (!p.full || a.k > KMAX || (h_f64 && a.k > 32)) return hipErrorInvalidValue;
+    if (h_f64)
+        hipLaunchKernelGGL(admm_minv_kernel<double>, dim3(1), dim3(256), 0, stream, gram64, (int)a.k, a.rho,
+                           (double*)a.minv);
+    else
+        hipLaunchKernelGGL(admm_minv_kernel<float>, dim3(1), dim3(256), 0, stream, gram64, (int)a.k, a.rho,
+                           (float*)a.minv);
+    const int64_t tiles = a.rows_pad / TR;
+    dim3 grid(tiles * SUBT), block(UT);
+    if (h_f64) {
+        if (a.k <= 8) hipLaunchKernelGGL((admm_update_kernel<double, 8>), grid, block, 0, stream, a, p);
+        else if (a.k <= 16) hipLaunchKernelGGL((admm_update_kernel<double, 16>), grid, block, 0, stream, a, p);
+        else hipLaunchKernelGGL((admm_update_kernel<double, 32>), grid, block, 0, stream, a, p);
+    } else {
+        if (a.k <= 8) hipLaunchKernelGGL((admm_update_kernel<float, 8>), grid, block, 0, stream, a, p);
+        else if (a.k <= 16) hipLaunchKernelGGL((admm_update_kernel<float, 16>), grid, block, 0, stream, a, p);
+        else if (a.k <= 32) hipLaunchKernelGGL((admm_update_kernel<float, 32>), grid, block, 0, stream, a, p);
+        else hipLaunchKernelGGL((admm_update_kernel<float, 64>), grid, block, 0, stream, a, p);
     }
     return hipGetLastError();
 }

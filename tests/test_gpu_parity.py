@@ -330,6 +330,80 @@ def test_block_svrg_mfma_path(dtype, k):
 
 
 # --- order statistics, Piecewise reset, objective ---------------------------
+# --- ADMM (appendix family 6) ---------------------------------------------------
+def test_admm_fp64_trajectory_matches_oracle(S600):
+    """300 ADMM iterations in FP64 storage and state: the objective of every
+    W_t and the final W and U agree with the oracle to summation order."""
+    c = ctx()
+    k, rho = 8, 20.0
+    S = sym.symnmf_S_load(c, to_dev(S600, torch.float64), dtype=sym.S_FP64)
+    H0 = o.init_H(S600.mean(), 600, k, 2)
+    st = sym.symnmf_state_create(c, S, k, sym.symnmf_params_default(method=sym.ADMM, rho=rho, max_iter=10 ** 9),
+                                 to_dev(H0, torch.float64))
+    solver = o.Solver(S600, k, o.Params(method=o.ADMM, rho=rho), H0)
+    for t in range(300):
+        s = sym.symnmf_step(c, S, st)
+        r = solver.step()
+        assert s.f == pytest.approx(r.f, rel=1e-10), t
+        assert s.kkt == pytest.approx(r.kkt, rel=1e-8, abs=1e-14), t
+    W = torch.empty(600, k, dtype=torch.float64, device=dev())
+    U = torch.empty(600, k, dtype=torch.float64, device=dev())
+    sym.symnmf_state_read(c, st, 0, W)
+    sym.symnmf_state_read(c, st, 3, U)
+    W, U = from_dev(W), from_dev(U)
+    assert np.max(np.abs(W - solver.H)) < 1e-9 * np.max(solver.H)
+    assert np.max(np.abs(U - solver.U)) < 1e-9 * max(np.max(np.abs(solver.U)), 1e-30) + 1e-15
+    assert np.all(U <= 0.0) and np.all(W >= 0.0) and np.all(W * U == 0.0)
+
+
+@pytest.mark.parametrize("dtype,k", [("fp32", 16), ("fp32", 32), ("fp32", 64), ("bf16", 32), ("fp8", 32), ("fp32", 5)])
+def test_admm_single_step_parity(S600, dtype, k):
+    """One ADMM step on the stored S (every stream kernel and the k x k
+    inverse): W_1 and U_1 against the oracle's update from the same W_0."""
+    c = ctx()
+    rho = 50.0
+    S = sym.symnmf_S_load(c, to_dev(S600, torch.float64), dtype=sym.DTYPES[dtype], fp8_panel_rows=128)
+    Sq = stored_numpy(S)
+    H0 = o.init_H(S600.mean(), 600, k, 3, as_float32=True)
+    st = sym.symnmf_state_create(c, S, k, sym.symnmf_params_default(method=sym.ADMM, rho=rho), to_dev(H0))
+    stats = sym.symnmf_step(c, S, st)
+    W1 = torch.empty(600, k, device=dev())
+    U1 = torch.empty(600, k, device=dev())
+    sym.symnmf_state_read(c, st, 0, W1)
+    sym.symnmf_state_read(c, st, 3, U1)
+    W_ref, U_ref = o.admm_update(Sq, H0.astype(np.float64), np.zeros((600, k)), rho)
+    scale = np.max(np.abs(W_ref))
+    assert np.max(np.abs(from_dev(W1) - W_ref)) <= 2e-5 * scale
+    assert np.max(np.abs(from_dev(U1) - U_ref)) <= 2e-5 * scale
+    assert stats.f == pytest.approx(o.objective_trace(Sq, H0.astype(np.float64)), rel=1e-6)
+
+
+def test_admm_certifies_planted_factorisation_like_the_oracle():
+    Hs = synth.planted_factor(3, 300, 4).numpy()
+    Snp = Hs @ Hs.T
+    H0 = o.init_H(Snp.mean(), 300, 4, 1)
+    kw = dict(rho=2.0, max_iter=5000, tau_g_inf=1e-10)
+    c = ctx()
+    S = sym.symnmf_S_load(c, to_dev(Snp, torch.float64), dtype=sym.S_FP64)
+    st = sym.symnmf_state_create(c, S, 4, sym.symnmf_params_default(method=sym.ADMM, **kw), to_dev(H0, torch.float64))
+    W = torch.empty(300, 4, dtype=torch.float64, device=dev())
+    stats, conv = sym.symnmf_solve_to_tol(c, S, st, H_out=W)
+    Wo, ost = o.Solver(Snp, 4, o.Params(method=o.ADMM, **kw), H0).solve()
+    assert conv and ost.converged and stats.t == ost.t
+    assert stats.E < 1e-12
+    assert o.subspace_error(from_dev(W), Hs) < 1e-6
+
+
+def test_admm_rejects_softplus_and_bad_rho(S600):
+    c = ctx()
+    S = sym.symnmf_S_load(c, to_dev(S600, torch.float64))
+    H0 = torch.full((600, 4), 0.05, device=dev())
+    for kw in (dict(rho=0.0), dict(rho=-1.0), dict(softplus=1)):
+        with pytest.raises(sym.SymnmfError) as e:
+            sym.symnmf_state_create(c, S, 4, sym.symnmf_params_default(method=sym.ADMM, **kw), H0)
+        assert e.value.code == sym.EINVAL
+
+
 def test_median_sq_matches_oracle():
     g = np.random.default_rng(3).normal(size=100003).astype(np.float32)
     g[:50] = 0.0
