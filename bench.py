@@ -453,6 +453,86 @@ def warm_start_study(args):
     return out
 
 
+def kmeans_cpu_baseline(X_host, K, rows):
+    """The FP64 oracle's Lloyd step (assignment against K unit centroids and
+    the cluster-sum update) on rows [0, rows) of the |corr| S, scaled to all
+    n rows; the panel build is not timed."""
+    import numpy as np
+    import oracle as o
+    import oracle.kmeans_oracle as km
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    n = X_host.shape[1]
+    Z = o.standardise_columns(X_host)
+    Sp = o.abs_corr_panel(Z, 0, rows)
+    del Z
+    Shat, _ = km.unit_rows(Sp)
+    rng = np.random.default_rng(0)
+    C = rng.random((K, n))
+    C /= np.linalg.norm(C, axis=1, keepdims=True)
+    t0 = time.time()
+    reps = 3
+    for _ in range(reps):
+        labels, _, _ = km.assign(Shat, C)
+        C = km.centroids(Shat, labels, K, C)
+    dt = (time.time() - t0) / reps
+    per_iter = dt * n / rows
+    return {"value": per_iter, "unit": "s/iteration", "cores": int(cores), "kind": "oracle",
+            "sample": f"FP64 oracle Lloyd iterations (assignment + update) on rows [0,{rows}) of the n={n} |corr| S "
+                      f"at K={K} ({reps} timed, {dt:.3f} s each), scaled by {n}/{rows}"}
+
+
+def kmeans_bench(args):
+    """Spherical K-means on the rows of the n = 10^5 |corr| S: wall time of
+    symnmf_kmeans to the stop rule (relative drop of sum(1 - cos) below 1e-4)
+    and of the silhouette, per storage type and cluster count."""
+    import torch
+    import paper_2607_24518_amd as sym
+    import synth
+    dev = torch.device("cuda:0")
+    n = args.n
+    log(f"generating returns T={args.T} n={n} groups={args.groups}")
+    X = synth.overlap_returns(args.seed, T=args.T, n=n, groups=args.groups, device=dev).X
+    ctx = sym.symnmf_create(0)
+    Ks = [int(v) for v in args.kmeans.split(",") if v]
+    runs = []
+    for dname in args.kmeans_dtypes.split(","):
+        S = sym.symnmf_build_S(ctx, X, kind=sym.ABS_CORR, dtype=sym.DTYPES[dname], fp8_panel_rows=256)
+        torch.cuda.synchronize()
+        sbytes = {"fp32": 4, "bf16": 2, "fp8": 1}[dname]
+        for K in Ks:
+            labels = torch.zeros(n, dtype=torch.int32, device=dev)
+            w = 16 if K <= 16 else (32 if K <= 32 else 64)
+            slices = (K + w - 1) // w
+            for rep in range(args.kmeans_reps):
+                t0 = time.perf_counter()
+                st = sym.symnmf_kmeans(ctx, S, K, labels, seed=args.kmeans_seed, tol=1e-4,
+                                       max_iter=args.kmeans_max_iter, allow_notconv=True)
+                wall = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            sil = sym.symnmf_silhouette(ctx, S, labels, K)
+            sil_s = time.perf_counter() - t0
+            passes = 2 * slices * (st["iters"] + 1)            # stream passes of the Lloyd iterations
+            rec = {"S_storage": dname, "K": K, "slice_width": w, "slices": slices, "seconds": round(wall, 4),
+                   "iters": st["iters"], "converged": bool(st["converged"]), "J0": st["J0"], "J": st["J"],
+                   "empty_clusters": st["empty"], "silhouette": round(sil, 5), "silhouette_s": round(sil_s, 4),
+                   "stream_passes": passes, "ms_per_pass_incl_overheads": round(1e3 * wall / (passes + 1), 3),
+                   "S_GB_per_pass": round(n * n * sbytes / 1e9, 2)}
+            log(f"kmeans {rec}")
+            runs.append(rec)
+        del S
+        torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu_baseline:
+        Kc = Ks[0]
+        cpu = kmeans_cpu_baseline(X.double().cpu().numpy(), Kc, min(args.cpu_rows, n))
+        log(f"cpu baseline {cpu}")
+    return {"runs": runs, "cpu_baseline": cpu}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -501,7 +581,22 @@ def main():
     ap.add_argument("--warm-c3", action="store_true", help="also evaluate on the n=100000 |corr| workload")
     ap.add_argument("--warm-c3-max", type=int, default=6000)
     ap.add_argument("--warm-c3-dtypes", default="fp32", help="storage types of the n=100000 evaluation, e.g. fp32,bf16")
+    ap.add_argument("--kmeans", default="", help="spherical K-means study instead of the step rate: cluster counts, "
+                                                 "e.g. 32,316")
+    ap.add_argument("--kmeans-dtypes", default="fp32,bf16")
+    ap.add_argument("--kmeans-seed", type=int, default=7)
+    ap.add_argument("--kmeans-max-iter", type=int, default=100)
+    ap.add_argument("--kmeans-reps", type=int, default=2, help="runs per case; the last is reported")
     args = ap.parse_args()
+
+    if args.kmeans:
+        res = kmeans_bench(args)
+        print(json.dumps({"metric": "spherical K-means on the rows of S: wall time to the stop rule", "unit": "s",
+                          "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": f"abs_corr_n{args.n}_T{args.T}_groups{args.groups}",
+                                     "stop": "relative drop of sum(1 - cos) below 1e-4"},
+                          **res}), flush=True)
+        return
 
     if args.warm:
         res = warm_start_study(args)

@@ -420,6 +420,85 @@ symnmf_status symnmf_canonical(symnmf_ctx* ctx, const float* Y, int64_t n, int64
 symnmf_status symnmf_warm_start(symnmf_ctx* ctx, const symnmf_S* S, symnmf_mlp* mlp, int64_t width, int64_t k,
                                 uint64_t omega_seed, float* H0);
 
+/* ------------------------------------------------------------------------
+ * Spherical K-means on the rows of S (paper section "Clustering": spherical
+ * K-means as constrained SymNMF, Theorem snmf_spkmeans, and the computational
+ * comparison with table tab:kmeans).  The points are the rows s_i of the
+ * full stored S (S->rows == n; a row panel is EUNSUPPORTED) scaled to unit
+ * length, s^_i = s_i / ||s_i||; a centroid is the normalised sum of its
+ * members; the objective is J = sum_i (1 - cos(s^_i, c_{label_i})).  Every
+ * product with S runs the S.H stream with an n x K factor in slices of at
+ * most 64 columns; because S is symmetric,
+ *     cos(s^_i, c_k) = (S C)_ik / ||s_i||   and
+ *     sum_{j in k} s^_j = (S W)_{:,k},  W_jk = [label_j = k] / ||s_j||.
+ * (FP8 storage with per-row-panel scales is symmetric only up to one
+ * quantisation step; both products then use the stored rows.)  Centroids,
+ * weights and products are FP64 for FP64 storage and FP32 otherwise; the
+ * argmax is taken on the products in that precision, ties to the lowest
+ * cluster index; J and the silhouette are summed in FP64.
+ * Readings of what the paper leaves open: Forgy seeding (K distinct rows by
+ * a partial Fisher-Yates shuffle, Knuth's Algorithm P, on 53-bit uniforms of
+ * SplitMix64 keyed by the seed: for i = 0..K-1 swap positions i and
+ * i + floor(u_i (n - i))); a cluster left without members keeps its previous
+ * centroid.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t iters;           /* (centroid update, assignment) pairs after the first assignment */
+    double J0;               /* objective of the first assignment (seed centroids) */
+    double J;                /* objective of the returned labels                   */
+    double wall_ms;          /* host wall time of the whole call                   */
+    int64_t changed;         /* labels changed by the last assignment              */
+    int32_t converged;       /* the stop rule fired within max_iter                */
+    int32_t empty;           /* clusters without members at the end                */
+} symnmf_kmeans_stats;
+
+/* The Forgy seed rows symnmf_kmeans draws for (seed, n, K), in draw order
+ * (host only, no GPU needed): out (host int64, K entries).  Returns EINVAL
+ * unless 1 <= K <= n. */
+symnmf_status symnmf_kmeans_seed_rows(uint64_t seed, int64_t n, int64_t K, int64_t* out);
+
+/* ||s_i|| for every row (norms: device FP64, n entries), one pass over S
+ * with FP64 sums.  EINVAL when a row is zero (it has no direction).
+ * Synchronises. */
+symnmf_status symnmf_row_norms(symnmf_ctx* ctx, const symnmf_S* S, double* norms);
+
+/* Lloyd's assignment step: labels (device int32, n) = argmax_k cos(s^_i, c_k)
+ * for the centroids C (device, n x K row-major, column k = c_k, unit length;
+ * FP64 for FP64 storage, FP32 otherwise); best (device, same type, n
+ * entries, may be NULL) receives the winning cosine; *J the objective.
+ * 1 <= K <= n.  Synchronises. */
+symnmf_status symnmf_kmeans_assign(symnmf_ctx* ctx, const symnmf_S* S, const void* C, int64_t K, int32_t* labels,
+                                   void* best, double* J);
+
+/* Lloyd's update step: C (device, n x K row-major, type as above) = the
+ * normalised sums of the unit rows of every cluster of labels (device int32,
+ * n entries in [-1, K); -1 = in no cluster).  A cluster without members
+ * keeps its column of C_prev (device, same layout; NULL: zeros).  C may
+ * equal C_prev.  Synchronises. */
+symnmf_status symnmf_kmeans_centroids(symnmf_ctx* ctx, const symnmf_S* S, const int32_t* labels, int64_t K,
+                                      const void* C_prev, void* C);
+
+/* Spherical K-means (Lloyd) from K seed rows: init_rows (host int64, K
+ * distinct rows) or, when NULL, the Forgy draw of `seed`.  Iterates
+ * (centroid update, assignment) until J_{t-1} - J_t < tol J_{t-1} (or
+ * J_{t-1} = 0) or max_iter pairs (the paper stops at a relative drop of
+ * 1e-4).  labels: device int32, n entries; C (may be NULL): device n x K,
+ * type as above, the last centroids.  stats (may be NULL).  ENOTCONV when
+ * max_iter ends the run (labels, C and stats are still written).  Device
+ * memory for the n x K factors is allocated and freed inside.
+ * Synchronises (once per iteration, to read J). */
+symnmf_status symnmf_kmeans(symnmf_ctx* ctx, const symnmf_S* S, int64_t K, uint64_t seed, const int64_t* init_rows,
+                            double tol, int64_t max_iter, int32_t* labels, void* C, symnmf_kmeans_stats* stats);
+
+/* Mean silhouette of the partition labels (device int32, n entries in
+ * [0, K)) under the cosine distance d(i, j) = 1 - cos(s^_i, s^_j)
+ * (Rousseeuw 1987): a(i) = (n_a - s^_i . m_a) / (n_a - 1) and
+ * b(i) = min over other non-empty clusters c of 1 - s^_i . m_c / n_c with
+ * m_c the sum of the unit rows of cluster c, s(i) = (b - a) / max(a, b), and
+ * s(i) = 0 in a singleton.  Two passes over S (M = S W, then S M).  EINVAL
+ * with fewer than two non-empty clusters.  Synchronises. */
+symnmf_status symnmf_silhouette(symnmf_ctx* ctx, const symnmf_S* S, const int32_t* labels, int64_t K, double* sil);
+
 #ifdef __cplusplus
 }
 #endif

@@ -55,6 +55,14 @@ class symnmf_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class symnmf_kmeans_stats(ctypes.Structure):
+    _fields_ = [("iters", c_i64), ("J0", c_dbl), ("J", c_dbl), ("wall_ms", c_dbl), ("changed", c_i64),
+                ("converged", c_i32), ("empty", c_i32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class symnmf_adamw(ctypes.Structure):
     _fields_ = [("lr", c_dbl), ("beta1", c_dbl), ("beta2", c_dbl), ("eps", c_dbl), ("weight_decay", c_dbl)]
 
@@ -114,6 +122,14 @@ SIGNATURES = {
     "symnmf_sketch": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_u64, c_i64, c_vp]),
     "symnmf_canonical": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_vp]),
     "symnmf_warm_start": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, c_i64, c_u64, c_vp]),
+    "symnmf_kmeans_seed_rows": (c_i32, [c_u64, c_i64, c_i64, ctypes.POINTER(c_i64)]),
+    "symnmf_row_norms": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp]),
+    "symnmf_kmeans_assign": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, c_vp, c_vp,
+                                     ctypes.POINTER(c_dbl)]),
+    "symnmf_kmeans_centroids": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, c_vp, c_vp]),
+    "symnmf_kmeans": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_i64, c_u64, c_vp, c_dbl, c_i64, c_vp, c_vp,
+                              ctypes.POINTER(symnmf_kmeans_stats)]),
+    "symnmf_silhouette": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, ctypes.POINTER(c_dbl)]),
 }
 
 PROFILE_KERNELS = ("stream", "update", "finalize", "plan", "image")
@@ -457,3 +473,53 @@ def symnmf_warm_start(ctx, S: Matrix, mlp, width: int, k: int, omega_seed: int, 
     _check(ctx, lib().symnmf_warm_start(ctx, ctypes.byref(S.desc), mlp.handle if mlp is not None else None,
                                         width, k, omega_seed, _ptr(H0)))
     return H0
+
+
+def symnmf_kmeans_seed_rows(seed: int, n: int, K: int):
+    out = (c_i64 * K)()
+    code = lib().symnmf_kmeans_seed_rows(seed, n, K, out)
+    if code != OK:
+        raise SymnmfError(code, "kmeans_seed_rows: need 1 <= K <= n")
+    return list(out)
+
+
+def symnmf_row_norms(ctx, S: Matrix, norms):
+    """norms: device float64 tensor of n entries."""
+    _check(ctx, lib().symnmf_row_norms(ctx, ctypes.byref(S.desc), _ptr(norms)))
+    return norms
+
+
+def symnmf_kmeans_assign(ctx, S: Matrix, C, labels, best=None):
+    """C: device n x K (float64 for FP64 storage, else float32); labels: device
+    int32 n.  Returns the objective J."""
+    J = c_dbl()
+    _check(ctx, lib().symnmf_kmeans_assign(ctx, ctypes.byref(S.desc), _ptr(C), C.shape[1], _ptr(labels),
+                                           _ptr(best) if best is not None else None, ctypes.byref(J)))
+    return J.value
+
+
+def symnmf_kmeans_centroids(ctx, S: Matrix, labels, K: int, C, C_prev=None):
+    _check(ctx, lib().symnmf_kmeans_centroids(ctx, ctypes.byref(S.desc), _ptr(labels), K,
+                                              _ptr(C_prev) if C_prev is not None else None, _ptr(C)))
+    return C
+
+
+def symnmf_kmeans(ctx, S: Matrix, K: int, labels, seed: int = 0, init_rows=None, tol: float = 1e-4,
+                  max_iter: int = 100, C=None, allow_notconv: bool = False):
+    """Spherical K-means; returns the stats as a dict.  init_rows: host
+    sequence of K distinct rows (None: Forgy draw of seed)."""
+    st = symnmf_kmeans_stats()
+    rows = None
+    if init_rows is not None:
+        rows = (ctypes.c_int64 * K)(*[int(r) for r in init_rows])
+    code = lib().symnmf_kmeans(ctx, ctypes.byref(S.desc), K, seed, rows, tol, max_iter, _ptr(labels),
+                               _ptr(C) if C is not None else None, ctypes.byref(st))
+    if not (allow_notconv and code == ENOTCONV):
+        _check(ctx, code)
+    return st.as_dict()
+
+
+def symnmf_silhouette(ctx, S: Matrix, labels, K: int):
+    out = c_dbl()
+    _check(ctx, lib().symnmf_silhouette(ctx, ctypes.byref(S.desc), _ptr(labels), K, ctypes.byref(out)))
+    return out.value

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <cstdlib>
 
 #include "../../include/symnmf.h"
 
@@ -162,9 +163,58 @@ inline PlanView plan_view(int32_t* base, int32_t full, int32_t n_tiles, int32_t 
 // the same reason as above), so the buffer needs 2 (P + pairs) tiles.
 __host__ __device__ inline int64_t tall_pairs(int64_t n_tiles) { return (n_tiles + 1) / 2; }
 
+// Work-groups of a tall full pass: one per CU, except that when a whole
+// number m of work-groups per tile pair fills at least 95 % of the CUs the
+// pass uses exactly pairs * m.  The contiguous unit ranges then split every
+// pair into the same m chunk segments, so all work-groups walk the same m
+// chunk positions at the same time and the H images they stage are served
+// from L2 / MALL instead of being fetched from HBM once per pair
+// (SYMNMF_TALL_ALIGN=0 turns this off).
+inline int32_t tall_wgs(int cus, int64_t n_tiles) {
+    const int64_t pairs = tall_pairs(n_tiles);
+    const char* e = std::getenv("SYMNMF_TALL_ALIGN");
+    if (pairs <= cus && !(e && e[0] == '0')) {
+        const int64_t m = cus / pairs;
+        if (20 * pairs * m >= 19 * (int64_t)cus) return (int32_t)(pairs * m);
+    }
+    return cus;
+}
+
 __host__ __device__ inline int64_t wg_start(int64_t w, int64_t U, int64_t Pe) { return w * U / Pe; }
 // the work-group whose range holds unit u
 __host__ __device__ inline int64_t wg_owner(int64_t u, int64_t U, int64_t Pe) { return ((u + 1) * Pe - 1) / U; }
+
+__device__ inline int64_t upd_unit_off(const PlanView& p, int32_t a) {
+    return p.full ? (int64_t)a * p.n_chunks : (int64_t)p.unit_offset[a];
+}
+
+// The S.H partial tiles of active tile act: index (w + act), or 2 (w + pair) +
+// half for tall full plans, over the work-groups w_lo..w_hi that streamed its
+// units (none when act < 0).
+__device__ inline void partial_slots(const PlanView& p, int32_t act, int64_t& w_lo, int64_t& w_hi,
+                                     int64_t& slot_base, int64_t& slot_mul) {
+    w_lo = 0;
+    w_hi = -1;
+    slot_base = act;
+    slot_mul = 1;
+    if (act < 0) return;
+    int64_t U;
+    if (p.full && p.tall) {
+        const int64_t q = act >> 1;
+        U = tall_pairs(p.n_tiles) * p.n_chunks;
+        const int64_t Pe = U < p.P ? U : p.P;
+        w_lo = wg_owner(q * p.n_chunks, U, Pe);
+        w_hi = wg_owner((q + 1) * p.n_chunks - 1, U, Pe);
+        slot_base = 2 * q + (act & 1);
+        slot_mul = 2;
+    } else {
+        if (p.full) U = (int64_t)p.n_tiles * p.n_chunks;
+        else U = (int64_t)(uint32_t)p.hdr[1] | ((int64_t)p.hdr[2] << 32);
+        const int64_t Pe = U < p.P ? U : p.P;
+        w_lo = wg_owner(upd_unit_off(p, act), U, Pe);
+        w_hi = wg_owner(upd_unit_off(p, act + 1) - 1, U, Pe);
+    }
+}
 
 // SplitMix64 (Steele, Lea & Flood 2014): output number c of the stream keyed s.
 __host__ __device__ inline uint64_t splitmix64(uint64_t key, uint64_t c) {

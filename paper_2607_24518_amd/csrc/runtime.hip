@@ -463,20 +463,7 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
         if (p->method == SYMNMF_BLOCK_SVRG) ALLOC(st->img[1], iw * 4);
     }
     st->tall = stream_tall_supported(S->dtype, h_f64, k) != 0 && std::getenv("SYMNMF_NO_TALL") == nullptr;
-    st->P_tall = ctx->cus;
-    // Aligned segments: when a whole number m of work-groups per tile pair
-    // fills nearly every CU, the contiguous unit ranges split every pair into
-    // the same m chunk segments, so all work-groups walk the same m chunk
-    // positions at the same time and the H images they stage are served from
-    // L2 / MALL instead of being fetched from HBM once per pair.
-    if (st->tall) {
-        const int64_t pairs = tall_pairs(st->tiles);
-        const char* e = std::getenv("SYMNMF_TALL_ALIGN");
-        if (pairs <= ctx->cus && !(e && e[0] == '0')) {
-            const int64_t m = ctx->cus / pairs;
-            if (20 * pairs * m >= 19 * (int64_t)ctx->cus) st->P_tall = (int32_t)(pairs * m);
-        }
-    }
+    st->P_tall = st->tall ? tall_wgs(ctx->cus, st->tiles) : ctx->cus;
     const int64_t part_tiles = std::max<int64_t>((int64_t)st->P + st->tiles,
                                                  st->tall ? 2 * ((int64_t)st->P_tall + tall_pairs(st->tiles)) : 0);
     ALLOC(st->part, part_tiles * TR * k * st->hsz);

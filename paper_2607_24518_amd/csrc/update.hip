@@ -39,39 +39,7 @@ __device__ inline double block_sum(double v, double* sh) {
     return s;   // valid in thread 0
 }
 
-__device__ inline int64_t upd_unit_off(const PlanView& p, int32_t a) {
-    return p.full ? (int64_t)a * p.n_chunks : (int64_t)p.unit_offset[a];
-}
-
 constexpr int UT = 256;   // threads of the update work-group (one row slice of SR rows)
-
-// The S.H partial tiles of active tile act: index (w + act), or 2 (w + pair) +
-// half for tall full plans, over the work-groups w_lo..w_hi that streamed its
-// units (none when act < 0).
-__device__ inline void partial_slots(const PlanView& p, int32_t act, int64_t& w_lo, int64_t& w_hi,
-                                     int64_t& slot_base, int64_t& slot_mul) {
-    w_lo = 0;
-    w_hi = -1;
-    slot_base = act;
-    slot_mul = 1;
-    if (act < 0) return;
-    int64_t U;
-    if (p.full && p.tall) {
-        const int64_t q = act >> 1;
-        U = tall_pairs(p.n_tiles) * p.n_chunks;
-        const int64_t Pe = U < p.P ? U : p.P;
-        w_lo = wg_owner(q * p.n_chunks, U, Pe);
-        w_hi = wg_owner((q + 1) * p.n_chunks - 1, U, Pe);
-        slot_base = 2 * q + (act & 1);
-        slot_mul = 2;
-    } else {
-        if (p.full) U = (int64_t)p.n_tiles * p.n_chunks;
-        else U = (int64_t)(uint32_t)p.hdr[1] | ((int64_t)p.hdr[2] << 32);
-        const int64_t Pe = U < p.P ? U : p.P;
-        w_lo = wg_owner(upd_unit_off(p, act), U, Pe);
-        w_hi = wg_owner(upd_unit_off(p, act + 1) - 1, U, Pe);
-    }
-}
 
 template <typename HT, int KB>
 __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {

@@ -55,6 +55,20 @@ def test_struct_sizes_match_header_layout(binding):
     assert binding.symnmf_abi_version() == 2
 
 
+def test_kmeans_seed_rows_are_bit_identical_to_the_oracle(binding):
+    import oracle.kmeans_oracle as km
+    for seed, n, K in [(0, 1000, 2), (5, 512, 8), (2**64 - 3, 100000, 316), (9, 64, 64), (1, 1, 1)]:
+        assert binding.symnmf_kmeans_seed_rows(seed, n, K) == km.seed_rows(seed, n, K).tolist()
+    with pytest.raises(binding.SymnmfError):
+        binding.symnmf_kmeans_seed_rows(0, 5, 6)
+    assert ctypes_sizeof(binding.symnmf_kmeans_stats) == 8 * 5 + 4 * 2
+
+
+def ctypes_sizeof(t):
+    import ctypes
+    return ctypes.sizeof(t)
+
+
 def test_params_default(binding):
     p = binding.symnmf_params_default()
     assert p.method == binding.ADAGRAD and p.delta == 10 and p.warmup == 50

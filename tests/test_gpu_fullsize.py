@@ -88,6 +88,44 @@ def test_full_size_abs_corr_sampled_rows_and_step(big):
     assert f_judge == pytest.approx(stats.f, rel=1e-6)
 
 
+def test_full_size_kmeans_sampled_rows(big):
+    """Spherical K-means on the n = 10^5 |corr| S (FP32, K = 32, the launch
+    configuration of the benchmark's K-means line): the returned labels are
+    the argmax of the returned centroids, J is their objective, and sampled
+    rows' cosines and row lengths match the oracle's definition row by row."""
+    import oracle.kmeans_oracle as km
+    X = big
+    n, K = X.shape[1], 32
+    c = ctx()
+    S = sym.symnmf_build_S(c, to_dev(X), dtype=sym.S_FP32)
+    labels = torch.zeros(n, dtype=torch.int32, device=dev())
+    C = torch.zeros((n, K), dtype=torch.float32, device=dev())
+    st = sym.symnmf_kmeans(c, S, K, labels, seed=0, tol=1e-4, max_iter=3, C=C, allow_notconv=True)
+    assert st["iters"] >= 1 and st["J"] <= st["J0"]
+    lab2 = torch.zeros_like(labels)
+    best = torch.zeros(n, dtype=torch.float32, device=dev())
+    J = sym.symnmf_kmeans_assign(c, S, C, lab2, best)
+    assert torch.equal(lab2, labels) and J == st["J"]
+    assert J == pytest.approx(float(np.sum(1.0 - from_dev(best))), rel=1e-6)
+    norms = torch.zeros(n, dtype=torch.float64, device=dev())
+    sym.symnmf_row_norms(c, S, norms)
+    norms, Cn, lab, best = from_dev(norms), from_dev(C), from_dev(labels).astype(np.int64), from_dev(best)
+    # centroids are unit columns
+    assert np.max(np.abs(np.linalg.norm(Cn, axis=0) - 1.0)) < 1e-5
+    Z = o.standardise_columns(X)
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([[0, 255, 256, 99839, n - 1], rng.integers(0, n, 40)]))
+    for r in rows:
+        s = o.abs_corr_panel(Z, int(r), 1)[0]
+        ns = np.linalg.norm(s)
+        assert norms[r] == pytest.approx(ns, rel=2e-6)
+        cos = s @ Cn / ns
+        top = cos.max()
+        assert cos[lab[r]] >= top - 1e-5, r
+        assert best[r] == pytest.approx(cos[lab[r]], abs=1e-5)
+    assert (st["converged"] == 1) or st["iters"] == 3
+
+
 @pytest.fixture(scope="module")
 def tpdm4096():
     X = synth.tpdm_returns(0, T=20000, n=4096, groups=16, nu=3.0).X.numpy()

@@ -1,0 +1,258 @@
+"""Parity of spherical K-means on the rows of S and of the cosine silhouette
+(HIP, through the C ABI) with the FP64 oracle.
+
+The oracle runs on the stored S (decoded to FP64), so storage rounding is
+common to both sides.  Tolerances: FP64 storage 1e-10 relative (summation
+order only).  FP32 factors: products S C accumulate n FP32 terms, so cosines
+carry errors of order sqrt(n) 2^-24 ~ 1e-6; an assignment is compared label
+for label wherever the oracle's winning cosine beats the runner-up by more
+than MARGIN = 1e-5, and elsewhere the GPU's choice must be within MARGIN of
+the best (both choices are then correct to the precision of the products).
+Sizes span several 256-row tiles with a ragged tail (n = 600, 1100)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as o
+import oracle.kmeans_oracle as km
+import paper_2607_24518_amd as sym
+import synth
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import ctx, dev, from_dev, stored_numpy, to_dev  # noqa: E402
+
+MARGIN = 1e-5
+DTYPES = ["fp64", "fp32", "bf16", "fp8"]
+
+
+@pytest.fixture(scope="module")
+def X600():
+    return synth.c1_instance(0, T=700, n=600, groups=6)
+
+
+@pytest.fixture(scope="module")
+def stores(X600):
+    c = ctx()
+    X = to_dev(X600.X.numpy())
+    out = {}
+    for d in DTYPES:
+        S = sym.symnmf_build_S(c, X, kind=sym.ABS_CORR, dtype=sym.DTYPES[d], fp8_panel_rows=128)
+        out[d] = (S, stored_numpy(S))
+    return out
+
+
+def _fdt(d):
+    return torch.float64 if d == "fp64" else torch.float32
+
+
+def _check_assignment(Shat, C_oracle_rows, labels_gpu, best_gpu=None, J_gpu=None, rel=1e-6):
+    cos = Shat @ C_oracle_rows.T
+    order = np.sort(cos, axis=1)
+    top = order[:, -1]
+    margin = top - order[:, -2] if cos.shape[1] > 1 else np.full(cos.shape[0], np.inf)
+    lab_o = np.argmax(cos, axis=1)
+    clear = margin > MARGIN
+    assert np.array_equal(labels_gpu[clear], lab_o[clear])
+    chosen = cos[np.arange(cos.shape[0]), labels_gpu]
+    assert np.all(chosen >= top - MARGIN)
+    if best_gpu is not None:
+        assert np.max(np.abs(best_gpu - chosen)) < max(rel, 1e-12) * 4
+    if J_gpu is not None:
+        assert J_gpu == pytest.approx(float(np.sum(1.0 - top)), rel=rel, abs=rel * 10)
+    return clear.mean()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_row_norms(stores, dtype):
+    S, M = stores[dtype]
+    norms = torch.zeros(600, dtype=torch.float64, device=dev())
+    sym.symnmf_row_norms(ctx(), S, norms)
+    _, ref = km.unit_rows(M)
+    assert np.max(np.abs(from_dev(norms) / ref - 1.0)) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_assignment_step(stores, dtype):
+    S, M = stores[dtype]
+    Shat, _ = km.unit_rows(M)
+    res = km.lloyd(M, 6, seed=3, max_iter=2)                 # centroids that are not yet a fixed point
+    C = to_dev(res["C"].T, _fdt(dtype))                      # n x K, column k = centroid k
+    labels = torch.full((600,), -7, dtype=torch.int32, device=dev())
+    best = torch.zeros(600, dtype=_fdt(dtype), device=dev())
+    J = sym.symnmf_kmeans_assign(ctx(), S, C, labels, best)
+    rel = 1e-12 if dtype == "fp64" else 2e-6
+    frac = _check_assignment(Shat, res["C"], from_dev(labels).astype(np.int64), from_dev(best), J, rel)
+    assert frac > 0.95
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_centroid_step(stores, dtype):
+    S, M = stores[dtype]
+    Shat, _ = km.unit_rows(M)
+    rng = np.random.default_rng(1)
+    labels = rng.integers(-1, 5, 600)                        # -1: in no cluster; cluster 5 of 6 stays empty
+    prev = rng.random((6, 600))
+    prev /= np.linalg.norm(prev, axis=1, keepdims=True)
+    ref = km.centroids(Shat, labels, 6, prev)
+    C = torch.zeros((600, 6), dtype=_fdt(dtype), device=dev())
+    sym.symnmf_kmeans_centroids(ctx(), S, to_dev(labels, torch.int32), 6, C, to_dev(prev.T, _fdt(dtype)))
+    got = from_dev(C).T
+    assert np.array_equal(got[5], prev[5].astype(np.float32).astype(np.float64) if dtype != "fp64" else prev[5])
+    if dtype == "fp64":
+        assert np.max(np.abs(got - ref)) < 1e-13
+    elif dtype in ("fp32", "bf16"):
+        assert np.max(np.abs(got - ref)) < 2e-6
+    else:
+        # FP8 storage with per-row-panel scales is symmetric only up to one
+        # quantisation step, and the update reads columns of S: a centroid is
+        # then within that step of the row-based one
+        cosines = np.sum(got[:5] * ref[:5], axis=1)
+        assert np.all(cosines > 1 - 1e-4)
+
+
+def test_centroid_step_rejects_labels_out_of_range(stores):
+    S, _ = stores["fp32"]
+    labels = torch.zeros(600, dtype=torch.int32, device=dev())
+    labels[17] = 6
+    C = torch.zeros((600, 6), dtype=torch.float32, device=dev())
+    with pytest.raises(sym.SymnmfError) as e:
+        sym.symnmf_kmeans_centroids(ctx(), S, labels, 6, C)
+    assert e.value.code == sym.EINVAL
+
+
+def test_lloyd_fp64_trajectory_is_the_oracle_s(stores):
+    S, M = stores["fp64"]
+    for seed, K in [(0, 6), (4, 9), (2, 3)]:
+        ref = km.lloyd(M, K, seed=seed, tol=1e-4, max_iter=50)
+        labels = torch.zeros(600, dtype=torch.int32, device=dev())
+        C = torch.zeros((600, K), dtype=torch.float64, device=dev())
+        st = sym.symnmf_kmeans(ctx(), S, K, labels, seed=seed, tol=1e-4, max_iter=50, C=C)
+        assert st["converged"] == 1 and st["iters"] == ref["iters"]
+        assert np.array_equal(from_dev(labels).astype(np.int64), ref["labels"])
+        assert st["J0"] == pytest.approx(ref["history"][0], rel=1e-10)
+        assert st["J"] == pytest.approx(ref["J"], rel=1e-10)
+        assert np.max(np.abs(from_dev(C).T - ref["C"])) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_lloyd_fp32_factors_follow_the_oracle(stores, dtype):
+    S, M = stores[dtype]
+    ref = km.lloyd(M, 6, seed=0, tol=1e-4, max_iter=50)
+    labels = torch.zeros(600, dtype=torch.int32, device=dev())
+    C = torch.zeros((600, 6), dtype=torch.float32, device=dev())
+    st = sym.symnmf_kmeans(ctx(), S, 6, labels, seed=0, tol=1e-4, max_iter=50, C=C)
+    lab = from_dev(labels).astype(np.int64)
+    Shat, _ = km.unit_rows(M)
+    # the oracle's final assignment is decided by more than the margin
+    cos = np.sort(Shat @ ref["C"].T, axis=1)
+    assert np.min(cos[:, -1] - cos[:, -2]) > 10 * MARGIN
+    assert st["converged"] == 1 and st["iters"] == ref["iters"]
+    assert np.array_equal(lab, ref["labels"])
+    assert st["J"] == pytest.approx(ref["J"], rel=2e-6)
+    assert np.max(np.abs(from_dev(C).T - ref["C"])) < 2e-6
+
+
+def test_lloyd_fp8_reaches_a_fixed_point(stores):
+    S, M = stores["fp8"]
+    labels = torch.zeros(600, dtype=torch.int32, device=dev())
+    C = torch.zeros((600, 6), dtype=torch.float32, device=dev())
+    st = sym.symnmf_kmeans(ctx(), S, 6, labels, seed=0, tol=1e-4, max_iter=50, C=C)
+    assert st["converged"] == 1
+    lab = from_dev(labels).astype(np.int64)
+    Shat, _ = km.unit_rows(M)
+    _check_assignment(Shat, from_dev(C).T, lab)   # labels are the argmax of the returned centroids
+    ref = km.lloyd(M, 6, seed=0, tol=1e-4, max_iter=50)
+    assert st["J"] == pytest.approx(ref["J"], rel=1e-3)
+
+
+def test_lloyd_beyond_64_clusters_uses_several_slices():
+    inst = synth.c1_instance(2, T=900, n=1100, groups=10)
+    c = ctx()
+    X = to_dev(inst.X.numpy())
+    for d in ["fp64", "fp32"]:
+        S = sym.symnmf_build_S(c, X, dtype=sym.DTYPES[d])
+        M = stored_numpy(S)
+        K = 100
+        labels = torch.zeros(1100, dtype=torch.int32, device=dev())
+        C = torch.zeros((1100, K), dtype=_fdt(d), device=dev())
+        if d == "fp64":
+            ref = km.lloyd(M, K, seed=5, tol=1e-4, max_iter=40)
+            st = sym.symnmf_kmeans(c, S, K, labels, seed=5, tol=1e-4, max_iter=40, C=C)
+            assert st["iters"] == ref["iters"] and st["J"] == pytest.approx(ref["J"], rel=1e-10)
+            assert np.array_equal(from_dev(labels).astype(np.int64), ref["labels"])
+        else:
+            # one assignment and one update step against the oracle
+            ref = km.lloyd(M, K, seed=5, max_iter=1)
+            C0 = to_dev(ref["C"].T, torch.float32)
+            J = sym.symnmf_kmeans_assign(c, S, C0, labels)
+            Shat, _ = km.unit_rows(M)
+            _check_assignment(Shat, ref["C"], from_dev(labels).astype(np.int64), J_gpu=J, rel=2e-6)
+            lab = from_dev(labels).astype(np.int64)
+            sym.symnmf_kmeans_centroids(c, S, labels, K, C, C0)
+            want = km.centroids(Shat, lab, K, ref["C"])
+            assert np.max(np.abs(from_dev(C).T - want)) < 2e-6
+
+
+def test_planted_groups_recovered_from_one_seed_each(X600, stores):
+    truth = X600.labels.numpy()
+    init = [int(np.flatnonzero(truth == g)[0]) for g in range(6)]
+    for d in DTYPES:
+        S, _ = stores[d]
+        labels = torch.zeros(600, dtype=torch.int32, device=dev())
+        sym.symnmf_kmeans(ctx(), S, 6, labels, init_rows=init)
+        assert np.array_equal(from_dev(labels).astype(np.int64), truth)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_silhouette(stores, dtype):
+    S, M = stores[dtype]
+    ref_run = km.lloyd(M, 6, seed=1)
+    lab = ref_run["labels"].copy()
+    # FP8 storage is symmetric only up to one quantisation step and the
+    # cluster sums read columns of S, which moves the mean by ~1e-5
+    rel = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-5, "fp8": 1e-4}[dtype]
+    got = sym.symnmf_silhouette(ctx(), S, to_dev(lab, torch.int32), 6)
+    want = km.silhouette_cosine(M, lab)
+    assert got == pytest.approx(want, rel=rel)
+    lab[7] = 6                                               # a singleton, K = 7, and an empty cluster 8
+    got = sym.symnmf_silhouette(ctx(), S, to_dev(lab, torch.int32), 9)
+    # with FP8 storage the distances to the singleton read one column of S
+    # instead of its row, without the averaging over members: ~2e-3
+    assert got == pytest.approx(km.silhouette_cosine(M, lab), rel=5e-3 if dtype == "fp8" else rel)
+
+
+def test_edge_cases(stores):
+    c = ctx()
+    S, M = stores["fp64"]
+    labels = torch.zeros(600, dtype=torch.int32, device=dev())
+    # K = 1: one cluster; the first update moves the centroid, the second
+    # changes nothing and the stop rule fires
+    st = sym.symnmf_kmeans(c, S, 1, labels, seed=0)
+    Shat, _ = km.unit_rows(M)
+    assert st["iters"] == 2 == km.lloyd(M, 1, seed=0)["iters"]
+    assert st["converged"] == 1 and np.all(from_dev(labels) == 0)
+    assert st["J"] == pytest.approx(600 - np.linalg.norm(Shat.sum(axis=0)), rel=1e-10)
+    with pytest.raises(sym.SymnmfError):                     # one cluster has no silhouette
+        sym.symnmf_silhouette(c, S, labels, 1)
+    # K = n: every row its own centroid
+    small = sym.symnmf_S_load(c, to_dev(M[:300, :300], torch.float64), dtype=sym.S_FP64)
+    lab300 = torch.zeros(300, dtype=torch.int32, device=dev())
+    st = sym.symnmf_kmeans(c, small, 300, lab300, seed=3)
+    assert st["J0"] < 1e-12 and st["converged"] == 1 and st["empty"] == 0
+    assert sorted(from_dev(lab300).astype(np.int64).tolist()) == list(range(300))
+    for bad in [dict(K=601), dict(K=0), dict(K=3, init_rows=[4, 4, 5]), dict(K=2, init_rows=[0, 600])]:
+        with pytest.raises(sym.SymnmfError) as e:
+            sym.symnmf_kmeans(c, S, bad.pop("K"), labels, **bad)
+        assert e.value.code == sym.EINVAL
+    # max_iter = 0: labels of the seeds' assignment, ENOTCONV
+    st = sym.symnmf_kmeans(c, S, 6, labels, seed=0, max_iter=0, allow_notconv=True)
+    assert st["converged"] == 0 and st["iters"] == 0
+    ref = km.lloyd(M, 6, seed=0, max_iter=0)
+    assert np.array_equal(from_dev(labels).astype(np.int64), ref["labels"])
+    # a row panel is not a full set of points
+    pan = sym.symnmf_build_S(c, to_dev(synth.c1_instance(0, T=300, n=512).X.numpy()), dtype=sym.S_FP32, row0=0,
+                             rows=256)
+    with pytest.raises(sym.SymnmfError) as e:
+        sym.symnmf_kmeans(c, pan, 4, labels)
+    assert e.value.code == sym.EUNSUPPORTED
