@@ -485,6 +485,56 @@ def kmeans_cpu_baseline(X_host, K, rows):
                       f"at K={K} ({reps} timed, {dt:.3f} s each), scaled by {n}/{rows}"}
 
 
+def kmeans_paper_benchmark(args, ctx, Ks):
+    """K-means on the appendix's own benchmark matrices (floor(sqrt(n))
+    groups plus the common factor, 40000 samples; |corr| and the raw-marginal
+    TPDM with the top 1 % of samples), one instance and seeding per seed, as
+    in the paper's K-means table (means over seeds 7, 42, 99)."""
+    import torch
+    import paper_2607_24518_amd as sym
+    import synth
+    dev = torch.device("cuda:0")
+    n = args.n
+    runs = []
+    for kind in args.kmeans_kinds.split(","):
+        for seed in [int(v) for v in args.kmeans_seeds.split(",")]:
+            log(f"paper benchmark {kind} n={n} seed={seed}")
+            X = synth.paper_benchmark(seed, n, kind, device=dev).X
+            torch.cuda.synchronize()
+            for dname in args.kmeans_dtypes.split(","):
+                if kind == "corr":
+                    S = sym.symnmf_build_S(ctx, X, kind=sym.ABS_CORR, dtype=sym.DTYPES[dname])
+                else:
+                    S = sym.symnmf_build_S(ctx, X, kind=sym.TPDM, dtype=sym.DTYPES[dname], q=0.01, lower_tail=0,
+                                           raw_marginals=1)
+                for K in Ks:
+                    labels = torch.zeros(n, dtype=torch.int32, device=dev)
+                    for rep in range(args.kmeans_reps):
+                        t0 = time.perf_counter()
+                        st = sym.symnmf_kmeans(ctx, S, K, labels, seed=seed, tol=1e-4,
+                                               max_iter=args.kmeans_max_iter, allow_notconv=True)
+                        wall = time.perf_counter() - t0
+                    sil = sym.symnmf_silhouette(ctx, S, labels, K)
+                    rec = {"kind": kind, "seed": seed, "S_storage": dname, "K": K, "seconds": round(wall, 4),
+                           "iters": st["iters"], "converged": bool(st["converged"]), "J": st["J"],
+                           "silhouette": round(sil, 4)}
+                    log(f"kmeans {rec}")
+                    runs.append(rec)
+                del S
+                torch.cuda.empty_cache()
+            del X
+            torch.cuda.empty_cache()
+    means = {}
+    for r in runs:
+        key = f"{r['kind']}_{r['S_storage']}_K{r['K']}"
+        means.setdefault(key, []).append(r)
+    summary = {k: {"seconds": round(sum(r["seconds"] for r in v) / len(v), 4),
+                   "iters": round(sum(r["iters"] for r in v) / len(v), 2),
+                   "silhouette": round(sum(r["silhouette"] for r in v) / len(v), 4),
+                   "converged": all(r["converged"] for r in v), "seeds": len(v)} for k, v in means.items()}
+    return {"runs": runs, "means": summary}
+
+
 def kmeans_bench(args):
     """Spherical K-means on the rows of the n = 10^5 |corr| S: wall time of
     symnmf_kmeans to the stop rule (relative drop of sum(1 - cos) below 1e-4)
@@ -494,11 +544,13 @@ def kmeans_bench(args):
     import synth
     dev = torch.device("cuda:0")
     n = args.n
-    log(f"generating returns T={args.T} n={n} groups={args.groups}")
-    X = synth.overlap_returns(args.seed, T=args.T, n=n, groups=args.groups, device=dev).X
     ctx = sym.symnmf_create(0)
     Ks = [int(v) for v in args.kmeans.split(",") if v]
     runs = []
+    if args.kmeans_family == "paper":
+        return kmeans_paper_benchmark(args, ctx, Ks)
+    log(f"generating returns T={args.T} n={n} groups={args.groups}")
+    X = synth.overlap_returns(args.seed, T=args.T, n=n, groups=args.groups, device=dev).X
     for dname in args.kmeans_dtypes.split(","):
         S = sym.symnmf_build_S(ctx, X, kind=sym.ABS_CORR, dtype=sym.DTYPES[dname], fp8_panel_rows=256)
         torch.cuda.synchronize()
@@ -587,13 +639,18 @@ def main():
     ap.add_argument("--kmeans-seed", type=int, default=7)
     ap.add_argument("--kmeans-max-iter", type=int, default=100)
     ap.add_argument("--kmeans-reps", type=int, default=2, help="runs per case; the last is reported")
+    ap.add_argument("--kmeans-family", default="overlap", choices=["overlap", "paper"],
+                    help="overlapping-groups returns, or the appendix's benchmark matrices (--kmeans-kinds)")
+    ap.add_argument("--kmeans-kinds", default="corr,tpdm")
+    ap.add_argument("--kmeans-seeds", default="7,42,99")
     args = ap.parse_args()
 
     if args.kmeans:
         res = kmeans_bench(args)
         print(json.dumps({"metric": "spherical K-means on the rows of S: wall time to the stop rule", "unit": "s",
                           "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
-                          "config": {"workload": f"abs_corr_n{args.n}_T{args.T}_groups{args.groups}",
+                          "config": {"workload": (f"paper_benchmark_n{args.n}_T40000" if args.kmeans_family == "paper"
+                                                  else f"abs_corr_n{args.n}_T{args.T}_groups{args.groups}"),
                                      "stop": "relative drop of sum(1 - cos) below 1e-4"},
                           **res}), flush=True)
         return
