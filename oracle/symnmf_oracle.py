@@ -16,9 +16,10 @@ numpy primitives (matmul, sort) as the only library steps:
   explicit n x n residual (eq. symnmf); gradient 4(H(H^T H) - SH)
   (section "Memory-Efficient Loss Reformulation").
 * Update rules of appendix "Detailed Algorithm Descriptions", family 3:
-  AdaGrad, RMSprop, their softplus (LogSpace) forms (eq. logspace_grad),
-  Piecewise AdaGrad, Row-Stochastic SVRG, Block-SVRG AdaptGrow; and
-  family 6, ADMM (eqs. admm_H, admm_W, admm_U).
+  AdaGrad, RMSprop, Adam, NAdam, Adan, their softplus (LogSpace) forms
+  (eq. logspace_grad), Piecewise AdaGrad, Row-Stochastic SVRG, Block-SVRG
+  AdaptGrow; family 1, the dampened multiplicative update; and family 6, ADMM
+  (eqs. admm_H, admm_W, admm_U).
 * The three-criterion stop rule (eqs. proj_grad, loss_gate, kkt_stop,
   kkt_scaled, obj_stag, conv_and).
 
@@ -360,6 +361,46 @@ def rmsprop_update(X, v, m, g, eta, eps, alpha, mu, project=True):
     return (np.maximum(X, 0.0) if project else X), v, m
 
 
+def adam_update(X, m, v, g, t, eta, eps, beta1, beta2, nesterov=False, project=True):
+    """Adam (appendix family 3), step t = 1, 2, ...:
+    m = b1 m + (1-b1) g ; v = b2 v + (1-b2) g^2 ; m^ = m/(1-b1^t) ; v^ = v/(1-b2^t) ;
+    X <- [X - eta m^ / (sqrt(v^) + eps)]_+ .
+    NAdam (nesterov=True) uses b1 m^ + (1-b1) g/(1-b1^t) in place of m^."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    if nesterov:
+        mhat = beta1 * mhat + (1.0 - beta1) * g / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    X = X - eta * mhat / (np.sqrt(vhat) + eps)
+    return (np.maximum(X, 0.0) if project else X), m, v
+
+
+def adan_update(X, m, d, nv, g, g_prev, t, eta, eps, beta1, beta2, beta3, project=True):
+    """Adan (Xie et al., "Adan: Adaptive Nesterov Momentum Algorithm", 2023,
+    Algorithm 1), written with the beta's as decay factors and bias-corrected
+    averages; the three buffers are the gradient average m, the average d of
+    gradient differences and the second moment nv of the Nesterov-corrected
+    gradient.  With diff = g - g_prev (0 at the first step, g_prev = None):
+    m = b1 m + (1-b1) g ; d = b2 d + (1-b2) diff ; nv = b3 nv + (1-b3)(g + b2 diff)^2 ;
+    X <- [X - eta (m/(1-b1^t) + b2 d/(1-b2^t)) / (sqrt(nv/(1-b3^t)) + eps)]_+ ."""
+    diff = np.zeros_like(g) if g_prev is None else g - g_prev
+    m = beta1 * m + (1.0 - beta1) * g
+    d = beta2 * d + (1.0 - beta2) * diff
+    u = g + beta2 * diff
+    nv = beta3 * nv + (1.0 - beta3) * u * u
+    step = (m / (1.0 - beta1 ** t) + beta2 * d / (1.0 - beta2 ** t)) / (np.sqrt(nv / (1.0 - beta3 ** t)) + eps)
+    X = X - eta * step
+    return (np.maximum(X, 0.0) if project else X), m, d, nv
+
+
+def mu_update(H, SH, HG, eps):
+    """Dampened multiplicative update (appendix family 1, He et al. 2011):
+    H <- (1/2) H * (1 + SH / (H (H^T H) + eps)), eps = fp32 machine epsilon in
+    the paper.  Keeps H >= 0 without a projection."""
+    return 0.5 * H * (1.0 + SH / (HG + eps))
+
+
 def admm_update(S, W, U, rho, SW=None):
     """One ADMM iteration (appendix family 6): the least-squares H of the
     bilinear surrogate ||S - H W^T||^2 with consensus penalty (eq. admm_H),
@@ -389,7 +430,7 @@ def piecewise_reset(g, c):
 # ---------------------------------------------------------------------------
 # Solver (state machine shared by every method).
 # ---------------------------------------------------------------------------
-ADAGRAD, RMSPROP, PIECEWISE_ADAGRAD, ROW_SVRG, BLOCK_SVRG, ADMM = range(6)
+ADAGRAD, RMSPROP, PIECEWISE_ADAGRAD, ROW_SVRG, BLOCK_SVRG, ADMM, ADAM, NADAM, ADAN, MU = range(10)
 
 
 @dataclass
@@ -419,6 +460,9 @@ class Params:
     tau_stag: float = 1e-5
     seed: int = 0
     rho: float = 500.0         # ADMM consensus penalty
+    beta1: float = 0.9         # Adam / NAdam / Adan first-moment decay
+    beta2: float = 0.999       # Adam / NAdam second moment; Adan difference average
+    beta3: float = 0.99        # Adan second moment
 
 
 @dataclass
@@ -464,6 +508,9 @@ class Solver:
       (H0, 0); step t records the statistics of W_t (the paper tracks
       convergence on the feasible factor) and applies eqs. admm_H, admm_W,
       admm_U in that order.
+    * Adam / NAdam / Adan: zero buffers, bias correction with the step count
+      t + 1; Adan's first gradient difference is zero.  MU has no step size
+      and no softplus form.
     """
 
     def __init__(self, S, k: int, params: Params, H0):
@@ -479,6 +526,11 @@ class Solver:
         self.G = np.zeros_like(self.H)       # AdaGrad accumulator (or RMSprop v)
         self.m = np.zeros_like(self.H)       # RMSprop momentum
         self.U = np.zeros_like(self.H)       # ADMM scaled dual
+        self.d = np.zeros_like(self.H)       # Adan average of gradient differences
+        self.nv = np.zeros_like(self.H)      # Adan second moment
+        self.g_prev = None                   # Adan previous gradient
+        if params.method == MU and params.softplus:
+            raise ValueError("MU keeps H >= 0 by construction and has no softplus form")
         self.mu_snap = None
         self.t = 0
         self.phi = params.phi0 if params.method == BLOCK_SVRG else 1.0
@@ -555,8 +607,27 @@ class Solver:
             if p.method in (ROW_SVRG, BLOCK_SVRG):
                 self.mu_snap = g.copy()
         self.last_g = g
+        tb = self.t + 1                                        # bias-correction step count
         if p.method == ADMM:
             self.H, self.U = admm_update(self.S, self.H, self.U, p.rho, SH)
+        elif p.method == MU:
+            self.H = mu_update(self.H, SH, self.H @ (self.H.T @ self.H), p.eps)
+        elif p.method in (ADAM, NADAM, ADAN):
+            x = self.theta if p.softplus else self.H
+            gx = g * sigmoid(self.theta) if p.softplus else g   # eq. logspace_grad
+            if p.method == ADAN:
+                x, self.m, self.d, self.nv = adan_update(x, self.m, self.d, self.nv, gx, self.g_prev, tb, p.eta,
+                                                         p.eps, p.beta1, p.beta2, p.beta3,
+                                                         project=not p.softplus)
+                self.g_prev = gx
+            else:
+                x, self.m, self.G = adam_update(x, self.m, self.G, gx, tb, p.eta, p.eps, p.beta1, p.beta2,
+                                                nesterov=p.method == NADAM, project=not p.softplus)
+            if p.softplus:
+                self.theta = x
+                self.H = softplus(x)
+            else:
+                self.H = x
         elif p.softplus:
             g_theta = g * sigmoid(self.theta)                 # eq. logspace_grad
             if p.method == RMSPROP:
