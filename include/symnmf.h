@@ -75,8 +75,17 @@ typedef enum {
     SYMNMF_PIECEWISE_ADAGRAD = 2,
     SYMNMF_ROW_SVRG = 3,
     SYMNMF_BLOCK_SVRG = 4,   /* Block-SVRG AdaptGrow */
-    SYMNMF_ADMM = 5          /* eqs. admm_H, admm_W, admm_U; the iterate is W, the
+    SYMNMF_ADMM = 5,         /* eqs. admm_H, admm_W, admm_U; the iterate is W, the
                                 dual U starts at 0; projected form only */
+    SYMNMF_ADAM = 6,         /* family 3: bias-corrected first and second moments
+                                (beta1, beta2), step eta m^ / (sqrt(v^) + eps) */
+    SYMNMF_NADAM = 7,        /* Adam with the look-ahead b1 m^ + (1 - b1) g / (1 - b1^t) */
+    SYMNMF_ADAN = 8,         /* Xie et al. 2023: averages of g (beta1), of g - g_prev
+                                (beta2) and of (g + beta2 (g - g_prev))^2 (beta3),
+                                bias-corrected; the first difference is 0 */
+    SYMNMF_MU = 9            /* family 1, dampened multiplicative update
+                                H <- H (1 + SH / (H H^T H + eps)) / 2 (eps: fp32
+                                machine epsilon in the paper); no eta, no softplus form */
 } symnmf_method;
 
 typedef struct symnmf_ctx symnmf_ctx;
@@ -143,6 +152,10 @@ typedef struct {
     double tau_stag;         /* stagnation tolerance (eq. obj_stag)               */
     uint64_t seed;           /* key of the index-set sampler                      */
     double rho;              /* ADMM consensus penalty rho > 0                    */
+    double beta1;            /* Adam / NAdam / Adan: decay of the gradient average (0.9) */
+    double beta2;            /* Adam / NAdam: second-moment decay (0.999); Adan: decay of
+                                the gradient-difference average (0.92 in Xie et al.) */
+    double beta3;            /* Adan: second-moment decay (0.99)                   */
 } symnmf_params;
 
 /* Statistics of one iteration, of the iterate H_t that the step read. */
@@ -237,7 +250,9 @@ symnmf_status symnmf_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st, 
  * precision: float32, or float64 for FP64 S).  which: 0 = current iterate,
  * 1 = previous iterate, 2 = accumulator G (RMSprop v), 3 = RMSprop momentum
  * (ADMM: the scaled dual U), 4 = Theta (softplus), 5 = snapshot gradient mu,
- * 6 = gradient of the last step. */
+ * 6 = gradient of the last step, 7 = Adan average of gradient differences,
+ * 8 = Adan previous gradient.  For Adam / NAdam / Adan, 2 holds the second
+ * moment and 3 the gradient average. */
 symnmf_status symnmf_state_read(symnmf_ctx* ctx, symnmf_state* st, int32_t which, void* dst);
 /* Host copy of the statistics of the last step (synchronises). */
 symnmf_status symnmf_state_stats(symnmf_ctx* ctx, symnmf_state* st, symnmf_stats* out);

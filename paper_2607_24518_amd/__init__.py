@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libsymnmf.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, ENOTCONV, EUNSUPPORTED = range(7)
 S_FP32, S_BF16, S_FP8, S_FP64 = range(4)
 ABS_CORR, TPDM = range(2)
-ADAGRAD, RMSPROP, PIECEWISE_ADAGRAD, ROW_SVRG, BLOCK_SVRG, ADMM = range(6)
+ADAGRAD, RMSPROP, PIECEWISE_ADAGRAD, ROW_SVRG, BLOCK_SVRG, ADMM, ADAM, NADAM, ADAN, MU = range(10)
 DTYPES = {"fp32": S_FP32, "bf16": S_BF16, "fp8": S_FP8, "fp64": S_FP64}
 
 c_i32, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
@@ -43,7 +43,8 @@ class symnmf_params(ctypes.Structure):
                 ("phi0", c_dbl), ("c_grow", c_dbl), ("grow_checks", c_i64), ("snapshot_s", c_i64),
                 ("block_rows", c_i64), ("independent_blocks", c_i32), ("reserved0", c_i32),
                 ("delta", c_i64), ("warmup", c_i64), ("max_iter", c_i64), ("tau_E", c_dbl),
-                ("tau_g_inf", c_dbl), ("n_ref", c_dbl), ("tau_stag", c_dbl), ("seed", c_u64), ("rho", c_dbl)]
+                ("tau_g_inf", c_dbl), ("n_ref", c_dbl), ("tau_stag", c_dbl), ("seed", c_u64), ("rho", c_dbl),
+                ("beta1", c_dbl), ("beta2", c_dbl), ("beta3", c_dbl)]
 
 
 class symnmf_stats(ctypes.Structure):

@@ -316,6 +316,11 @@ struct UpdateArgs {
     int32_t* tile_bad;    // [tiles] non-finite gradient count
     double rho;           // ADMM consensus penalty
     void* minv;           // ADMM: (2 W^T W + rho I)^-1, k x k (state precision)
+    double beta1, beta2, beta3;   // Adam / NAdam / Adan decays
+    double bc1, bc2, bc3;         // 1 - beta^(t+1): bias corrections of this step
+    int32_t first;                // first step (Adan: zero gradient difference)
+    void* D;              // Adan average of gradient differences
+    void* Gp;             // Adan previous gradient
 };
 hipError_t launch_update(const UpdateArgs& a, int h_f64, const PlanView& plan, hipStream_t stream);
 // ADMM step (full plans): the k x k inverse from the FP64 Gram of W_t, then the

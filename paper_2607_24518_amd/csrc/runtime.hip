@@ -84,6 +84,7 @@ struct symnmf_state {
     int cur = 0;
     void *G = nullptr, *M = nullptr, *Theta = nullptr, *Mu = nullptr, *Gout = nullptr, *part = nullptr;
     void* minv = nullptr;            // ADMM: (2 W^T W + rho I)^-1 (M holds the dual U)
+    void *D = nullptr, *Gp = nullptr;   // Adan: average of gradient differences, previous gradient
     double *tile_gram = nullptr, *tile_tr = nullptr, *tile_kkt = nullptr;
     int32_t* tile_bad = nullptr;
     double* gram64[2] = {nullptr, nullptr};
@@ -114,7 +115,7 @@ struct symnmf_state {
 
 extern "C" {
 
-int32_t symnmf_abi_version(void) { return 2; }
+int32_t symnmf_abi_version(void) { return 3; }
 
 void symnmf_params_default(symnmf_params* p) {
     std::memset(p, 0, sizeof(*p));
@@ -143,6 +144,9 @@ void symnmf_params_default(symnmf_params* p) {
     p->tau_stag = 1e-5;
     p->seed = 0;
     p->rho = 500.0;
+    p->beta1 = 0.9;
+    p->beta2 = 0.999;
+    p->beta3 = 0.99;
 }
 
 symnmf_status symnmf_create(symnmf_ctx** out, int32_t device, void* hip_stream) {
@@ -398,8 +402,14 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
     const int h_f64 = S->dtype == SYMNMF_S_FP64;
     if (h_f64 && !h0_is_f64) return fail(ctx, SYMNMF_EINVAL, "state_create: FP64 S needs an FP64 H0");
     if (h_f64 && k > 32) return fail(ctx, SYMNMF_EUNSUPPORTED, "state_create: FP64 state supports k <= 32");
-    if (p->method < SYMNMF_ADAGRAD || p->method > SYMNMF_ADMM)
+    if (p->method < SYMNMF_ADAGRAD || p->method > SYMNMF_MU)
         return fail(ctx, SYMNMF_EINVAL, "state_create: bad method");
+    if (p->method == SYMNMF_MU && p->softplus)
+        return fail(ctx, SYMNMF_EINVAL, "state_create: MU keeps H >= 0 by construction and has no softplus form");
+    if ((p->method == SYMNMF_ADAM || p->method == SYMNMF_NADAM || p->method == SYMNMF_ADAN) &&
+        !(p->beta1 >= 0.0 && p->beta1 < 1.0 && p->beta2 >= 0.0 && p->beta2 < 1.0 && p->beta3 >= 0.0 &&
+          p->beta3 < 1.0))
+        return fail(ctx, SYMNMF_EINVAL, "state_create: beta1, beta2, beta3 must lie in [0, 1)");
     if (p->method == SYMNMF_ADMM && (!(p->rho > 0.0) || p->softplus))
         return fail(ctx, SYMNMF_EINVAL, "state_create: ADMM needs rho > 0 and the projected form");
     if (!(p->eta > 0.0) || !(p->eps >= 0.0) || p->delta < 1 || p->max_iter < 0)
@@ -451,7 +461,13 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
     ALLOC(st->H[0], hbytes);
     ALLOC(st->H[1], hbytes);
     ALLOC(st->G, pbytes);
-    if (p->method == SYMNMF_RMSPROP || p->method == SYMNMF_ADMM) ALLOC(st->M, pbytes);
+    if (p->method == SYMNMF_RMSPROP || p->method == SYMNMF_ADMM || p->method == SYMNMF_ADAM ||
+        p->method == SYMNMF_NADAM || p->method == SYMNMF_ADAN)
+        ALLOC(st->M, pbytes);
+    if (p->method == SYMNMF_ADAN) {
+        ALLOC(st->D, pbytes);
+        ALLOC(st->Gp, pbytes);
+    }
     if (p->method == SYMNMF_ADMM) ALLOC(st->minv, k * k * st->hsz);
     if (p->softplus) ALLOC(st->Theta, pbytes);
     if (svrg) ALLOC(st->Mu, pbytes);
@@ -560,7 +576,21 @@ static symnmf_status do_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* s
     a.n = st->n;
     a.k = st->k;
     a.row0 = st->row0;
-    a.method = p.method == SYMNMF_RMSPROP ? SYMNMF_RMSPROP : SYMNMF_ADAGRAD;
+    // Piecewise AdaGrad and the SVRG variants step with the AdaGrad rule
+    a.method = (p.method == SYMNMF_PIECEWISE_ADAGRAD || p.method == SYMNMF_ROW_SVRG ||
+                p.method == SYMNMF_BLOCK_SVRG) ? SYMNMF_ADAGRAD : p.method;
+    a.beta1 = p.beta1;
+    a.beta2 = p.beta2;
+    a.beta3 = p.beta3;
+    {   // bias corrections of step count t + 1
+        const double tb = (double)(t + 1);
+        a.bc1 = 1.0 - std::pow(p.beta1, tb);
+        a.bc2 = 1.0 - std::pow(p.beta2, tb);
+        a.bc3 = 1.0 - std::pow(p.beta3, tb);
+    }
+    a.first = t == 0 ? 1 : 0;
+    a.D = st->D;
+    a.Gp = st->Gp;
     a.softplus = p.softplus;
     a.eta = p.eta;
     a.eps = p.eps;
@@ -677,6 +707,8 @@ symnmf_status symnmf_state_read(symnmf_ctx* ctx, symnmf_state* st, int32_t which
         case 4: src = st->Theta; break;
         case 5: src = st->Mu; break;
         case 6: src = st->Gout; break;
+        case 7: src = st->D; break;
+        case 8: src = st->Gp; break;
         default: return fail(ctx, SYMNMF_EINVAL, "state_read: bad buffer id %d", which);
     }
     (void)off;

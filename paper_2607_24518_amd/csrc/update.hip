@@ -80,14 +80,12 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
         if (prow < a.rows) {
             const HT h = Hs[r * KB + c];
             const int64_t idx = prow * k + c;
-            HT g;
+            HT g, sh = 0, hg = 0;
             if (act >= 0) {
-                HT sh = 0;
                 for (int64_t w = w_lo; w <= w_hi; ++w)
                     sh += part[((slot_mul * w + slot_base) * TR + r0 + r) * (int64_t)k + c];
                 if (a.fp8)   // codes carry S * scale off the diagonal; S_ii is kept exactly
                     sh = sh / (HT)a.panel_scale[prow / a.panel_rows] + (HT)a.diag[prow] * h;
-                HT hg = 0;
                 for (int b = 0; b < k; ++b) hg += Hs[r * KB + b] * Gs[b * KB + c];
                 g = cg * (hg - sh);
                 tr += (double)h * (double)sh;
@@ -99,7 +97,44 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
             if (!(g == g) || g - g != (HT)0) ++bad;
             if (a.store_mu) Mu[idx] = g;
             if (Go) Go[idx] = g;
-            if (a.softplus) {
+            if (a.method == SYMNMF_ADAM || a.method == SYMNMF_NADAM || a.method == SYMNMF_ADAN) {
+                // family 3, Adam-type rules on x = Theta (softplus) or H (projected)
+                const HT x = a.softplus ? Th[idx] : h;
+                const HT gx = a.softplus ? g * sigmoid_f(x) : g;
+                const HT b1 = (HT)a.beta1, b2 = (HT)a.beta2;
+                const HT m = b1 * M[idx] + ((HT)1 - b1) * gx;
+                M[idx] = m;
+                HT step;
+                if (a.method == SYMNMF_ADAN) {
+                    const HT b3 = (HT)a.beta3;
+                    HT* D = (HT*)a.D;
+                    HT* Gp = (HT*)a.Gp;
+                    const HT diff = a.first ? (HT)0 : gx - Gp[idx];
+                    const HT d = b2 * D[idx] + ((HT)1 - b2) * diff;
+                    const HT u = gx + b2 * diff;
+                    const HT nv = b3 * G[idx] + ((HT)1 - b3) * u * u;
+                    D[idx] = d;
+                    G[idx] = nv;
+                    Gp[idx] = gx;
+                    step = (m / (HT)a.bc1 + b2 * d / (HT)a.bc2) / (dev_sqrt(nv / (HT)a.bc3) + eps);
+                } else {
+                    const HT v = b2 * G[idx] + ((HT)1 - b2) * gx * gx;
+                    G[idx] = v;
+                    HT mh = m / (HT)a.bc1;
+                    if (a.method == SYMNMF_NADAM) mh = b1 * mh + ((HT)1 - b1) * gx / (HT)a.bc1;
+                    step = mh / (dev_sqrt(v / (HT)a.bc2) + eps);
+                }
+                const HT xn = x - eta * step;
+                if (a.softplus) {
+                    Th[idx] = xn;
+                    hn = softplus_f(xn);
+                } else {
+                    hn = xn > (HT)0 ? xn : (HT)0;
+                }
+            } else if (a.method == SYMNMF_MU) {
+                // family 1: dampened multiplicative update, H stays >= 0
+                hn = (HT)0.5 * h * ((HT)1 + sh / (hg + eps));
+            } else if (a.softplus) {
                 HT th = Th[idx];
                 const HT gt = g * sigmoid_f(th);
                 if (a.method == SYMNMF_RMSPROP) {

@@ -51,8 +51,8 @@ def test_struct_sizes_match_header_layout(binding):
     assert ctypes.sizeof(binding.symnmf_sbuild_params) == 64
     assert ctypes.sizeof(binding.symnmf_S) == 8 * 3 + 8 * 6 + 4 * 2 + 8 * 4
     assert ctypes.sizeof(binding.symnmf_stats) == 8 * 7 + 4 * 4
-    assert ctypes.sizeof(binding.symnmf_params) == 8 + 8 * 10 + 8 * 3 + 8 + 8 * 3 + 8 * 4 + 8 + 8
-    assert binding.symnmf_abi_version() == 2
+    assert ctypes.sizeof(binding.symnmf_params) == 8 + 8 * 10 + 8 * 3 + 8 + 8 * 3 + 8 * 4 + 8 + 8 + 8 * 3
+    assert binding.symnmf_abi_version() == 3
 
 
 def test_kmeans_seed_rows_are_bit_identical_to_the_oracle(binding):
@@ -74,6 +74,7 @@ def test_params_default(binding):
     assert p.method == binding.ADAGRAD and p.delta == 10 and p.warmup == 50
     assert p.tau_E == 0.1 and p.tau_g_inf == 1e-4 and p.n_ref == 1e4 and p.tau_stag == 1e-5
     assert p.rho == 500.0
+    assert (p.beta1, p.beta2, p.beta3) == (0.9, 0.999, 0.99)
 
 
 def test_S_bytes(binding):
