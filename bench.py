@@ -496,6 +496,61 @@ def kmeans_cpu_baseline(X_host, K, rows):
                       f"at K={K} ({reps} timed, {dt:.3f} s each), scaled by {n}/{rows}"}
 
 
+def logspace_study(args):
+    """Projected (P) vs softplus (L) convergence counts on the appendix's
+    benchmark matrices, as in the paper's LogSpace table: runs satisfying the
+    three-criterion stop rule within --logspace-budget iterations, out of
+    3 seeds x 2 matrix types per size, k = floor(sqrt(n)) (capped at 64)."""
+    import torch
+    import paper_2607_24518_amd as sym
+    import synth
+    dev = torch.device("cuda:0")
+    ctx = sym.symnmf_create(0)
+    sizes = [int(v) for v in args.logspace_sizes.split(",")]
+    methods = {"rmsprop": dict(method=sym.RMSPROP, c=0.03, eps=1e-8, alpha=0.99, mu=0.5),
+               "adam": dict(method=sym.ADAM, c=ADAM_ETA["adam"]),
+               "adagrad": dict(method=sym.ADAGRAD, c=1.0)}
+    table, runs = {}, []
+    for n in sizes:
+        k = min(math.isqrt(n), 64)
+        for kind in ("corr", "tpdm"):
+            for seed in (7, 42, 99):
+                X = synth.paper_benchmark(seed, n, kind, device=dev).X
+                if kind == "corr":
+                    S = sym.symnmf_build_S(ctx, X, kind=sym.ABS_CORR, dtype=sym.S_FP32)
+                else:
+                    S = sym.symnmf_build_S(ctx, X, kind=sym.TPDM, dtype=sym.S_FP32, q=0.01, lower_tail=0,
+                                           raw_marginals=1)
+                del X
+                H0 = torch.empty(n, k, device=dev)
+                sym.symnmf_init_H(ctx, S, k, seed, H0)
+                base = math.sqrt(S.desc.mean / k)
+                for name, m in methods.items():
+                    for form in (0, 1):
+                        kw = {q: v for q, v in m.items() if q != "c"}
+                        p = sym.symnmf_params_default(eta=m["c"] * base, softplus=form, max_iter=args.logspace_budget,
+                                                      seed=seed, **kw)
+                        st = sym.symnmf_state_create(ctx, S, k, p, H0)
+                        t0 = time.perf_counter()
+                        try:
+                            stats, conv = sym.symnmf_solve_to_tol(ctx, S, st)
+                        except sym.SymnmfError as e:     # e.g. a non-finite gradient: not converged
+                            log(f"logspace n={n} {kind} seed={seed} {name} form={form}: {e}")
+                            stats, conv = sym.symnmf_state_stats(ctx, st), False
+                        wall = time.perf_counter() - t0
+                        key = f"n{n}_{name}_{'L' if form else 'P'}"
+                        table[key] = table.get(key, 0) + int(bool(conv))
+                        rec = {"n": n, "k": k, "kind": kind, "seed": seed, "method": name, "form": "L" if form else "P",
+                               "converged": bool(conv), "t": int(stats.t), "E": stats.E, "kkt": stats.kkt,
+                               "seconds": round(wall, 3)}
+                        runs.append(rec)
+                        log(f"logspace {rec}")
+                        del st
+                del S
+                torch.cuda.empty_cache()
+    return {"converged_of_6": table, "runs": runs}
+
+
 def kmeans_paper_benchmark(args, ctx, Ks):
     """K-means on the appendix's own benchmark matrices (floor(sqrt(n))
     groups plus the common factor, 40000 samples; |corr| and the raw-marginal
@@ -654,7 +709,18 @@ def main():
                     help="overlapping-groups returns, or the appendix's benchmark matrices (--kmeans-kinds)")
     ap.add_argument("--kmeans-kinds", default="corr,tpdm")
     ap.add_argument("--kmeans-seeds", default="7,42,99")
+    ap.add_argument("--logspace", action="store_true", help="projected vs softplus convergence counts instead of the "
+                                                           "step rate")
+    ap.add_argument("--logspace-sizes", default="100,1000,10000")
+    ap.add_argument("--logspace-budget", type=int, default=20000)
     args = ap.parse_args()
+
+    if args.logspace:
+        res = logspace_study(args)
+        print(json.dumps({"metric": "runs certified by the stop rule within the iteration budget, projected vs "
+                                    "softplus", "unit": "runs of 6", "n_gpus": 1, "data": "synthetic",
+                          "budget": args.logspace_budget, **res}), flush=True)
+        return
 
     if args.kmeans:
         res = kmeans_bench(args)
