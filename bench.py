@@ -573,6 +573,13 @@ def kmeans_paper_benchmark(args, ctx, Ks):
                 else:
                     S = sym.symnmf_build_S(ctx, X, kind=sym.TPDM, dtype=sym.DTYPES[dname], q=0.01, lower_tail=0,
                                            raw_marginals=1)
+                spec = None
+                if dname == "fp32":
+                    t0 = time.perf_counter()
+                    spec = sym.symnmf_spectral(ctx, S, max_iter=300, tol=1e-9)
+                    spec["seconds"] = round(time.perf_counter() - t0, 3)
+                    spec["bound"] = (spec["r_eff"] - 1.0) ** 2
+                    log(f"spectral {kind} seed={seed}: {spec}")
                 for K in Ks:
                     labels = torch.zeros(n, dtype=torch.int32, device=dev)
                     for rep in range(args.kmeans_reps):
@@ -583,7 +590,7 @@ def kmeans_paper_benchmark(args, ctx, Ks):
                     sil = sym.symnmf_silhouette(ctx, S, labels, K)
                     rec = {"kind": kind, "seed": seed, "S_storage": dname, "K": K, "seconds": round(wall, 4),
                            "iters": st["iters"], "converged": bool(st["converged"]), "J": st["J"],
-                           "silhouette": round(sil, 4)}
+                           "silhouette": round(sil, 4), "spectral": spec}
                     log(f"kmeans {rec}")
                     runs.append(rec)
                 del S
@@ -594,7 +601,13 @@ def kmeans_paper_benchmark(args, ctx, Ks):
     for r in runs:
         key = f"{r['kind']}_{r['S_storage']}_K{r['K']}"
         means.setdefault(key, []).append(r)
+    def mean_spec(v, key):
+        vals = [r["spectral"][key] for r in v if r.get("spectral")]
+        return round(sum(vals) / len(vals), 4) if vals else None
+
     summary = {k: {"seconds": round(sum(r["seconds"] for r in v) / len(v), 4),
+                   "lambda1": mean_spec(v, "lambda1"), "r_eff": mean_spec(v, "r_eff"),
+                   "collapse": mean_spec(v, "collapse"), "bound": mean_spec(v, "bound"),
                    "iters": round(sum(r["iters"] for r in v) / len(v), 2),
                    "silhouette": round(sum(r["silhouette"] for r in v) / len(v), 4),
                    "converged": all(r["converged"] for r in v), "seeds": len(v)} for k, v in means.items()}

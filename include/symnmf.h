@@ -505,6 +505,23 @@ symnmf_status symnmf_kmeans_centroids(symnmf_ctx* ctx, const symnmf_S* S, const 
 symnmf_status symnmf_kmeans(symnmf_ctx* ctx, const symnmf_S* S, int64_t K, uint64_t seed, const int64_t* init_rows,
                             double tol, int64_t max_iter, int32_t* labels, void* C, symnmf_kmeans_stats* stats);
 
+/* Spectral diagnostic of the collapse of angular clustering (section
+ * "Clustering", eq. angular_collapse; table tab:spectral): lambda_1 of S by
+ * power iteration from the normalised all-ones vector (S >= 0, so its Perron
+ * vector is non-negative) until the Rayleigh quotient changes by at most
+ * tol relative or max_iter passes; tr(S); r_eff = tr(S) / lambda_1;
+ * collapse = (||S||_F^2 - lambda_1^2) / ||S||_F^2, the norm-weighted mean of
+ * sin^2 of the angle between the rows and u_1, bounded by (r_eff - 1)^2 for
+ * PSD S; collapse_rows = (||S||_F^2 - ||S u||^2) / ||S||_F^2, the same mean
+ * evaluated from the rows with the computed u (equal to collapse when u is
+ * exact).  ||S||_F^2 is S->fro2_stored.  Every output pointer (host) may be
+ * NULL; u1 (device float32, n entries, may be NULL) receives the unit
+ * vector.  One S pass per iteration.  ENUMERIC if S u vanishes.
+ * Synchronises. */
+symnmf_status symnmf_spectral(symnmf_ctx* ctx, const symnmf_S* S, int64_t max_iter, double tol, double* lambda1,
+                              double* trace, double* r_eff, double* collapse, double* collapse_rows, int64_t* iters,
+                              float* u1);
+
 /* Mean silhouette of the partition labels (device int32, n entries in
  * [0, K)) under the cosine distance d(i, j) = 1 - cos(s^_i, s^_j)
  * (Rousseeuw 1987): a(i) = (n_a - s^_i . m_a) / (n_a - 1) and

@@ -130,6 +130,9 @@ SIGNATURES = {
     "symnmf_kmeans_centroids": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, c_vp, c_vp]),
     "symnmf_kmeans": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_i64, c_u64, c_vp, c_dbl, c_i64, c_vp, c_vp,
                               ctypes.POINTER(symnmf_kmeans_stats)]),
+    "symnmf_spectral": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_i64, c_dbl, ctypes.POINTER(c_dbl),
+                                ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl),
+                                ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64), c_vp]),
     "symnmf_silhouette": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, ctypes.POINTER(c_dbl)]),
 }
 
@@ -524,3 +527,15 @@ def symnmf_silhouette(ctx, S: Matrix, labels, K: int):
     out = c_dbl()
     _check(ctx, lib().symnmf_silhouette(ctx, ctypes.byref(S.desc), _ptr(labels), K, ctypes.byref(out)))
     return out.value
+
+
+def symnmf_spectral(ctx, S: Matrix, max_iter: int = 500, tol: float = 1e-10, u1=None):
+    """Returns a dict: lambda1, trace, r_eff, collapse, collapse_rows, iters."""
+    vals = [c_dbl() for _ in range(5)]
+    it = c_i64()
+    _check(ctx, lib().symnmf_spectral(ctx, ctypes.byref(S.desc), max_iter, tol, *[ctypes.byref(v) for v in vals],
+                                      ctypes.byref(it), _ptr(u1) if u1 is not None else None))
+    keys = ("lambda1", "trace", "r_eff", "collapse", "collapse_rows")
+    out = {k: v.value for k, v in zip(keys, vals)}
+    out["iters"] = it.value
+    return out

@@ -355,6 +355,61 @@ __global__ __launch_bounds__(KT) void sum_parts_kernel(const double* __restrict_
     }
 }
 
+// --------------------------------------------------------------------------
+// Spectral diagnostic: trace and power iteration on the first column of a
+// 16-wide factor slice.
+// --------------------------------------------------------------------------
+template <int DT>   // 0 FP32, 1 BF16, 2 FP8 tiled storage, 3 FP64 row-major
+__global__ __launch_bounds__(KT) void diag_sum_kernel(const void* __restrict__ S, int64_t n, int64_t ld,
+                                                      int64_t n_chunks, const float* __restrict__ diag,
+                                                      double* __restrict__ part) {
+    const int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x;
+    double v = 0.0;
+    if (i < n) {
+        if (DT == 3) v = ((const double*)S)[i * ld + i];
+        else if (DT == 2) v = (double)diag[i];
+        else if (DT == 1) v = (double)bf16_bits_to_f32(((const uint16_t*)S)[tiled_offset(i, i, n_chunks, 8)]);
+        else v = (double)((const float*)S)[tiled_offset(i, i, n_chunks, 4)];
+    }
+    block_sum2(v, 0, part + blockIdx.x, nullptr);
+}
+
+// partials of v . y and y . y over rows i < n (column 0 of 16-wide slices)
+template <typename T>
+__global__ __launch_bounds__(KT) void power_dots_kernel(const T* __restrict__ X, const T* __restrict__ Y, int64_t n,
+                                                        int w, double* __restrict__ pvy, double* __restrict__ pyy) {
+    const int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x;
+    double vy = 0.0, yy = 0.0;
+    if (i < n) {
+        const double v = (double)X[i * w], y = (double)Y[i * w];
+        vy = v * y;
+        yy = y * y;
+    }
+    block_sum2(vy, 0, pvy + blockIdx.x, nullptr);
+    __syncthreads();
+    block_sum2(yy, 0, pyy + blockIdx.x, nullptr);
+}
+
+template <typename T>
+__global__ __launch_bounds__(KT) void power_scale_kernel(const T* __restrict__ Y, int64_t n, int w, double scale,
+                                                         T* __restrict__ X) {
+    const int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x;
+    if (i < n) X[i * w] = (T)((double)Y[i * w] * scale);
+}
+
+template <typename T>
+__global__ __launch_bounds__(KT) void fill_col0_kernel(T* __restrict__ X, int64_t n, int w, double value) {
+    const int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x;
+    if (i < n) X[i * w] = (T)value;
+}
+
+template <typename T>
+__global__ __launch_bounds__(KT) void copy_col0_kernel(const T* __restrict__ X, int64_t n, int w,
+                                                       float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x;
+    if (i < n) out[i] = (float)X[i * w];
+}
+
 inline unsigned blocks_for(int64_t m) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((m + KT - 1) / KT, 65536)); }
 
 // --------------------------------------------------------------------------
@@ -668,6 +723,86 @@ symnmf_status kmeans_run(symnmf_ctx* ctx, KCall& kc, Scratch& sc, const std::vec
     return SYMNMF_OK;
 }
 
+template <typename T>
+symnmf_status spectral_run(symnmf_ctx* ctx, KCall& kc, Scratch& sc, int64_t max_iter, double tol, double* lambda1,
+                           double* trace, double* r_eff, double* collapse, double* collapse_rows, int64_t* iters,
+                           float* u1) {
+    const symnmf_S* S = kc.S;
+    void* X = sc.get(kc.factor_bytes());
+    void* Y = sc.get(kc.factor_bytes());
+    double* p1 = (double*)sc.get(kc.row_blocks() * 8);
+    double* p2 = (double*)sc.get(kc.row_blocks() * 8);
+    double* out = (double*)sc.get(4 * 8);
+    if (sc.err != hipSuccess) return fail(ctx, SYMNMF_ENOMEM, "spectral: %s", hipGetErrorString(sc.err));
+    const unsigned nb = (unsigned)kc.row_blocks();
+    // trace
+    switch (S->dtype) {
+        case SYMNMF_S_FP32:
+            hipLaunchKernelGGL(diag_sum_kernel<0>, dim3(nb), dim3(KT), 0, kc.sm, S->data, kc.n, S->ld, kc.chunks,
+                               S->diag, p1);
+            break;
+        case SYMNMF_S_BF16:
+            hipLaunchKernelGGL(diag_sum_kernel<1>, dim3(nb), dim3(KT), 0, kc.sm, S->data, kc.n, S->ld, kc.chunks,
+                               S->diag, p1);
+            break;
+        case SYMNMF_S_FP8:
+            hipLaunchKernelGGL(diag_sum_kernel<2>, dim3(nb), dim3(KT), 0, kc.sm, S->data, kc.n, S->ld, kc.chunks,
+                               S->diag, p1);
+            break;
+        default:
+            hipLaunchKernelGGL(diag_sum_kernel<3>, dim3(nb), dim3(KT), 0, kc.sm, S->data, kc.n, S->ld, kc.chunks,
+                               S->diag, p1);
+    }
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(KT), 0, kc.sm, p1, nullptr, kc.row_blocks(), out);
+    HIP_OK(ctx, hipGetLastError());
+    double tr[2];
+    HIP_OK(ctx, hipMemcpyAsync(tr, out, 16, hipMemcpyDeviceToHost, kc.sm));
+    HIP_OK(ctx, hipStreamSynchronize(kc.sm));
+    // power iteration from the normalised all-ones vector (S >= 0: its
+    // Perron vector is non-negative, so the start is never orthogonal to it)
+    hipLaunchKernelGGL(fill_col0_kernel<T>, dim3(nb), dim3(KT), 0, kc.sm, (T*)X, kc.n, (int)kc.w,
+                       1.0 / std::sqrt((double)kc.n));
+    HIP_OK(ctx, hipGetLastError());
+    double lam = 0.0, yy = 0.0;
+    int64_t it = 0;
+    for (; it < max_iter;) {
+        HIP_OK(ctx, s_times(kc, X, Y));
+        hipLaunchKernelGGL(power_dots_kernel<T>, dim3(nb), dim3(KT), 0, kc.sm, (const T*)X, (const T*)Y, kc.n,
+                           (int)kc.w, p1, p2);
+        hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(KT), 0, kc.sm, p1, nullptr, kc.row_blocks(), out);
+        hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(KT), 0, kc.sm, p2, nullptr, kc.row_blocks(), out + 2);
+        HIP_OK(ctx, hipGetLastError());
+        double d[4];
+        HIP_OK(ctx, hipMemcpyAsync(d, out, 32, hipMemcpyDeviceToHost, kc.sm));
+        HIP_OK(ctx, hipStreamSynchronize(kc.sm));
+        ++it;
+        const double lam_new = d[0];   // Rayleigh quotient v^T S v with ||v|| = 1
+        yy = d[2];
+        if (!std::isfinite(lam_new) || !(yy > 0.0))
+            return fail(ctx, SYMNMF_ENUMERIC, "spectral: power iteration broke down (S v = 0 or non-finite)");
+        hipLaunchKernelGGL(power_scale_kernel<T>, dim3(nb), dim3(KT), 0, kc.sm, (const T*)Y, kc.n, (int)kc.w,
+                           1.0 / std::sqrt(yy), (T*)X);
+        HIP_OK(ctx, hipGetLastError());
+        const bool done = it > 1 && std::fabs(lam_new - lam) <= tol * std::fabs(lam_new);
+        lam = lam_new;
+        if (done) break;
+    }
+    if (u1) {
+        hipLaunchKernelGGL(copy_col0_kernel<T>, dim3(nb), dim3(KT), 0, kc.sm, (const T*)X, kc.n, (int)kc.w, u1);
+        HIP_OK(ctx, hipGetLastError());
+    }
+    HIP_OK(ctx, hipStreamSynchronize(kc.sm));
+    const double fro2 = S->fro2_stored;
+    if (lambda1) *lambda1 = lam;
+    if (trace) *trace = tr[0];
+    if (r_eff) *r_eff = tr[0] / lam;
+    if (collapse) *collapse = (fro2 - lam * lam) / fro2;
+    // from the rows: sum_i ||s_i||^2 sin^2(theta_i) = ||S||^2 - sum_i (u . s_i)^2 = ||S||^2 - ||S u||^2
+    if (collapse_rows) *collapse_rows = (fro2 - yy) / fro2;
+    if (iters) *iters = it;
+    return SYMNMF_OK;
+}
+
 }  // namespace
 }  // namespace symnmf
 
@@ -774,6 +909,21 @@ symnmf_status symnmf_kmeans(symnmf_ctx* ctx, const symnmf_S* S, int64_t K, uint6
     }
     if (kc.f64) return kmeans_run<double>(ctx, kc, sc, rows, tol, max_iter, labels, C, stats, t0);
     return kmeans_run<float>(ctx, kc, sc, rows, tol, max_iter, labels, C, stats, t0);
+}
+
+symnmf_status symnmf_spectral(symnmf_ctx* ctx, const symnmf_S* S, int64_t max_iter, double tol, double* lambda1,
+                              double* trace, double* r_eff, double* collapse, double* collapse_rows, int64_t* iters,
+                              float* u1) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (max_iter < 1 || !(tol >= 0.0)) return fail(ctx, SYMNMF_EINVAL, "spectral: need max_iter >= 1, tol >= 0");
+    Scratch sc(ctx->stream);
+    KCall kc;
+    symnmf_status r = kcall_setup(ctx, S, 1, sc, kc);
+    if (r != SYMNMF_OK) return r;
+    if (kc.f64)
+        return spectral_run<double>(ctx, kc, sc, max_iter, tol, lambda1, trace, r_eff, collapse, collapse_rows, iters,
+                                    u1);
+    return spectral_run<float>(ctx, kc, sc, max_iter, tol, lambda1, trace, r_eff, collapse, collapse_rows, iters, u1);
 }
 
 symnmf_status symnmf_silhouette(symnmf_ctx* ctx, const symnmf_S* S, const int32_t* labels, int64_t K, double* sil) {

@@ -256,3 +256,64 @@ def test_edge_cases(stores):
     with pytest.raises(sym.SymnmfError) as e:
         sym.symnmf_kmeans(c, pan, 4, labels)
     assert e.value.code == sym.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_spectral_diagnostic_matches_oracle(stores, dtype):
+    """lambda_1 by power iteration, tr(S), r_eff and the collapse ratio of
+    eq. angular_collapse against LAPACK's eigen-decomposition of the stored S."""
+    S, M = stores[dtype]
+    u = torch.zeros(600, dtype=torch.float32, device=dev())
+    got = sym.symnmf_spectral(ctx(), S, max_iter=2000, tol=1e-13 if dtype == "fp64" else 1e-9, u1=u)
+    lhs, spectral, bound, r_eff, lam1 = km.angular_collapse(M)
+    rel = 1e-10 if dtype == "fp64" else 2e-6
+    assert got["trace"] == pytest.approx(np.trace(M), rel=1e-14)
+    if dtype == "fp8":
+        # per-row-panel scales leave the stored S symmetric only to one
+        # quantisation step: the power iteration finds the Perron root of the
+        # stored (non-symmetric) matrix, within that step of the symmetric one
+        perron = float(np.max(np.linalg.eigvals(M).real))
+        assert got["lambda1"] == pytest.approx(perron, rel=rel)
+        assert got["lambda1"] == pytest.approx(lam1, rel=1e-3)
+        return
+    assert got["lambda1"] == pytest.approx(lam1, rel=rel)
+    assert got["r_eff"] == pytest.approx(r_eff, rel=rel)
+    assert got["collapse"] == pytest.approx(spectral, rel=1e-5)
+    assert got["collapse_rows"] == pytest.approx(lhs, rel=1e-4)
+    w, V = np.linalg.eigh(M)
+    v = V[:, -1] * np.sign(V[:, -1].sum())
+    assert np.max(np.abs(from_dev(u) - v)) < 1e-4
+
+
+def test_spectral_diagnostic_reproduces_the_paper_table_at_n_10000(golden_dir):
+    """lambda_1 and r_eff of the appendix's benchmark matrices at n = 10^4
+    (power iteration on the FP32 S built on the device), means over seeds 7,
+    42, 99, against the values the paper prints.  Instances are redrawn here
+    (a different random stream than the paper's), so the check is
+    statistical: 5 % on lambda_1 (the three seeds spread by 7 % for the TPDM)
+    and 0.1 on r_eff."""
+    ref = {}
+    for line in open(f"{golden_dir}/spectral_table_large.txt"):
+        if line.startswith("#") or not line.strip():
+            continue
+        kind, n, lam, reff = line.split()
+        ref[(kind, int(n))] = (float(lam), float(reff))
+    c = ctx()
+    n = 10000
+    for kind in ("tpdm", "corr"):
+        lams, reffs = [], []
+        for seed in (7, 42, 99):
+            X = synth.paper_benchmark(seed, n, kind, device=dev()).X
+            if kind == "corr":
+                S = sym.symnmf_build_S(c, X, kind=sym.ABS_CORR, dtype=sym.S_FP32)
+            else:
+                S = sym.symnmf_build_S(c, X, kind=sym.TPDM, dtype=sym.S_FP32, q=0.01, lower_tail=0, raw_marginals=1)
+            got = sym.symnmf_spectral(c, S, max_iter=300, tol=1e-9)
+            assert got["trace"] == pytest.approx(n, rel=1e-12)   # unit diagonal
+            assert 0.0 < got["collapse"] <= (got["r_eff"] - 1.0) ** 2 or kind == "corr"
+            lams.append(got["lambda1"])
+            reffs.append(got["r_eff"])
+            del S, X
+        lam_p, reff_p = ref[(kind, n)]
+        assert np.mean(lams) == pytest.approx(lam_p, rel=0.05), kind
+        assert abs(np.mean(reffs) - reff_p) < 0.1, kind
