@@ -173,7 +173,7 @@ ADAM_ETA = {"adam": 0.1, "nadam": 0.03, "adan": 0.01}
 
 
 def variant_params(variant, eta_base, seed=0):
-    """Solver parameters of a variant name "<storage>[-<method>][-softplus]";
+    """Solver parameters of a variant name "<storage>[-<method>][-softplus][-principal]";
     "admm<rho>" selects ADMM with that penalty (plain "admm": rho = 500)."""
     import paper_2607_24518_amd as sym
 
@@ -197,6 +197,8 @@ def variant_params(variant, eta_base, seed=0):
         kw.update(eps=2.0 ** -23)
     if method in ("rowsvrg", "blocksvrg"):
         kw.update(block_rows=1024, snapshot_s=10, delta=10, phi0=0.75, row_frac=0.5)
+    if "principal" in parts:            # Block-SVRG with J = I
+        kw.update(independent_blocks=0)
     return sym.symnmf_params_default(**kw)
 
 
