@@ -528,11 +528,23 @@ __global__ __launch_bounds__(256) void split_planes_kernel(const float* __restri
     }
 }
 
+// Operands are staged through LDS: per 32-sample slab the work-group's 128
+// rows and 128 columns in both planes (32 KB) are loaded with 16-byte vectors
+// into registers one slab ahead, written to one of two LDS buffers, and every
+// wave reads its MFMA fragments from there, so each operand byte is fetched
+// from L2 once per work-group instead of once per wave.  The MFMA sequence of
+// a slab is unchanged, so the result does not depend on the staging.
+constexpr int SPLIT_VECS = 8;   // 16-byte vectors per thread and slab (2 sides x 2 planes x 128 rows x 4)
+
 template <int MODE, int DT>
 __global__ __launch_bounds__(256, 2) void syrk_split_kernel(const uint16_t* __restrict__ P, int64_t Kp, int64_t ldz,
                                                             BuildOut o, int64_t n_ti, int64_t n_tj,
                                                             double* __restrict__ wg_sums,
                                                             uint32_t* __restrict__ panel_max) {
+    // [buffer][side A/B][plane][row][16-byte part]: 2 x 2 x 2 x 128 x 4 vectors;
+    // vector q of thread t sits at f = t + 256 q of its buffer: side q / 4,
+    // plane (q / 2) % 2, row t / 4 + 64 (q % 2), part t % 4
+    __shared__ u32x4 lds[2 * 2048];
     __shared__ uint32_t rowmax[128];
     __shared__ double red[3][4];
     int64_t ti, tj;
@@ -541,9 +553,11 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(const uint16_t* __re
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1, lr = lane & 15, lg = lane >> 4;
     const int64_t plane = ldz * Kp;
-    // row r of A / B fragment a: column (instrument) index, samples from 8 lg
-    const uint16_t* pa = P + (o.row0 + i0 + 64 * wr + lr) * Kp + 8 * lg;
-    const uint16_t* pb = P + (j0 + 64 * wc + lr) * Kp + 8 * lg;
+    const uint16_t* tp = P + (int64_t)(t >> 2) * Kp + 8 * (t & 3);
+    // work-group-uniform offsets of the 8 vectors (elements)
+    auto voff = [&](int q) -> int64_t {
+        return ((q >> 2) ? j0 : o.row0 + i0) * Kp + (q & 1) * 64 * Kp + ((q >> 1) & 1) * plane;
+    };
     // hh products accumulate in acc; the cross terms of one 32-sample block
     // are formed in two fresh MFMAs (x from the row's lower planes, y from the
     // column's) and added as x + y, so that element (j, i) repeats the exact
@@ -557,24 +571,38 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(const uint16_t* __re
             crs[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
     const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+    u32x4 reg[SPLIT_VECS];
+#pragma unroll
+    for (int q = 0; q < SPLIT_VECS; ++q) reg[q] = *(const u32x4*)(tp + voff(q));
     for (int64_t k0 = 0; k0 < Kp; k0 += 32) {
-        bf16x8 av[2][4], bv[2][4];
+        u32x4* lb = lds + ((k0 >> 5) & 1) * 2048;
+#pragma unroll
+        for (int q = 0; q < SPLIT_VECS; ++q) lb[t + 256 * q] = reg[q];
+        __syncthreads();
+        if (k0 + 32 < Kp) {
+#pragma unroll
+            for (int q = 0; q < SPLIT_VECS; ++q) reg[q] = *(const u32x4*)(tp + voff(q) + k0 + 32);
+        }
+        // fragment of row / column block a of plane p, side sd:
+        // lb[((sd * 2 + p) * 128 + 64 w + 16 a + lr) * 4 + lg]
+        bf16x8 bv[2][4];
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                av[p][a] = *(const bf16x8*)(pa + p * plane + (int64_t)16 * a * Kp + k0);
-                bv[p][a] = *(const bf16x8*)(pb + p * plane + (int64_t)16 * a * Kp + k0);
-            }
+            for (int b = 0; b < 4; ++b)
+                bv[p][b] = __builtin_bit_cast(bf16x8, lb[((2 + p) * 128 + 64 * wc + 16 * b + lr) * 4 + lg]);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a) {
+            const bf16x8 a0 = __builtin_bit_cast(bf16x8, lb[(64 * wr + 16 * a + lr) * 4 + lg]);
+            const bf16x8 a1 = __builtin_bit_cast(bf16x8, lb[(128 + 64 * wr + 16 * a + lr) * 4 + lg]);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const floatx4 x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1][a], bv[0][b], zero, 0, 0, 0);
-                const floatx4 y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][a], bv[1][b], zero, 0, 0, 0);
+                const floatx4 x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv[0][b], zero, 0, 0, 0);
+                const floatx4 y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv[1][b], zero, 0, 0, 0);
                 crs[a][b] += x + y;
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0][a], bv[0][b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv[0][b], acc[a][b], 0, 0, 0);
             }
+        }
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
