@@ -42,9 +42,9 @@ __device__ inline double block_sum(double v, double* sh) {
 constexpr int UT = 256;   // threads of the update work-group (one row slice of SR rows)
 
 template <typename HT, int KB>
-__global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
-    __shared__ HT Hs[SR * KB];
-    __shared__ HT Hns[SR * KB];
+__global__ __launch_bounds__(UT, sizeof(HT) == 4 ? 7 : 1) void update_kernel(UpdateArgs a, PlanView p) {
+    __shared__ __align__(32) HT Hs[SR * KB];
+    __shared__ __align__(32) HT Hns[SR * KB];
     __shared__ HT Gs[KB * KB];
     __shared__ double red[UT / 64];
     const int t = threadIdx.x;
@@ -71,9 +71,38 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
     HT* Go = (HT*)a.Gout;
     HT* Hn = (HT*)a.Hn;
     const HT eta = (HT)a.eta, eps = (HT)a.eps, alpha = (HT)a.alpha, mom = (HT)a.mu, cg = (HT)a.cgrad;
+    // H (H^T H) of this thread's elements.  With k == KB the elements
+    // f = t + UT j of a thread share the column c = t % KB (UT is a multiple
+    // of KB), so every Gram entry is read from LDS once for all of them and
+    // the H rows in 4-wide vectors; the products are summed in the same order
+    // as the per-element loop below.
+    constexpr int NJ = SR * KB / UT;
+    typedef HT hvec4 __attribute__((ext_vector_type(4)));
+    const bool full_k = k == KB && act >= 0;
+    HT hgv[NJ];
+    if (full_k) {
+        const int c = t % KB, rb = t / KB;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) hgv[j] = 0;
+        for (int b = 0; b < KB; b += 4) {
+            const HT g0 = Gs[b * KB + c], g1 = Gs[(b + 1) * KB + c], g2 = Gs[(b + 2) * KB + c],
+                     g3 = Gs[(b + 3) * KB + c];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const hvec4 hv = *(const hvec4*)&Hs[(rb + j * (UT / KB)) * KB + b];
+                HT v = hgv[j];
+                v += hv[0] * g0;
+                v += hv[1] * g1;
+                v += hv[2] * g2;
+                v += hv[3] * g3;
+                hgv[j] = v;
+            }
+        }
+    }
     double tr = 0.0, kkt = 0.0;
     int bad = 0;
-    for (int f = t; f < SR * k; f += UT) {
+    int jj = 0;
+    for (int f = t; f < SR * k; f += UT, ++jj) {
         const int r = f / k, c = f - r * k;             // slice row, column
         const int64_t prow = tile * TR + r0 + r;
         HT hn = 0;
@@ -86,7 +115,11 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
                     sh += part[((slot_mul * w + slot_base) * TR + r0 + r) * (int64_t)k + c];
                 if (a.fp8)   // codes carry S * scale off the diagonal; S_ii is kept exactly
                     sh = sh / (HT)a.panel_scale[prow / a.panel_rows] + (HT)a.diag[prow] * h;
-                for (int b = 0; b < k; ++b) hg += Hs[r * KB + b] * Gs[b * KB + c];
+                if (full_k) {
+                    hg = hgv[jj < NJ ? jj : 0];
+                } else {
+                    for (int b = 0; b < k; ++b) hg += Hs[r * KB + b] * Gs[b * KB + c];
+                }
                 g = cg * (hg - sh);
                 tr += (double)h * (double)sh;
             } else {
@@ -169,11 +202,34 @@ __global__ __launch_bounds__(UT) void update_kernel(UpdateArgs a, PlanView p) {
     }
     __syncthreads();
     double* tg = a.tile_gram + slice * (int64_t)k * k;
-    for (int e = t; e < k * k; e += UT) {
-        const int ia = e / k, ib = e - ia * k;
-        double s = 0.0;
-        for (int r = 0; r < SR; ++r) s += (double)Hns[r * KB + ia] * (double)Hns[r * KB + ib];
-        tg[e] = s;
+    if (KB >= 32 && k == KB) {
+        // each thread: entries (ia0 + q, ib), q < NQ (a multiple of 4, ia0 too),
+        // consecutive ia read as aligned 4-wide vectors; the same FP64 sums
+        // over the slice rows
+        constexpr int NQ = KB >= 32 ? (KB * KB) / UT : 4;
+        static_assert(NQ % 4 == 0, "4-wide Gram reads need NQ % 4 == 0");
+        const int ib = t % KB, ia0 = (t / KB) * NQ;
+        double sq[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sq[q] = 0.0;
+        for (int r = 0; r < SR; ++r) {
+            const double hb = (double)Hns[r * KB + ib];
+#pragma unroll
+            for (int q = 0; q < NQ; q += 4) {
+                const hvec4 hv = *(const hvec4*)&Hns[r * KB + ia0 + q];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sq[q + e] += (double)hv[e] * hb;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tg[(ia0 + q) * k + ib] = sq[q];
+    } else {
+        for (int e = t; e < k * k; e += UT) {
+            const int ia = e / k, ib = e - ia * k;
+            double s = 0.0;
+            for (int r = 0; r < SR; ++r) s += (double)Hns[r * KB + ia] * (double)Hns[r * KB + ib];
+            tg[e] = s;
+        }
     }
     const double str = block_sum(tr, red);
     const double skk = block_sum(kkt, red);
