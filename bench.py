@@ -487,7 +487,7 @@ def kmeans_cpu_baseline(X_host, K, rows):
     C = rng.random((K, n))
     C /= np.linalg.norm(C, axis=1, keepdims=True)
     t0 = time.time()
-    reps = 3
+    reps = 8
     for _ in range(reps):
         labels, _, _ = km.assign(Shat, C)
         C = km.centroids(Shat, labels, K, C)
@@ -681,8 +681,8 @@ def main():
     ap.add_argument("--rows", type=int, default=0, help="row-panel share of S (0: all n rows)")
     ap.add_argument("--no-read-probe", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-rows", type=int, default=2048)
-    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--cpu-rows", type=int, default=8192)
+    ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run the library's plain copy kernel over this many GiB (counter calibration)")

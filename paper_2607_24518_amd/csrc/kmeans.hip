@@ -273,7 +273,7 @@ __global__ __launch_bounds__(KT) void assign_kernel(const T* __restrict__ P, con
                                                     int64_t n, int64_t rows_pad, int w, int64_t K,
                                                     int32_t* __restrict__ labels, T* __restrict__ best,
                                                     int32_t* __restrict__ counts, double* __restrict__ jpart,
-                                                    int64_t* __restrict__ chpart) {
+                                                    int64_t* __restrict__ chpart, int track) {
     const int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x;
     double jl = 0.0;
     int64_t ch = 0;
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(KT) void assign_kernel(const T* __restrict__ P, con
         }
         const double cv = (double)bv / norms[i];
         jl = 1.0 - cv;
-        ch = labels[i] != bk ? 1 : 0;
+        ch = (track && labels[i] != bk) ? 1 : 0;   // labels hold the previous assignment only when tracked
         labels[i] = bk;
         if (best) best[i] = (T)cv;
         atomicAdd(&counts[bk], 1);
@@ -610,13 +610,13 @@ hipError_t centroid_step(const KCall& kc, const int32_t* labels, void* W, void* 
 // labels = argmax_k (S C)_ik; kc.counts = the new member counts; scal[0] = J,
 // scal[1] = labels changed.
 template <typename T>
-hipError_t assign_step(const KCall& kc, const void* C, void* Pbuf, int32_t* labels, void* best) {
+hipError_t assign_step(const KCall& kc, const void* C, void* Pbuf, int32_t* labels, void* best, int track = 1) {
     hipError_t e = s_times(kc, C, Pbuf);
     if (e == hipSuccess) e = hipMemsetAsync(kc.counts, 0, kc.ncol * 4, kc.sm);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(assign_kernel<T>, dim3((unsigned)kc.row_blocks()), dim3(KT), 0, kc.sm, (const T*)Pbuf,
                        kc.norms, kc.n, kc.rows_pad, (int)kc.w, kc.K, labels, (T*)best, kc.counts, kc.jpart,
-                       kc.chpart);
+                       kc.chpart, track);
     hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(KT), 0, kc.sm, kc.jpart, kc.chpart, kc.row_blocks(), kc.scal);
     return hipGetLastError();
 }
@@ -844,10 +844,10 @@ symnmf_status symnmf_kmeans_assign(symnmf_ctx* ctx, const symnmf_S* S, const voi
     if ((r = compute_norms(ctx, kc, sc)) != SYMNMF_OK) return r;
     if (kc.f64) {
         HIP_OK(ctx, launch_pack<double>(kc, C, Cs));
-        HIP_OK(ctx, assign_step<double>(kc, Cs, Pb, labels, best));
+        HIP_OK(ctx, assign_step<double>(kc, Cs, Pb, labels, best, 0));
     } else {
         HIP_OK(ctx, launch_pack<float>(kc, C, Cs));
-        HIP_OK(ctx, assign_step<float>(kc, Cs, Pb, labels, best));
+        HIP_OK(ctx, assign_step<float>(kc, Cs, Pb, labels, best, 0));
     }
     double sv[2];
     if ((r = read_scal(ctx, kc, sv)) != SYMNMF_OK) return r;
