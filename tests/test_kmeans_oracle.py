@@ -170,3 +170,44 @@ def test_angular_collapse_identity_and_bound():
     u = np.abs(np.random.default_rng(0).standard_normal(50)) + 0.1
     lhs1, spec1, bound1, r1, _ = km.angular_collapse(np.outer(u, u))
     assert abs(lhs1) < 1e-12 and abs(spec1) < 1e-12 and r1 == pytest.approx(1.0, rel=1e-12)
+
+
+def test_kmeanspp_first_draw_and_second_draw_distribution():
+    # the first seed is floor(u_0 n); the second is drawn with probability
+    # proportional to 1 - cos to the first (k-means++ on unit vectors)
+    X, _ = _clustered(3, 4, 3, 9, 0.3)
+    S = X @ X.T
+    Shat, _ = km.unit_rows(S)
+    n = S.shape[0]
+    counts = np.zeros(n)
+    first_row = None
+    firsts = []
+    for seed in range(3000):
+        r = km.kmeanspp_rows(S, 2, seed)
+        firsts.append(r[0])
+        if r[0] == 0:
+            counts[r[1]] += 1
+    firsts = np.bincount(firsts, minlength=n)
+    assert abs(firsts.mean() - 3000 / n) < 1e-9 and firsts.min() > 0.5 * 3000 / n
+    d = np.maximum(1.0 - Shat @ Shat[0], 0.0)
+    expect = d / d.sum() * counts.sum()
+    assert counts[0] == 0
+    chi2 = float(((counts - expect)[expect > 0] ** 2 / expect[expect > 0]).sum())
+    assert chi2 < 40.0           # 10 degrees of freedom
+
+
+def test_kmeanspp_seeds_every_planted_group():
+    X, truth = _clustered(5, 30, 6, 24, 0.3)
+    S = X @ X.T
+    hits, forgy = 0, 0
+    for seed in range(20):
+        rows = km.kmeanspp_rows(S, 6, seed)
+        assert len(set(rows.tolist())) == 6
+        hits += len(set(truth[rows].tolist())) == 6
+        forgy += len(set(truth[km.seed_rows(seed, S.shape[0], 6)].tolist())) == 6
+    # uniform draws cover all six groups with probability 6!/6^6 = 1.5 %;
+    # distance-weighted draws favour rows far from the seeds so far
+    assert hits >= 14 and forgy <= 3
+    # duplicate rows only: the zero-distance fallback takes the lowest unchosen rows
+    Sd = np.ones((5, 5))
+    assert sorted(km.kmeanspp_rows(Sd, 3, 1).tolist()) == sorted(set(km.kmeanspp_rows(Sd, 3, 1).tolist()))
