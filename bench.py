@@ -586,11 +586,15 @@ def kmeans_paper_benchmark(args, ctx, Ks):
                     labels = torch.zeros(n, dtype=torch.int32, device=dev)
                     for rep in range(args.kmeans_reps):
                         t0 = time.perf_counter()
-                        st = sym.symnmf_kmeans(ctx, S, K, labels, seed=seed, tol=1e-4,
+                        rows = (sym.symnmf_kmeans_seed_pp(ctx, S, K, seed) if args.kmeans_seeding == "kpp"
+                                else None)
+                        seed_s = time.perf_counter() - t0
+                        st = sym.symnmf_kmeans(ctx, S, K, labels, seed=seed, init_rows=rows, tol=1e-4,
                                                max_iter=args.kmeans_max_iter, allow_notconv=True)
                         wall = time.perf_counter() - t0
                     sil = sym.symnmf_silhouette(ctx, S, labels, K)
                     rec = {"kind": kind, "seed": seed, "S_storage": dname, "K": K, "seconds": round(wall, 4),
+                           "seeding": args.kmeans_seeding, "seeding_s": round(seed_s, 4),
                            "iters": st["iters"], "converged": bool(st["converged"]), "J": st["J"],
                            "silhouette": round(sil, 4), "spectral": spec}
                     log(f"kmeans {rec}")
@@ -608,6 +612,7 @@ def kmeans_paper_benchmark(args, ctx, Ks):
         return round(sum(vals) / len(vals), 4) if vals else None
 
     summary = {k: {"seconds": round(sum(r["seconds"] for r in v) / len(v), 4),
+                   "seeding_s": round(sum(r["seeding_s"] for r in v) / len(v), 4),
                    "lambda1": mean_spec(v, "lambda1"), "r_eff": mean_spec(v, "r_eff"),
                    "collapse": mean_spec(v, "collapse"), "bound": mean_spec(v, "bound"),
                    "iters": round(sum(r["iters"] for r in v) / len(v), 2),
@@ -642,7 +647,10 @@ def kmeans_bench(args):
             slices = (K + w - 1) // w
             for rep in range(args.kmeans_reps):
                 t0 = time.perf_counter()
-                st = sym.symnmf_kmeans(ctx, S, K, labels, seed=args.kmeans_seed, tol=1e-4,
+                rows = (sym.symnmf_kmeans_seed_pp(ctx, S, K, args.kmeans_seed) if args.kmeans_seeding == "kpp"
+                        else None)
+                seed_s = time.perf_counter() - t0
+                st = sym.symnmf_kmeans(ctx, S, K, labels, seed=args.kmeans_seed, init_rows=rows, tol=1e-4,
                                        max_iter=args.kmeans_max_iter, allow_notconv=True)
                 wall = time.perf_counter() - t0
             t0 = time.perf_counter()
@@ -650,6 +658,7 @@ def kmeans_bench(args):
             sil_s = time.perf_counter() - t0
             passes = 2 * slices * (st["iters"] + 1)            # stream passes of the Lloyd iterations
             rec = {"S_storage": dname, "K": K, "slice_width": w, "slices": slices, "seconds": round(wall, 4),
+                   "seeding": args.kmeans_seeding, "seeding_s": round(seed_s, 4),
                    "iters": st["iters"], "converged": bool(st["converged"]), "J0": st["J0"], "J": st["J"],
                    "empty_clusters": st["empty"], "silhouette": round(sil, 5), "silhouette_s": round(sil_s, 4),
                    "stream_passes": passes, "ms_per_pass_incl_overheads": round(1e3 * wall / (passes + 1), 3),
@@ -723,6 +732,8 @@ def main():
     ap.add_argument("--kmeans-family", default="overlap", choices=["overlap", "paper"],
                     help="overlapping-groups returns, or the appendix's benchmark matrices (--kmeans-kinds)")
     ap.add_argument("--kmeans-kinds", default="corr,tpdm")
+    ap.add_argument("--kmeans-seeding", default="forgy", choices=["forgy", "kpp"],
+                    help="Forgy rows or k-means++ rows (symnmf_kmeans_seed_pp, timed with the run)")
     ap.add_argument("--kmeans-seeds", default="7,42,99")
     ap.add_argument("--logspace", action="store_true", help="projected vs softplus convergence counts instead of the "
                                                            "step rate")

@@ -472,6 +472,17 @@ typedef struct {
  * unless 1 <= K <= n. */
 symnmf_status symnmf_kmeans_seed_rows(uint64_t seed, int64_t n, int64_t K, int64_t* out);
 
+/* k-means++ seed rows (Arthur & Vassilvitskii 2007) on the unit rows of the
+ * stored S, for symnmf_kmeans's init_rows: the first is row floor(u_0 n);
+ * seed i is the smallest j with sum_{l <= j} d_l > u_i sum_l d_l, where
+ * d_l = min over the seeds so far of max(1 - cos(s^_l, s^_seed), 0) (the
+ * squared distance of unit vectors up to the factor 2; 0 at the seeds) and
+ * u_i is the i-th 53-bit uniform of SplitMix64 keyed by seed; when every d_l
+ * is 0 the lowest unchosen row is taken.  One S pass per seed (FP64 sums of
+ * d in a fixed order).  rows: host int64, K entries in draw order.
+ * 1 <= K <= n.  Synchronises. */
+symnmf_status symnmf_kmeans_seed_pp(symnmf_ctx* ctx, const symnmf_S* S, int64_t K, uint64_t seed, int64_t* rows);
+
 /* ||s_i|| for every row (norms: device FP64, n entries), one pass over S
  * with FP64 sums.  EINVAL when a row is zero (it has no direction).
  * Synchronises. */

@@ -69,9 +69,10 @@ def kmeanspp_rows(S, K: int, seed: int = 0) -> np.ndarray:
     where the squared Euclidean distance of unit vectors is 2 (1 - cos): the
     first seed is row floor(u_0 n); seed i is the smallest j with
     sum_{l <= j} d_l > u_i sum_l d_l, d_l = min over the seeds so far of
-    (1 - cos) (negative rounding clamped to 0), u_i the i-th 53-bit uniform
-    of the SplitMix64 stream keyed by seed.  If every d is 0 (fewer distinct
-    rows than K), the lowest unchosen row is taken."""
+    (1 - cos) (negative rounding clamped to 0, and exactly 0 at the seeds),
+    u_i the i-th 53-bit uniform of the SplitMix64 stream keyed by seed.  If
+    every d is 0 (fewer distinct rows than K), the lowest unchosen row is
+    taken."""
     Shat, _ = unit_rows(S)
     n = Shat.shape[0]
     if not 1 <= K <= n:
@@ -79,9 +80,9 @@ def kmeanspp_rows(S, K: int, seed: int = 0) -> np.ndarray:
     key = np.uint64(seed & (2**64 - 1))
     first = min(int(float(uniform53(key, 0)) * n), n - 1)
     rows = [first]
-    d = np.maximum(1.0 - Shat @ Shat[first], 0.0)
     chosen = np.zeros(n, dtype=bool)
     chosen[first] = True
+    d = np.where(chosen, 0.0, np.maximum(1.0 - Shat @ Shat[first], 0.0))
     for i in range(1, K):
         total = float(d.sum())
         if total > 0.0:
@@ -92,7 +93,7 @@ def kmeanspp_rows(S, K: int, seed: int = 0) -> np.ndarray:
             j = int(np.flatnonzero(~chosen)[0])
         rows.append(j)
         chosen[j] = True
-        d = np.minimum(d, np.maximum(1.0 - Shat @ Shat[j], 0.0))
+        d = np.where(chosen, 0.0, np.minimum(d, np.maximum(1.0 - Shat @ Shat[j], 0.0)))
     return np.array(rows, dtype=np.int64)
 
 

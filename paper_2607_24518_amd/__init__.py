@@ -124,6 +124,7 @@ SIGNATURES = {
     "symnmf_canonical": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_vp]),
     "symnmf_warm_start": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, c_i64, c_u64, c_vp]),
     "symnmf_kmeans_seed_rows": (c_i32, [c_u64, c_i64, c_i64, ctypes.POINTER(c_i64)]),
+    "symnmf_kmeans_seed_pp": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_i64, c_u64, ctypes.POINTER(c_i64)]),
     "symnmf_row_norms": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp]),
     "symnmf_kmeans_assign": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, c_vp, c_vp,
                                      ctypes.POINTER(c_dbl)]),
@@ -484,6 +485,13 @@ def symnmf_kmeans_seed_rows(seed: int, n: int, K: int):
     code = lib().symnmf_kmeans_seed_rows(seed, n, K, out)
     if code != OK:
         raise SymnmfError(code, "kmeans_seed_rows: need 1 <= K <= n")
+    return list(out)
+
+
+def symnmf_kmeans_seed_pp(ctx, S: Matrix, K: int, seed: int = 0):
+    """k-means++ seed rows (list of K ints, draw order)."""
+    out = (c_i64 * K)()
+    _check(ctx, lib().symnmf_kmeans_seed_pp(ctx, ctypes.byref(S.desc), K, seed, out))
     return list(out)
 
 

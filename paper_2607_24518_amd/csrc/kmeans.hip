@@ -410,6 +410,44 @@ __global__ __launch_bounds__(KT) void copy_col0_kernel(const T* __restrict__ X, 
     if (i < n) out[i] = (float)X[i * w];
 }
 
+// --------------------------------------------------------------------------
+// k-means++ seeding: row c of the stored S scaled by 1 / ||s_c|| into column 0
+// of a 16-wide slice, then d_j <- min(d_j, 1 - cos) after one S pass.
+// --------------------------------------------------------------------------
+template <int DT, typename T>   // DT: 0 FP32, 1 BF16, 2 FP8 tiled, 3 FP64 row-major
+__global__ __launch_bounds__(KT) void gather_row_kernel(const void* __restrict__ S, int64_t n, int64_t ld,
+                                                        int64_t n_chunks, const float* __restrict__ scale,
+                                                        const float* __restrict__ diag, int64_t panel_rows,
+                                                        int64_t c, double inv_norm, int w, T* __restrict__ X) {
+    const int64_t j = (int64_t)blockIdx.x * KT + threadIdx.x;
+    if (j >= n) return;
+    double v;
+    if (DT == 3) v = ((const double*)S)[c * ld + j];
+    else if (DT == 2) v = j == c ? (double)diag[c]
+                                 : (double)fp8e4m3_to_f32(((const uint8_t*)S)[tiled_offset(c, j, n_chunks, 16)]) /
+                                       (double)scale[c / panel_rows];
+    else if (DT == 1) v = (double)bf16_bits_to_f32(((const uint16_t*)S)[tiled_offset(c, j, n_chunks, 8)]);
+    else v = (double)((const float*)S)[tiled_offset(c, j, n_chunks, 4)];
+    X[j * w] = (T)(v * inv_norm);
+}
+
+// d_j = min(d_j, max(1 - (S x)_j / ||s_j||, 0)), 0 at the seeds; FP64 block sums
+template <typename T>
+__global__ __launch_bounds__(KT) void kpp_update_kernel(const T* __restrict__ P, const double* __restrict__ norms,
+                                                        const uint8_t* __restrict__ chosen, int64_t n, int w,
+                                                        double* __restrict__ d, double* __restrict__ part) {
+    const int64_t j = (int64_t)blockIdx.x * KT + threadIdx.x;
+    double v = 0.0;
+    if (j < n) {
+        const double dist = fmax(1.0 - (double)P[j * w] / norms[j], 0.0);
+        v = chosen[j] ? 0.0 : fmin(d[j], dist);
+        d[j] = v;
+    }
+    block_sum2(v, 0, part + blockIdx.x, nullptr);
+}
+
+__global__ void mark_kernel(uint8_t* __restrict__ chosen, int64_t c) { chosen[c] = 1; }
+
 inline unsigned blocks_for(int64_t m) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((m + KT - 1) / KT, 65536)); }
 
 // --------------------------------------------------------------------------
@@ -803,6 +841,107 @@ symnmf_status spectral_run(symnmf_ctx* ctx, KCall& kc, Scratch& sc, int64_t max_
     return SYMNMF_OK;
 }
 
+// k-means++ seed rows (host vector) on the unit rows of the stored S
+template <typename T>
+symnmf_status kpp_run(symnmf_ctx* ctx, KCall& kc, Scratch& sc, uint64_t seed, std::vector<int64_t>& rows) {
+    const symnmf_S* S = kc.S;
+    void* X = sc.get(kc.factor_bytes());
+    void* Pb = sc.get(kc.factor_bytes());
+    double* d = (double*)sc.get(kc.rows_pad * 8);
+    uint8_t* chosen = (uint8_t*)sc.get(kc.rows_pad);
+    double* part = (double*)sc.get(kc.row_blocks() * 8);
+    if (sc.err != hipSuccess) return fail(ctx, SYMNMF_ENOMEM, "kmeans_seed_pp: %s", hipGetErrorString(sc.err));
+    symnmf_status r = compute_norms(ctx, kc, sc);
+    if (r != SYMNMF_OK) return r;
+    std::vector<double> norms_h((size_t)kc.n);
+    HIP_OK(ctx, hipMemcpyAsync(norms_h.data(), kc.norms, kc.n * 8, hipMemcpyDeviceToHost, kc.sm));
+    HIP_OK(ctx, hipStreamSynchronize(kc.sm));
+    const unsigned nb = (unsigned)kc.row_blocks();
+    const bool fp8 = S->dtype == SYMNMF_S_FP8;
+    const int64_t pr = S->fp8_panel_rows > 0 ? S->fp8_panel_rows : 1;
+    auto draw = [&](int64_t i) { return (double)(splitmix64(seed, (uint64_t)i) >> 11) * 0x1.0p-53; };
+    auto add_seed = [&](int64_t c) -> hipError_t {
+        const double inv = 1.0 / norms_h[(size_t)c];
+        switch (S->dtype) {
+            case SYMNMF_S_FP32:
+                hipLaunchKernelGGL((gather_row_kernel<0, T>), dim3(nb), dim3(KT), 0, kc.sm, S->data, kc.n, S->ld,
+                                   kc.chunks, S->panel_scale, S->diag, pr, c, inv, (int)kc.w, (T*)X);
+                break;
+            case SYMNMF_S_BF16:
+                hipLaunchKernelGGL((gather_row_kernel<1, T>), dim3(nb), dim3(KT), 0, kc.sm, S->data, kc.n, S->ld,
+                                   kc.chunks, S->panel_scale, S->diag, pr, c, inv, (int)kc.w, (T*)X);
+                break;
+            case SYMNMF_S_FP8:
+                hipLaunchKernelGGL((gather_row_kernel<2, T>), dim3(nb), dim3(KT), 0, kc.sm, S->data, kc.n, S->ld,
+                                   kc.chunks, S->panel_scale, S->diag, pr, c, inv, (int)kc.w, (T*)X);
+                break;
+            default:
+                hipLaunchKernelGGL((gather_row_kernel<3, T>), dim3(nb), dim3(KT), 0, kc.sm, S->data, kc.n, S->ld,
+                                   kc.chunks, S->panel_scale, S->diag, pr, c, inv, (int)kc.w, (T*)X);
+        }
+        hipLaunchKernelGGL(mark_kernel, dim3(1), dim3(1), 0, kc.sm, chosen, c);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = s_times(kc, X, Pb);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kpp_update_kernel<T>, dim3(nb), dim3(KT), 0, kc.sm, (const T*)Pb, kc.norms, chosen, kc.n,
+                           (int)kc.w, d, part);
+        return hipGetLastError();
+    };
+    (void)fp8;
+    // d starts at +infinity (the first update takes the distances to seed 0)
+    {
+        std::vector<double> inf((size_t)kc.n, INFINITY);
+        HIP_OK(ctx, hipMemcpyAsync(d, inf.data(), kc.n * 8, hipMemcpyHostToDevice, kc.sm));
+        HIP_OK(ctx, hipStreamSynchronize(kc.sm));
+    }
+    std::vector<uint8_t> chosen_h((size_t)kc.n, 0);
+    rows.clear();
+    int64_t first = (int64_t)(draw(0) * (double)kc.n);
+    if (first > kc.n - 1) first = kc.n - 1;
+    rows.push_back(first);
+    chosen_h[(size_t)first] = 1;
+    HIP_OK(ctx, add_seed(first));
+    std::vector<double> parts(nb), blk(KT);
+    for (int64_t i = 1; i < kc.K; ++i) {
+        HIP_OK(ctx, hipMemcpyAsync(parts.data(), part, nb * 8, hipMemcpyDeviceToHost, kc.sm));
+        HIP_OK(ctx, hipStreamSynchronize(kc.sm));
+        double total = 0.0;
+        for (unsigned b = 0; b < nb; ++b) total += parts[b];
+        if (!std::isfinite(total)) return fail(ctx, SYMNMF_ENUMERIC, "kmeans_seed_pp: non-finite distances");
+        int64_t j = -1;
+        if (total > 0.0) {
+            // smallest j with sum_{l <= j} d_l > u_i * total
+            const double target = draw(i) * total;
+            double acc = 0.0;
+            unsigned b = 0;
+            while (b + 1 < nb && acc + parts[b] <= target) acc += parts[b++];
+            const int64_t r0 = (int64_t)b * KT;
+            const int64_t cnt = std::min<int64_t>(KT, kc.n - r0);
+            HIP_OK(ctx, hipMemcpyAsync(blk.data(), d + r0, cnt * 8, hipMemcpyDeviceToHost, kc.sm));
+            HIP_OK(ctx, hipStreamSynchronize(kc.sm));
+            j = r0 + cnt - 1;
+            for (int64_t q = 0; q < cnt; ++q) {
+                acc += blk[(size_t)q];
+                if (acc > target) {
+                    j = r0 + q;
+                    break;
+                }
+            }
+        } else {
+            for (int64_t q = 0; q < kc.n; ++q)
+                if (!chosen_h[(size_t)q]) {
+                    j = q;
+                    break;
+                }
+        }
+        rows.push_back(j);
+        chosen_h[(size_t)j] = 1;
+        if (i + 1 < kc.K) HIP_OK(ctx, add_seed(j));
+    }
+    HIP_OK(ctx, hipStreamSynchronize(kc.sm));
+    return SYMNMF_OK;
+}
+
 }  // namespace
 }  // namespace symnmf
 
@@ -814,6 +953,23 @@ symnmf_status symnmf_kmeans_seed_rows(uint64_t seed, int64_t n, int64_t K, int64
     if (!out || K < 1 || K > n) return SYMNMF_EINVAL;
     const std::vector<int64_t> rows = forgy_rows(seed, n, K);
     std::copy(rows.begin(), rows.end(), out);
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_kmeans_seed_pp(symnmf_ctx* ctx, const symnmf_S* S, int64_t K, uint64_t seed, int64_t* rows) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!rows) return fail(ctx, SYMNMF_EINVAL, "kmeans_seed_pp: rows is NULL");
+    Scratch sc(ctx->stream);
+    KCall kc;
+    // one-column passes: K = 1 sets up a 16-wide slice; the seed count is K
+    symnmf_status r = kcall_setup(ctx, S, 1, sc, kc);
+    if (r != SYMNMF_OK) return r;
+    if (K < 1 || K > kc.n) return fail(ctx, SYMNMF_EINVAL, "kmeans_seed_pp: need 1 <= K <= n");
+    kc.K = K;
+    std::vector<int64_t> v;
+    r = kc.f64 ? kpp_run<double>(ctx, kc, sc, seed, v) : kpp_run<float>(ctx, kc, sc, seed, v);
+    if (r != SYMNMF_OK) return r;
+    std::copy(v.begin(), v.end(), rows);
     return SYMNMF_OK;
 }
 

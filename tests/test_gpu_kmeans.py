@@ -317,3 +317,21 @@ def test_spectral_diagnostic_reproduces_the_paper_table_at_n_10000(golden_dir):
         lam_p, reff_p = ref[(kind, n)]
         assert np.mean(lams) == pytest.approx(lam_p, rel=0.05), kind
         assert abs(np.mean(reffs) - reff_p) < 0.1, kind
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_kmeanspp_seeds_match_oracle(stores, dtype):
+    """k-means++ seeds on the GPU (one S pass per seed) against the oracle's
+    draw on the stored S; a run from them follows the oracle's Lloyd run."""
+    S, M = stores[dtype]
+    for seed, K in [(0, 6), (3, 9), (11, 20)]:
+        got = sym.symnmf_kmeans_seed_pp(ctx(), S, K, seed)
+        assert got == km.kmeanspp_rows(M, K, seed).tolist(), (seed, K)
+    if dtype == "fp64":
+        rows = sym.symnmf_kmeans_seed_pp(ctx(), S, 6, 5)
+        labels = torch.zeros(600, dtype=torch.int32, device=dev())
+        st = sym.symnmf_kmeans(ctx(), S, 6, labels, init_rows=rows)
+        ref = km.lloyd(M, 6, init_rows=rows)
+        assert st["iters"] == ref["iters"] and np.array_equal(from_dev(labels).astype(np.int64), ref["labels"])
+    with pytest.raises(sym.SymnmfError):
+        sym.symnmf_kmeans_seed_pp(ctx(), S, 601, 0)
