@@ -553,6 +553,79 @@ def logspace_study(args):
     return {"converged_of_6": table, "runs": runs}
 
 
+def phase1_study(args):
+    """The paper's Phase-1 protocol on the appendix's benchmark matrices: for
+    n in --phase1-sizes, both matrix types and seeds 7, 42, 99 (6 runs per
+    size), every method solves with the three-criterion stop rule within
+    --logspace-budget iterations; reports the runs certified and the mean wall
+    time of the certified runs (the paper's Phase-1 table, one GPU).
+    k = floor(sqrt(n)), capped at 64."""
+    import torch
+    import paper_2607_24518_amd as sym
+    import synth
+    dev = torch.device("cuda:0")
+    ctx = sym.symnmf_create(0)
+    sizes = [int(v) for v in args.phase1_sizes.split(",")]
+    svrg = dict(block_rows=256, snapshot_s=10, delta=10, phi0=0.75, row_frac=0.5)
+    methods = {
+        "admm": dict(method=sym.ADMM, c=1.0, rho=500.0),
+        "rmsprop": dict(method=sym.RMSPROP, c=0.03, eps=1e-8, alpha=0.99, mu=0.5),
+        "blocksvrg": dict(method=sym.BLOCK_SVRG, c=1.0, **svrg),
+        "adagrad": dict(method=sym.ADAGRAD, c=1.0),
+        "rowsvrg": dict(method=sym.ROW_SVRG, c=1.0, **svrg),
+        "piecewise": dict(method=sym.PIECEWISE_ADAGRAD, c=1.0),
+        "adan": dict(method=sym.ADAN, c=ADAM_ETA["adan"], beta1=0.98, beta2=0.92, beta3=0.99),
+        "adam": dict(method=sym.ADAM, c=ADAM_ETA["adam"]),
+        "nadam": dict(method=sym.NADAM, c=ADAM_ETA["nadam"]),
+        "mu": dict(method=sym.MU, c=1.0, eps=2.0 ** -23),
+    }
+    runs = []
+    for n in sizes:
+        k = min(math.isqrt(n), 64)
+        for kind in ("corr", "tpdm"):
+            for seed in (7, 42, 99):
+                X = synth.paper_benchmark(seed, n, kind, device=dev).X
+                if kind == "corr":
+                    S = sym.symnmf_build_S(ctx, X, kind=sym.ABS_CORR, dtype=sym.S_FP32)
+                else:
+                    S = sym.symnmf_build_S(ctx, X, kind=sym.TPDM, dtype=sym.S_FP32, q=0.01, lower_tail=0,
+                                           raw_marginals=1)
+                del X
+                H0 = torch.empty(n, k, device=dev)
+                sym.symnmf_init_H(ctx, S, k, seed, H0)
+                base = math.sqrt(S.desc.mean / k)
+                for name, m in methods.items():
+                    kw = {q: v for q, v in m.items() if q != "c"}
+                    p = sym.symnmf_params_default(eta=m["c"] * base, max_iter=args.logspace_budget, seed=seed, **kw)
+                    st = sym.symnmf_state_create(ctx, S, k, p, H0)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    try:
+                        stats, conv = sym.symnmf_solve_to_tol(ctx, S, st)
+                    except sym.SymnmfError as e:
+                        log(f"phase1 n={n} {kind} seed={seed} {name}: {e}")
+                        stats, conv = sym.symnmf_state_stats(ctx, st), False
+                    wall = time.perf_counter() - t0
+                    rec = {"n": n, "k": k, "kind": kind, "seed": seed, "method": name, "converged": bool(conv),
+                           "t": int(stats.t), "E": stats.E, "kkt": stats.kkt, "seconds": round(wall, 4)}
+                    runs.append(rec)
+                    log(f"phase1 {rec}")
+                    del st
+                del S
+                torch.cuda.empty_cache()
+    table = {}
+    for name in methods:
+        row = {}
+        for n in sizes:
+            rr = [r for r in runs if r["method"] == name and r["n"] == n]
+            ok = [r for r in rr if r["converged"]]
+            row[str(n)] = {"converged": f"{len(ok)}/{len(rr)}",
+                           "wall_s": round(sum(r["seconds"] for r in ok) / len(ok), 3) if ok else None,
+                           "iters": round(sum(r["t"] for r in ok) / len(ok), 1) if ok else None}
+        table[name] = row
+    return {"table": table, "runs": runs}
+
+
 def kmeans_paper_benchmark(args, ctx, Ks):
     """K-means on the appendix's own benchmark matrices (floor(sqrt(n))
     groups plus the common factor, 40000 samples; |corr| and the raw-marginal
@@ -739,7 +812,17 @@ def main():
                                                            "step rate")
     ap.add_argument("--logspace-sizes", default="100,1000,10000")
     ap.add_argument("--logspace-budget", type=int, default=20000)
+    ap.add_argument("--phase1", action="store_true", help="the paper's Phase-1 table (every method, n <= 1e4) "
+                                                         "instead of the step rate")
+    ap.add_argument("--phase1-sizes", default="100,1000,10000")
     args = ap.parse_args()
+
+    if args.phase1:
+        res = phase1_study(args)
+        print(json.dumps({"metric": "runs certified by the stop rule and mean wall time of the certified runs",
+                          "unit": "s", "n_gpus": 1, "data": "synthetic", "budget": args.logspace_budget, **res}),
+              flush=True)
+        return
 
     if args.logspace:
         res = logspace_study(args)
