@@ -340,41 +340,123 @@ inline int64_t syrk_grid(int64_t n_ti, int64_t n_tj) {
     return (blocks + 7) / 8 * 8 * 64;
 }
 
+// A full square S (no row panel) is symmetric, so the S-building GEMMs
+// compute only the 128 x 128 tiles with ti <= tj; the work-group of an
+// off-diagonal tile also stores its transpose.  The transposed value is
+// bitwise the one the (tj, ti) tile would compute: the products commute and
+// the reduction runs over the same samples in the same order.  Work-groups of
+// tiles below the diagonal only clear their sum slot.
+__device__ inline bool syrk_symmetric(const BuildOut& o) { return o.row0 == 0 && o.rows == o.n; }
+
 // Epilogue of the S-building GEMMs: |.|, unit diagonal, storage rounding into
 // the tiled layout, FP64 sums per work-group (MODE 1), or the FP8 panel
 // maxima (MODE 0).  acc[a][b][v] holds element (64 wr + 16 a + 4 lg + v,
 // 64 wc + 16 b + lr) of the work-group's 128 x 128 tile (the D layout of the
-// 16 x 16 MFMAs).
+// 16 x 16 MFMAs).  With mirror, element (j, i) of the transposed tile is
+// stored too: a lane's four v values are four consecutive columns of row j,
+// one aligned piece of a 16-byte vector of the tiled layout.
+// tab: 128 + 128 words of work-group scratch (MODE 0: row and column maxima;
+// FP8 MODE 1: the scales of the tile's rows and of the mirrored rows), inv:
+// 256 doubles (FP8 MODE 1: their reciprocals).
 template <int MODE, int DT>
-__device__ inline void syrk_epilogue(const floatx4 (&acc)[4][4], int64_t i0, int64_t j0, const BuildOut& o,
-                                     double* __restrict__ wg_sums, uint32_t* __restrict__ panel_max,
-                                     uint32_t* rowmax, double (*red)[4], int64_t slot) {
+__device__ __attribute__((always_inline)) inline void syrk_epilogue(const floatx4 (&acc)[4][4], int64_t i0, int64_t j0, bool mirror,
+                                     const BuildOut& o, double* __restrict__ wg_sums,
+                                     uint32_t* __restrict__ panel_max, uint32_t* tab, double* inv,
+                                     double (*red)[4], int64_t slot) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1, lr = lane & 15, lg = lane >> 4;
+    // |S_ij| of an off-diagonal element inside the matrix, else 0
+    auto offdiag = [&](int a, int b, int v) -> float {
+        const int64_t i = i0 + 64 * wr + 16 * a + 4 * lg + v, j = j0 + 64 * wc + 16 * b + lr;
+        const bool valid = i < o.rows && j < o.n && o.row0 + i != j;
+        return valid ? __builtin_fabsf(acc[a][b][v]) : 0.0f;
+    };
     if (MODE == 0) {
-        if (t < 128) rowmax[t] = 0;
+        // maxima of non-negative floats compare as their bit patterns; rows
+        // reduce over b in registers and over the 16 lanes lr, columns over
+        // a and v in registers and over the 4 lanes lg, then one LDS atomic
+        // per row (column) and wave
+        uint32_t* rowmax = tab;
+        uint32_t* colmax = tab + 128;
+        if (t < 128) {
+            rowmax[t] = 0;
+            colmax[t] = 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float r = 0.0f;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) r = fmaxf(r, offdiag(a, b, v));
+#pragma unroll
+                for (int sh = 1; sh < 16; sh <<= 1) r = fmaxf(r, __shfl_xor(r, sh, 64));
+                if (lr == 0 && r > 0.0f) atomicMax(&rowmax[64 * wr + 16 * a + 4 * lg + v], __builtin_bit_cast(uint32_t, r));
+            }
+        if (mirror) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                float c = 0.0f;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) c = fmaxf(c, offdiag(a, b, v));
+                c = fmaxf(c, __shfl_xor(c, 16, 64));
+                c = fmaxf(c, __shfl_xor(c, 32, 64));
+                if (lg == 0 && c > 0.0f) atomicMax(&colmax[64 * wc + 16 * b + lr], __builtin_bit_cast(uint32_t, c));
+            }
+        }
+        __syncthreads();
+        // one device atomic per scale panel that the tile's rows (and the
+        // mirrored rows) touch: the thread of the first such row of a panel
+        // reduces the panel's rows of the tile
+        const int q = t & 127;
+        const bool col = t >= 128;
+        const int64_t base = col ? j0 : i0, r = base + q;
+        if ((!col || mirror) && r < o.rows) {
+            const int64_t pnl = r / o.panel_rows, first = pnl * o.panel_rows;
+            if (q == 0 || r == first) {
+                const uint32_t* mx = col ? colmax : rowmax;
+                const int64_t end = min(min(first + o.panel_rows, o.rows), base + 128) - base;
+                uint32_t m = 0;
+                for (int u = q; u < end; ++u) m = max(m, mx[u]);
+                if (m) atomicMax(&panel_max[pnl], m);
+            }
+        }
+        return;
+    }
+    float* srow = (float*)tab;            // FP8: scale of tile row li
+    float* scol = (float*)tab + 128;      // FP8: scale of mirrored row lj
+    if constexpr (DT == SYMNMF_S_FP8) {
+        const int64_t r = t < 128 ? i0 + t : j0 + (t - 128);
+        float sc = 1.0f;
+        if (r < o.rows && (t < 128 || mirror)) sc = o.scale[r / o.panel_rows];
+        tab[t] = __builtin_bit_cast(uint32_t, sc);
+        inv[t] = 1.0 / (double)sc;
         __syncthreads();
     }
+    constexpr int E = DT == SYMNMF_S_FP32 ? 4 : (DT == SYMNMF_S_BF16 ? 8 : 16);
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    // per 16 x 16 block (a, b): the tile's elements, then (mirror) the
+    // transposed block, row j with four consecutive columns per lane (never a
+    // diagonal element, i < j; an FP8 element takes the scale of row j); the
+    // block's accumulators are dead after it, which keeps register pressure
+    // at the level of the tile alone
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 4; ++b) {
+            const int lj = 64 * wc + 16 * b + lr;
+            const int64_t j = j0 + lj;                         // column (mirror: row)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int li = 64 * wr + 16 * a + 4 * lg + v;
                 const int64_t i = i0 + li;                     // panel row
-                const int64_t j = j0 + 64 * wc + 16 * b + lr;  // column
-                const int64_t gi = o.row0 + i;
                 const bool valid = i < o.rows && j < o.n;
-                const bool diag = valid && gi == j;
+                const bool diag = valid && o.row0 + i == j;
                 float val = valid ? __builtin_fabsf(acc[a][b][v]) : 0.0f;
                 if (diag) val = 1.0f;
-                if (MODE == 0) {
-                    if (valid && !diag) atomicMax(&rowmax[li], __builtin_bit_cast(uint32_t, val));
-                    continue;
-                }
-                constexpr int E = DT == SYMNMF_S_FP32 ? 4 : (DT == SYMNMF_S_BF16 ? 8 : 16);
                 const int64_t off = tiled_offset(i, j, o.ld / KC, E);
                 double stored;
                 if constexpr (DT == SYMNMF_S_FP32) {
@@ -390,10 +472,9 @@ __device__ inline void syrk_epilogue(const floatx4 (&acc)[4][4], int64_t i0, int
                         o.diag[i] = val;
                         stored = val;
                     } else if (valid) {
-                        const float sc = o.scale[i / o.panel_rows];
-                        const uint8_t code = f32_to_fp8e4m3(val * sc);
+                        const uint8_t code = f32_to_fp8e4m3(val * srow[li]);
                         ((uint8_t*)o.data)[off] = code;
-                        stored = (double)fp8e4m3_to_f32(code) / (double)sc;
+                        stored = (double)fp8e4m3_to_f32(code) * inv[li];
                     } else {
                         ((uint8_t*)o.data)[off] = 0;
                         stored = 0.0;
@@ -403,14 +484,40 @@ __device__ inline void syrk_epilogue(const floatx4 (&acc)[4][4], int64_t i0, int
                 s2 += (double)val * (double)val;
                 s3 += stored * stored;
             }
-    if (MODE == 0) {
-        __syncthreads();
-        if (t < 128) {
-            const int64_t i = i0 + t;
-            if (i < o.rows && rowmax[t]) atomicMax(&panel_max[i / o.panel_rows], rowmax[t]);
+            if (mirror) {
+                uint32_t mw[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t i = i0 + 64 * wr + 16 * a + 4 * lg + v;
+                    const bool valid = i < o.rows && j < o.n;
+                    const float val = valid ? __builtin_fabsf(acc[a][b][v]) : 0.0f;
+                    double stored;
+                    if constexpr (DT == SYMNMF_S_FP32) {
+                        mw[v] = __builtin_bit_cast(uint32_t, val);
+                        stored = val;
+                    } else if constexpr (DT == SYMNMF_S_BF16) {
+                        const uint16_t bits = f32_to_bf16_bits(val);
+                        mw[v] = bits;
+                        stored = bf16_bits_to_f32(bits);
+                    } else {
+                        const uint8_t code = valid ? f32_to_fp8e4m3(val * scol[lj]) : (uint8_t)0;
+                        mw[v] = code;
+                        stored = (double)fp8e4m3_to_f32(code) * inv[128 + lj];
+                    }
+                    s1 += val;
+                    s2 += (double)val * (double)val;
+                    s3 += stored * stored;
+                }
+                const int64_t off = tiled_offset(j, i0 + 64 * wr + 16 * a + 4 * lg, o.ld / KC, E);
+                if constexpr (DT == SYMNMF_S_FP32) {
+                    *(u32x4*)((float*)o.data + off) = u32x4{mw[0], mw[1], mw[2], mw[3]};
+                } else if constexpr (DT == SYMNMF_S_BF16) {
+                    *(u32x2*)((uint16_t*)o.data + off) = u32x2{mw[0] | (mw[1] << 16), mw[2] | (mw[3] << 16)};
+                } else {
+                    *(uint32_t*)((uint8_t*)o.data + off) = mw[0] | (mw[1] << 8) | (mw[2] << 16) | (mw[3] << 24);
+                }
+            }
         }
-        return;
-    }
     for (int off = 32; off > 0; off >>= 1) {
         s1 += __shfl_down(s1, off, 64);
         s2 += __shfl_down(s2, off, 64);
@@ -433,10 +540,16 @@ __global__ __launch_bounds__(256, 2) void syrk_kernel(const float* __restrict__ 
                                                    uint32_t* __restrict__ panel_max) {
     __shared__ float As[2][16][128 + 4];
     __shared__ float Bs[2][16][128 + 4];
-    __shared__ uint32_t rowmax[128];
+    __shared__ uint32_t tab[256];
+    __shared__ double inv[(MODE == 1 && DT == SYMNMF_S_FP8) ? 256 : 1];
     __shared__ double red[3][4];
     int64_t ti, tj;
     if (!syrk_tile(blockIdx.x, n_ti, n_tj, ti, tj)) return;
+    const bool sym = syrk_symmetric(o);
+    if (sym && ti > tj) {
+        if (MODE == 1 && threadIdx.x < 3) wg_sums[(ti * n_tj + tj) * 3 + threadIdx.x] = 0.0;
+        return;
+    }
     const int64_t i0 = ti * 128, j0 = tj * 128;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1, lr = lane & 15, lg = lane >> 4;
@@ -491,7 +604,8 @@ __global__ __launch_bounds__(256, 2) void syrk_kernel(const float* __restrict__ 
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
     }
-    syrk_epilogue<MODE, DT>(acc, i0, j0, o, wg_sums, panel_max, rowmax, red, ti * n_tj + tj);
+    syrk_epilogue<MODE, DT>(acc, i0, j0, sym && ti < tj, o, wg_sums, panel_max, tab, inv, red,
+                            ti * n_tj + tj);
 }
 
 // ---------------------------------------------------------------------------
@@ -545,10 +659,16 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(const uint16_t* __re
     // vector q of thread t sits at f = t + 256 q of its buffer: side q / 4,
     // plane (q / 2) % 2, row t / 4 + 64 (q % 2), part t % 4
     __shared__ u32x4 lds[2 * 2048];
-    __shared__ uint32_t rowmax[128];
+    __shared__ uint32_t tab[256];
+    __shared__ double inv[(MODE == 1 && DT == SYMNMF_S_FP8) ? 256 : 1];
     __shared__ double red[3][4];
     int64_t ti, tj;
     if (!syrk_tile(blockIdx.x, n_ti, n_tj, ti, tj)) return;
+    const bool sym = syrk_symmetric(o);
+    if (sym && ti > tj) {
+        if (MODE == 1 && threadIdx.x < 3) wg_sums[(ti * n_tj + tj) * 3 + threadIdx.x] = 0.0;
+        return;
+    }
     const int64_t i0 = ti * 128, j0 = tj * 128;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1, lr = lane & 15, lg = lane >> 4;
@@ -608,7 +728,8 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(const uint16_t* __re
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] += crs[a][b];
-    syrk_epilogue<MODE, DT>(acc, i0, j0, o, wg_sums, panel_max, rowmax, red, ti * n_tj + tj);
+    syrk_epilogue<MODE, DT>(acc, i0, j0, sym && ti < tj, o, wg_sums, panel_max, tab, inv, red,
+                            ti * n_tj + tj);
 }
 
 // FP64 S (parity runs): plain FP64 FMAs, 64 x 64 tile per work-group, each

@@ -66,15 +66,23 @@ def test_build_abs_corr(X600, S600, dtype):
     assert S.desc.fro2 == pytest.approx((ref * ref).sum(), rel=1e-6 if dtype != "fp64" else 1e-12)
     assert S.desc.fro2_stored == pytest.approx((M * M).sum(), rel=1e-9)
     assert S.desc.mean == pytest.approx(ref.mean(), rel=1e-6)
-    assert np.all(M == M.T) or dtype == "fp8"   # every tile is computed, products commute exactly
+    # upper tiles are computed and stored twice (FP8 rows carry their own panel scale)
+    assert np.all(M == M.T) or dtype == "fp8"
 
 
-def test_build_row_panel_equals_rows_of_full(X600):
+@pytest.mark.parametrize("dtype,row0,rows", [("fp32", 130, 300), ("bf16", 130, 300), ("fp8", 128, 256),
+                                             ("fp32", 0, 599)])
+def test_build_row_panel_equals_rows_of_full(X600, dtype, row0, rows):
+    """A row panel computes every tile of its rows directly; the full square
+    build computes the tiles on and above the diagonal and mirrors them, so
+    its lower rows must be the same bits (FP8: panels aligned to the scale
+    panels, whose maxima then cover the same rows)."""
     c = ctx()
-    full = stored_numpy(sym.symnmf_build_S(c, to_dev(X600), dtype=sym.S_FP32))
-    pan = stored_numpy(sym.symnmf_build_S(c, to_dev(X600), dtype=sym.S_FP32, row0=130, rows=300))
-    assert pan.shape == (300, 600)
-    assert np.array_equal(pan, full[130:430])
+    kw = dict(dtype=sym.DTYPES[dtype], fp8_panel_rows=128)
+    full = stored_numpy(sym.symnmf_build_S(c, to_dev(X600), **kw))
+    pan = stored_numpy(sym.symnmf_build_S(c, to_dev(X600), row0=row0, rows=rows, **kw))
+    assert pan.shape == (rows, 600)
+    assert np.array_equal(pan, full[row0:row0 + rows])
 
 
 @pytest.mark.parametrize("dtype,tol", [("fp64", 1e-12), ("fp32", 3e-6)])
