@@ -70,6 +70,47 @@ def test_build_abs_corr(X600, S600, dtype):
     assert np.all(M == M.T) or dtype == "fp8"
 
 
+@pytest.mark.parametrize("n", [1, 2, 127, 128, 129, 257, 384])
+@pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp8"])
+def test_build_tile_boundaries(n, dtype):
+    """Sizes on both sides of the 128-row output tiles and the 256-row storage
+    tiles: the mirrored blocks land where the oracle's entries are, the
+    padding stays zero, and (FP8, 100-row scale panels that straddle the
+    tiles) every panel's largest off-diagonal entry is coded as 448, which
+    only holds if the panel maxima covered the panel's rows in every tile
+    and every mirrored block."""
+    inst = synth.c1_instance(5, T=300, n=n, groups=1 if n < 8 else 4)
+    X = inst.X.numpy()
+    ref = o.abs_corr(X)
+    c = ctx()
+    S = sym.symnmf_build_S(c, to_dev(X), dtype=sym.DTYPES[dtype], fp8_panel_rows=100)
+    M = stored_numpy(S)
+    assert np.all(np.diag(M) == 1.0)
+    if dtype == "fp32":
+        assert np.max(np.abs(M - ref)) < 2e-6
+        assert np.all(M == M.T)
+    elif dtype == "bf16":
+        ulp = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(ref), 1e-30))) - 7)
+        assert np.all(np.abs(M - ref) <= 0.5 * ulp + 2e-6)
+        assert np.all(M == M.T)
+    else:
+        off = ~np.eye(n, dtype=bool)
+        assert np.all(np.abs(M - ref)[off] <= 2.0 ** -4 * np.abs(ref)[off] + 2.0 ** -9 / 448 * 1.2 + 1e-7)
+        d = S.desc
+        scale = from_dev(S.buf[d.panel_scale - d.data: d.panel_scale - d.data + 4 * ((n + 99) // 100)]
+                         .view(torch.float32))
+        for p in range(0, n, 100):
+            blk = (M[p:p + 100] * scale[p // 100])[off[p:p + 100]]
+            if blk.size:
+                assert np.max(np.abs(blk)) == pytest.approx(448.0, rel=1e-6), p
+    # the tiled buffer holds nothing outside the matrix
+    d = S.desc
+    E = {"fp32": 4, "bf16": 2, "fp8": 1}[dtype]
+    raw = S.buf[: d.rows_pad * d.ld * E]
+    nz = int(torch.count_nonzero(raw).item())
+    assert nz <= n * n * E
+
+
 @pytest.mark.parametrize("dtype,row0,rows", [("fp32", 130, 300), ("bf16", 130, 300), ("fp8", 128, 256),
                                              ("fp32", 0, 599)])
 def test_build_row_panel_equals_rows_of_full(X600, dtype, row0, rows):
