@@ -100,12 +100,15 @@ def cpu_baseline(X_host, k, H0, eta, rows, steps, total_rows):
                       f"{build_s:.1f} s not timed"}
 
 
-def ttt_trace(ctx, S, k, params, init, max_steps, every, store):
+def ttt_trace(ctx, S, k, params, init, max_steps, every, store, S_hi=None, tau_switch=None):
     """Iterate from init(H) for max_steps with every rule of the solve applied
     at the checks (symnmf_solve_trace), keeping every ``every``-th iterate in
-    ``store``.  Returns (seconds of every kept iterate from the start of the
-    initialisation, first certified t or -1, initialisation seconds); times
-    come from HIP events on the solver stream."""
+    ``store``.  With S_hi, the precision ladder: the state moves from S to
+    S_hi at the first check whose stagnation measure is below tau_switch
+    (symnmf_solve_trace_ladder).  Returns (seconds of every kept iterate from
+    the start of the initialisation, first certified t or -1, initialisation
+    seconds, switch t or -1); times come from HIP events on the solver
+    stream."""
     import torch
     import paper_2607_24518_amd as sym
 
@@ -118,11 +121,16 @@ def ttt_trace(ctx, S, k, params, init, max_steps, every, store):
     init(H)
     st = sym.symnmf_state_create(ctx, S, k, params, H)
     ev_b.record()
-    ms, certified = sym.symnmf_solve_trace(ctx, S, st, nsave * every, every, store)
+    switched = -1
+    if S_hi is None:
+        ms, certified = sym.symnmf_solve_trace(ctx, S, st, nsave * every, every, store)
+    else:
+        ms, certified, switched = sym.symnmf_solve_trace_ladder(ctx, S, S_hi, st, nsave * every, every, store,
+                                                                tau_switch)
     torch.cuda.synchronize()
     t_init = ev_a.elapsed_time(ev_b) / 1000.0
     del st
-    return [t_init + m / 1000.0 for m in ms], certified, t_init
+    return [t_init + m / 1000.0 for m in ms], certified, t_init, switched
 
 
 def ttt_scan(objective_of, store, nsave, f_ref, tol, every, times):
@@ -156,11 +164,15 @@ def ttt_scan(objective_of, store, nsave, f_ref, tol, every, times):
     return entry
 
 
-def ttt_run(ctx, S, k, params, init, objective_of, f_ref, tol, max_steps, every, store):
+def ttt_run(ctx, S, k, params, init, objective_of, f_ref, tol, max_steps, every, store, S_hi=None,
+            tau_switch=None):
     """Trace from init(H), then the time to (objective_of(H_t) - f_ref) / f_ref <= tol."""
-    times, certified, t_init = ttt_trace(ctx, S, k, params, init, max_steps, every, store)
+    times, certified, t_init, switched = ttt_trace(ctx, S, k, params, init, max_steps, every, store, S_hi,
+                                                   tau_switch)
     entry = ttt_scan(objective_of, store, max_steps // every, f_ref, tol, every, times)
     entry.update(init_seconds=round(t_init, 4), certified_at=certified, times=times)
+    if S_hi is not None:
+        entry.update(switched_at=switched)
     return entry
 
 
@@ -236,9 +248,9 @@ def time_to_tolerance(args):
     stores = {"fp32": sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32, **build)}
     variants = [v for v in args.ttt_variants.split(",") if v]
     for v in variants:
-        dt = v.split("-")[0]
-        if dt not in stores:
-            stores[dt] = sym.symnmf_build_S(ctx, X, dtype=sym.DTYPES[dt], **build)
+        for dt in v.split("-")[0].split(">"):       # "fp8>bf16": the precision ladder
+            if dt not in stores:
+                stores[dt] = sym.symnmf_build_S(ctx, X, dtype=sym.DTYPES[dt], **build)
     del X
     S32 = stores["fp32"]
     eta = math.sqrt(S32.desc.mean / k)
@@ -252,9 +264,11 @@ def time_to_tolerance(args):
     every = max(1, args.ttt_save_every)
     store = torch.empty(args.ttt_max // every, n, k, device=dev)
     for v in variants:
-        S = stores[v.split("-")[0]]
+        ladder = v.split("-")[0].split(">")
+        S = stores[ladder[0]]
+        S_hi = stores[ladder[1]] if len(ladder) > 1 else None
         entry = ttt_run(ctx, S, k, variant_params(v, eta), lambda H: sym.symnmf_init_H(ctx, S, k, 1, H), objective_of,
-                        f_ref, args.ttt_tol, args.ttt_max, every, store)
+                        f_ref, args.ttt_tol, args.ttt_max, every, store, S_hi, args.ttt_switch)
         entry.pop("times")
         results["variants"][v] = entry
         log(f"variant {v}: {entry}")
@@ -396,7 +410,7 @@ def warm_start_study(args):
 
         every = 2
         store = torch.empty(rand_steps // every, nn, k_eval, device=dev)
-        times, cert, t_init = ttt_trace(ctx, S, k_eval, params, lambda H: sym.symnmf_init_H(ctx, S, k_eval, seed, H),
+        times, cert, t_init, _ = ttt_trace(ctx, S, k_eval, params, lambda H: sym.symnmf_init_H(ctx, S, k_eval, seed, H),
                                         rand_steps, every, store)
         ref_slot = (cert + 1) // every - 1 if cert >= 0 else rand_steps // every - 1
         f_ref = objective_of(store[ref_slot])
@@ -408,7 +422,7 @@ def warm_start_study(args):
         }
         r_it, r_s = res["random"].get("iters"), res["random"].get("seconds")
         for name, init in inits.items():
-            wt, wcert, w_init = ttt_trace(ctx, S, k_eval, params, init, warm_steps, every, store)
+            wt, wcert, w_init, _ = ttt_trace(ctx, S, k_eval, params, init, warm_steps, every, store)
             e = ttt_scan(objective_of, store, warm_steps // every, f_ref, args.ttt_tol, every, wt)
             e["init_seconds"] = round(w_init, 4)
             if r_it is not None:
@@ -431,7 +445,7 @@ def warm_start_study(args):
             }
             for name, init in xinits.items():
                 steps = rand_steps if name == "random" else warm_steps
-                wt, _, w_init = ttt_trace(ctx, Sx, k_eval, params, init, steps, every, store)
+                wt, _, w_init, _ = ttt_trace(ctx, Sx, k_eval, params, init, steps, every, store)
                 e = ttt_scan(objective_of, store, steps // every, f_ref, args.ttt_tol, every, wt)
                 e["init_seconds"] = round(w_init, 4)
                 if r_s is not None and e.get("seconds"):
@@ -772,6 +786,9 @@ def main():
     ap.add_argument("--ttt-variants", default="fp32,bf16,fp8,fp32-softplus")
     ap.add_argument("--ttt-kind", default="abs_corr", choices=["abs_corr", "tpdm"])
     ap.add_argument("--ttt-tol", type=float, default=1e-4)
+    ap.add_argument("--ttt-switch", type=float, default=1e-5,
+                    help="precision ladder (variants 'lo>hi-...'): move to the precise storage at the first check "
+                         "whose stagnation measure (E_{t-delta} - E_t) / E_0 is below this")
     ap.add_argument("--ttt-max", type=int, default=6000)
     ap.add_argument("--ttt-save-every", type=int, default=2)
     ap.add_argument("--ttt-ref-iters", type=int, default=8000)

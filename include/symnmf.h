@@ -290,6 +290,35 @@ symnmf_status symnmf_solve_trace(symnmf_ctx* ctx, const symnmf_S* S, symnmf_stat
                                  int64_t save_every, void* H_save, int64_t slots, double* ms_out,
                                  int64_t* certified_at);
 
+/* Precision ladder (not in the paper, whose discussion of numerical
+ * considerations leaves reduced-precision storage open): the solver iterates
+ * on the rounded problem min ||S_q - H H^T||^2, whose minimiser differs from
+ * that of S by a term of the order of the rounding of S, so on FP8 storage
+ * the objective on S stalls above a tight tolerance.  The ladder iterates on
+ * the low-precision storage while it makes progress and then continues on a
+ * second, more precise storage of the same matrix.
+ *
+ * symnmf_state_rebind: point the state at S (another storage of the matrix
+ * the state was created for: same n, row0, rows and padding; FP64 storage for
+ * an FP64 state only, else EINVAL).  The iterate, the optimiser buffers and
+ * t are kept; the stream launch shape and the image / partial buffers follow
+ * the new storage type (grown when needed; synchronises); the stagnation
+ * reference of the stop rule restarts because E is measured on the stored
+ * matrix.  Later calls must pass S.
+ *
+ * symnmf_solve_trace_ladder: symnmf_solve_trace that starts on S_lo (the
+ * state's storage) and rebinds the state to S_hi at the first check (t a
+ * multiple of delta, t >= warmup) whose stagnation measure
+ * (E_{t-delta} - E_t) / E_0 is below tau_switch (>= 0); *switched_at
+ * (may be NULL) receives that t or -1.  *certified_at only counts
+ * certifications on S_hi.  The state is left bound to the storage of the last
+ * step. */
+symnmf_status symnmf_state_rebind(symnmf_ctx* ctx, symnmf_state* st, const symnmf_S* S);
+symnmf_status symnmf_solve_trace_ladder(symnmf_ctx* ctx, const symnmf_S* S_lo, const symnmf_S* S_hi,
+                                        symnmf_state* st, int64_t steps, int64_t save_every, void* H_save,
+                                        int64_t slots, double* ms_out, double tau_switch, int64_t* certified_at,
+                                        int64_t* switched_at);
+
 /* Subspace error of two factors (solutions are defined up to column
  * permutation and scaling): ||P_A - P_B||_F / sqrt(2k) with P_X the orthogonal
  * projector onto the column span of X, from ||P_A - P_B||_F^2 =

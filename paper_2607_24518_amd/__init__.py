@@ -103,6 +103,10 @@ SIGNATURES = {
                                     ctypes.POINTER(symnmf_stats), c_vp]),
     "symnmf_solve_trace": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i64, c_i64, c_vp, c_i64,
                                    ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
+    "symnmf_state_rebind": (c_i32, [c_vp, c_vp, ctypes.POINTER(symnmf_S)]),
+    "symnmf_solve_trace_ladder": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), ctypes.POINTER(symnmf_S), c_vp, c_i64,
+                                          c_i64, c_vp, c_i64, ctypes.POINTER(c_dbl), c_dbl, ctypes.POINTER(c_i64),
+                                          ctypes.POINTER(c_i64)]),
     "symnmf_subspace_error": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_i64, ctypes.POINTER(c_dbl)]),
     "symnmf_median_sq": (c_i32, [c_vp, c_vp, c_i64, ctypes.POINTER(ctypes.c_float)]),
     "symnmf_piecewise_reset": (c_i32, [c_vp, c_vp, c_dbl, ctypes.POINTER(ctypes.c_float)]),
@@ -339,6 +343,28 @@ def symnmf_solve_trace(ctx, S: Matrix, st: State, steps: int, save_every: int, H
     _check(ctx, lib().symnmf_solve_trace(ctx, ctypes.byref(S.desc), st.handle, steps, save_every, _ptr(H_save),
                                          H_save.shape[0], ms, ctypes.byref(cert)))
     return [ms[i] for i in range(nsave)], cert.value
+
+
+def symnmf_state_rebind(ctx, st: State, S: Matrix):
+    """Point the state at another storage S of its matrix (precision ladder)."""
+    _check(ctx, lib().symnmf_state_rebind(ctx, st.handle, ctypes.byref(S.desc)))
+    st.S = S
+
+
+def symnmf_solve_trace_ladder(ctx, S_lo: Matrix, S_hi: Matrix, st: State, steps: int, save_every: int, H_save,
+                              tau_switch: float):
+    """symnmf_solve_trace starting on S_lo and moving to S_hi at the first check
+    whose stagnation measure is below tau_switch.  Returns (ms per kept
+    iterate, first certified t on S_hi or -1, switch t or -1)."""
+    nsave = steps // save_every
+    ms = (c_dbl * max(nsave, 1))()
+    cert, sw = c_i64(), c_i64()
+    _check(ctx, lib().symnmf_solve_trace_ladder(ctx, ctypes.byref(S_lo.desc), ctypes.byref(S_hi.desc), st.handle,
+                                                steps, save_every, _ptr(H_save), H_save.shape[0], ms, tau_switch,
+                                                ctypes.byref(cert), ctypes.byref(sw)))
+    if sw.value >= 0:
+        st.S = S_hi
+    return [ms[i] for i in range(nsave)], cert.value, sw.value
 
 
 def symnmf_subspace_error(ctx, A, B):

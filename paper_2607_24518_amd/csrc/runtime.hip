@@ -94,6 +94,7 @@ struct symnmf_state {
     int32_t *plan = nullptr, *tiles_I = nullptr, *tiles_J = nullptr, *counts = nullptr;
     void* sel = nullptr;
     void* img[2] = {nullptr, nullptr};   // chunk images of H and 2H (MFMA stream)
+    int64_t img_bytes = 0, part_bytes = 0;   // capacities of img[*] and part
     bool mfma = false;
     bool tall = false;               // full steps run the 8-wave stream kernel
     int32_t P_tall = 0;
@@ -477,12 +478,14 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
         const int64_t iw = h_image_words(S->dtype, k, st->chunks);
         ALLOC(st->img[0], iw * 4);
         if (p->method == SYMNMF_BLOCK_SVRG) ALLOC(st->img[1], iw * 4);
+        st->img_bytes = iw * 4;
     }
     st->tall = stream_tall_supported(S->dtype, h_f64, k) != 0 && std::getenv("SYMNMF_NO_TALL") == nullptr;
     st->P_tall = st->tall ? tall_wgs(ctx->cus, st->tiles) : ctx->cus;
     const int64_t part_tiles = std::max<int64_t>((int64_t)st->P + st->tiles,
                                                  st->tall ? 2 * ((int64_t)st->P_tall + tall_pairs(st->tiles)) : 0);
     ALLOC(st->part, part_tiles * TR * k * st->hsz);
+    st->part_bytes = part_tiles * TR * k * st->hsz;
     ALLOC(st->tile_gram, st->tiles * SUBT * k * k * 8);
     ALLOC(st->tile_tr, st->tiles * SUBT * 8);
     ALLOC(st->tile_kkt, st->tiles * SUBT * 8);
@@ -983,13 +986,73 @@ symnmf_status symnmf_solve_to_tol(symnmf_ctx* ctx, const symnmf_S* S, symnmf_sta
     return SYMNMF_ENOTCONV;
 }
 
-symnmf_status symnmf_solve_trace(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st, int64_t steps,
-                                 int64_t save_every, void* H_save, int64_t slots, double* ms_out,
-                                 int64_t* certified_at) {
+// Point the state at another storage of the same matrix (same n, rows, row0
+// and tiling; FP64 storage only for an FP64 state): the stream launch shape,
+// the image and partial buffers follow the new storage type; the optimiser
+// state, the iterate and t are kept; the stagnation reference restarts, since
+// E changes with the stored matrix.
+static symnmf_status rebind_state(symnmf_state* st, const symnmf_S* S) {
+    symnmf_ctx* ctx = st->ctx;
+    if (S->n != st->n || S->rows != st->rows || S->row0 != st->row0 || S->rows_pad != st->rows_pad ||
+        S->ld / KC != st->chunks)
+        return fail(ctx, SYMNMF_EINVAL, "state_rebind: S has another shape than the state's");
+    if ((S->dtype == SYMNMF_S_FP64) != (st->h_f64 != 0))
+        return fail(ctx, SYMNMF_EINVAL, "state_rebind: FP64 storage goes with an FP64 state only");
+    const int64_t k = st->k;
+    const bool mfma = stream_uses_mfma(S->dtype, st->h_f64, st->h_f64, k) != 0;
+    const int32_t P = ctx->cus * (ctx->wgs_per_cu > 0 ? ctx->wgs_per_cu : stream_wgs_per_cu(S->dtype, k));
+    const bool tall = stream_tall_supported(S->dtype, st->h_f64, k) != 0 && std::getenv("SYMNMF_NO_TALL") == nullptr;
+    const int32_t P_tall = tall ? tall_wgs(ctx->cus, st->tiles) : ctx->cus;
+    const int64_t part_tiles = std::max<int64_t>((int64_t)P + st->tiles,
+                                                 tall ? 2 * ((int64_t)P_tall + tall_pairs(st->tiles)) : 0);
+    const int64_t part_bytes = part_tiles * TR * k * st->hsz;
+    const int64_t img_bytes = mfma ? h_image_words(S->dtype, k, st->chunks) * 4 : 0;
+    HIP_OK(ctx, hipStreamSynchronize(ctx->stream));   // no kernel of the old shape still reads the buffers
+    auto grow = [&](void*& buf, int64_t need) -> symnmf_status {
+        void* fresh = nullptr;
+        symnmf_status s = state_alloc(st, &fresh, need);
+        if (s != SYMNMF_OK) return s;
+        for (auto& q : st->allocs)
+            if (q == buf) {
+                (void)hipFree(q);
+                q = nullptr;
+            }
+        buf = fresh;
+        return SYMNMF_OK;
+    };
+    symnmf_status s = SYMNMF_OK;
+    if (part_bytes > st->part_bytes) {
+        if ((s = grow(st->part, part_bytes)) != SYMNMF_OK) return s;
+        st->part_bytes = part_bytes;
+    }
+    if (img_bytes > st->img_bytes) {
+        if ((s = grow(st->img[0], img_bytes)) != SYMNMF_OK) return s;
+        if (st->p.method == SYMNMF_BLOCK_SVRG && (s = grow(st->img[1], img_bytes)) != SYMNMF_OK) return s;
+        st->img_bytes = img_bytes;
+    }
+    st->S = *S;
+    st->mfma = mfma;
+    st->P = P;
+    st->tall = tall;
+    st->P_tall = P_tall;
+    st->have_prev = false;
+    st->stag_run = 0;
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_state_rebind(symnmf_ctx* ctx, symnmf_state* st, const symnmf_S* S) {
     if (!ctx) return SYMNMF_EINVAL;
-    if (!S || !st || st->ctx != ctx || !H_save || !ms_out || save_every < 1 || steps < 0 || slots < steps / save_every)
-        return fail(ctx, SYMNMF_EINVAL, "solve_trace: bad argument");
-    if (S->data != st->S.data) return fail(ctx, SYMNMF_EINVAL, "solve_trace: S does not match the state");
+    if (!S || !st || st->ctx != ctx) return fail(ctx, SYMNMF_EINVAL, "state_rebind: bad state or context");
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    return rebind_state(st, S);
+}
+
+// The loop of symnmf_solve_trace; with S_hi it starts on S and moves the
+// state to S_hi at the first check whose stagnation measure falls below
+// tau_switch (the precision ladder).
+static symnmf_status trace_impl(symnmf_ctx* ctx, const symnmf_S* S, const symnmf_S* S_hi, double tau_switch,
+                                int64_t* switched_at, symnmf_state* st, int64_t steps, int64_t save_every,
+                                void* H_save, double* ms_out, int64_t* certified_at) {
     const symnmf_params& p = st->p;
     const int64_t nsave = steps / save_every;
     const int64_t hbytes = st->n * st->k * st->hsz;
@@ -1006,10 +1069,12 @@ symnmf_status symnmf_solve_trace(symnmf_ctx* ctx, const symnmf_S* S, symnmf_stat
         return fail(ctx, SYMNMF_EDEVICE, "solve_trace: %s", hipGetErrorString(e));
     }
     if (certified_at) *certified_at = -1;
+    if (switched_at) *switched_at = -1;
+    const symnmf_S* cur = S;
     (void)hipEventRecord(ev[0], ctx->stream);
     symnmf_status s = SYMNMF_OK;
     for (int64_t i = 0; i < nsave * save_every && s == SYMNMF_OK; ++i) {
-        s = do_step(ctx, S, st);
+        s = do_step(ctx, cur, st);
         if (s != SYMNMF_OK) break;
         const int64_t t = st->t - 1;
         if ((i + 1) % save_every == 0) {
@@ -1035,7 +1100,14 @@ symnmf_status symnmf_solve_trace(symnmf_ctx* ctx, const symnmf_S* S, symnmf_stat
         }
         s = check_iteration(st, &sv);
         st->last = sv;
-        if (s == SYMNMF_OK && sv.converged && certified_at && *certified_at < 0) *certified_at = t;
+        const bool low = S_hi && cur != S_hi;
+        // certification counts on the final storage only
+        if (s == SYMNMF_OK && !low && sv.converged && certified_at && *certified_at < 0) *certified_at = t;
+        if (s == SYMNMF_OK && low && sv.t >= p.warmup && !std::isnan(sv.stag) && sv.stag < tau_switch) {
+            s = rebind_state(st, S_hi);
+            cur = S_hi;
+            if (switched_at) *switched_at = t;
+        }
     }
     if (s == SYMNMF_OK) {
         if (hipStreamSynchronize(ctx->stream) != hipSuccess) s = fail(ctx, SYMNMF_EDEVICE, "solve_trace: sync");
@@ -1047,6 +1119,31 @@ symnmf_status symnmf_solve_trace(symnmf_ctx* ctx, const symnmf_S* S, symnmf_stat
     }
     cleanup();
     return s;
+}
+
+symnmf_status symnmf_solve_trace(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* st, int64_t steps,
+                                 int64_t save_every, void* H_save, int64_t slots, double* ms_out,
+                                 int64_t* certified_at) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!S || !st || st->ctx != ctx || !H_save || !ms_out || save_every < 1 || steps < 0 || slots < steps / save_every)
+        return fail(ctx, SYMNMF_EINVAL, "solve_trace: bad argument");
+    if (S->data != st->S.data) return fail(ctx, SYMNMF_EINVAL, "solve_trace: S does not match the state");
+    return trace_impl(ctx, S, nullptr, 0.0, nullptr, st, steps, save_every, H_save, ms_out, certified_at);
+}
+
+symnmf_status symnmf_solve_trace_ladder(symnmf_ctx* ctx, const symnmf_S* S_lo, const symnmf_S* S_hi,
+                                        symnmf_state* st, int64_t steps, int64_t save_every, void* H_save,
+                                        int64_t slots, double* ms_out, double tau_switch, int64_t* certified_at,
+                                        int64_t* switched_at) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!S_lo || !S_hi || !st || st->ctx != ctx || !H_save || !ms_out || save_every < 1 || steps < 0 ||
+        slots < steps / save_every || !(tau_switch >= 0.0))
+        return fail(ctx, SYMNMF_EINVAL, "solve_trace_ladder: bad argument");
+    if (S_lo->data != st->S.data) return fail(ctx, SYMNMF_EINVAL, "solve_trace_ladder: S_lo does not match the state");
+    if (S_hi->n != S_lo->n || S_hi->rows != S_lo->rows || S_hi->row0 != S_lo->row0 || S_hi->ld != S_lo->ld ||
+        S_hi->rows_pad != S_lo->rows_pad || (S_hi->dtype == SYMNMF_S_FP64) != (S_lo->dtype == SYMNMF_S_FP64))
+        return fail(ctx, SYMNMF_EINVAL, "solve_trace_ladder: S_lo and S_hi differ in shape or state precision");
+    return trace_impl(ctx, S_lo, S_hi, tau_switch, switched_at, st, steps, save_every, H_save, ms_out, certified_at);
 }
 
 symnmf_status symnmf_probe_read(symnmf_ctx* ctx, const void* src, void* sink, int64_t sink_words, int64_t bytes) {
