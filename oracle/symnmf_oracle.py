@@ -545,6 +545,20 @@ class Solver:
         self.last_g = None
         self.history = []
 
+    def rebind(self, S):
+        """Precision ladder (not in the paper; a remedy for the rounding of
+        reduced-precision storage): continue the same iteration - iterate,
+        optimiser buffers, t, E_0 - on another storage S of the matrix.  E is
+        measured on the stored matrix, so the stagnation reference (E of the
+        previous check, the Block-SVRG run of stagnating checks) restarts."""
+        S = np.asarray(S, dtype=np.float64)
+        if S.shape != self.S.shape:
+            raise ValueError("rebind: S has another shape")
+        self.S = S
+        self.fro2 = float((S * S).sum())
+        self.E_prev = None
+        self.stag_run = 0
+
     # -- helpers ---------------------------------------------------------
     def _rows_of(self, blocks):
         br = self.p.block_rows

@@ -21,7 +21,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-from gpu_util import ctx, dev, from_dev, to_dev  # noqa: E402
+from gpu_util import ctx, dev, from_dev, stored_numpy, to_dev  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -123,3 +123,31 @@ def test_ladder_ends_below_fp8_alone(stores):
     _, _, sw = sym.symnmf_solve_trace_ladder(c, S8, S32, stl, steps, steps, store, 1e-4)
     fl = sym.symnmf_objective(c, S32, store[0], k)[0]
     assert 0 < sw < steps and fl < f8
+
+
+@pytest.mark.parametrize("lo,hi", [("fp8", "fp32"), ("fp8", "bf16"), ("bf16", "fp32")])
+def test_ladder_matches_the_oracle(lo, hi):
+    """The laddered trace against the FP64 oracle taking the same iteration on
+    the same stored matrices (decoded), moved by Solver.rebind after the
+    switch check: the objective of the final iterate on the precise storage to
+    1e-5 relative (the FP32 bar)."""
+    X = synth.c1_instance(0).X.numpy()
+    c = ctx()
+    S_lo = sym.symnmf_build_S(c, to_dev(X), dtype=sym.DTYPES[lo], fp8_panel_rows=128)
+    S_hi = sym.symnmf_build_S(c, to_dev(X), dtype=sym.DTYPES[hi], fp8_panel_rows=128)
+    A_lo, A_hi = stored_numpy(S_lo), stored_numpy(S_hi)
+    n, k, steps = 512, 8, 100
+    H0 = o.init_H(A_hi.mean(), n, k, 0, as_float32=True)
+    eta = math.sqrt(A_hi.mean() / k)
+    st = sym.symnmf_state_create(c, S_lo, k, sym.symnmf_params_default(eta=eta, max_iter=10 ** 9), to_dev(H0))
+    store = torch.empty(1, n, k, device=dev())
+    _, _, sw = sym.symnmf_solve_trace_ladder(c, S_lo, S_hi, st, steps, steps, store, 1.0)
+    assert sw == 50
+    solver = o.Solver(A_lo, k, o.Params(eta=eta), H0.astype(np.float64))
+    for t in range(steps):
+        if t == sw + 1:
+            solver.rebind(A_hi)
+        solver.step()
+    f_gpu = o.objective_trace(A_hi, from_dev(store[0]).astype(np.float64))
+    f_orc = o.objective_trace(A_hi, solver.H)
+    assert abs(f_gpu - f_orc) / f_orc <= 1e-5

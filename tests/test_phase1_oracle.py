@@ -143,3 +143,41 @@ def test_softplus_forms_keep_h_positive():
         assert np.all(sol.H > 0) and st.f < o.objective_trace(S, H0)
     with pytest.raises(ValueError):
         o.Solver(S, 3, o.Params(method=o.MU, softplus=True), H0)
+
+
+def test_rebind_keeps_the_iteration_and_moves_it_to_the_new_matrix():
+    """The precision ladder's move (Solver.rebind): onto a copy of S it changes
+    nothing; onto another matrix S2 the next step is the AdaGrad rule with the
+    carried accumulator and the gradient of S2, E is measured on S2, and the
+    stagnation reference restarts (the first check after the move has none)."""
+    inst = synth.c1_instance(2, T=600, n=120, groups=3)
+    S = o.abs_corr(inst.X.double().numpy())
+    rng = np.random.default_rng(4)
+    S2 = S + 0.01 * np.abs(rng.standard_normal(S.shape))
+    S2 = 0.5 * (S2 + S2.T)
+    k = 3
+    H0 = o.init_H(S.mean(), 120, k, 2)
+    p = o.Params(eta=math.sqrt(S.mean() / k))
+    a, b = o.Solver(S, k, p, H0), o.Solver(S, k, p, H0)
+    for _ in range(20):
+        a.step()
+        b.step()
+    a.rebind(S.copy())
+    for _ in range(20):
+        a.step()
+        b.step()
+    assert np.array_equal(a.H, b.H) and a.E0 == b.E0
+    c = o.Solver(S, k, p, H0)
+    for _ in range(20):
+        c.step()
+    H20, G20 = c.H.copy(), c.G.copy()
+    c.E_prev = 0.3                                    # as if a check had run
+    c.rebind(S2)
+    assert c.E_prev is None and c.fro2 == pytest.approx(float((S2 * S2).sum()), rel=1e-15)
+    st = c.step()
+    g = 4.0 * (H20 @ (H20.T @ H20) - S2 @ H20)
+    H_exp, _ = o.adagrad_update(H20, G20, g, p.eta, p.eps)
+    assert np.allclose(c.H, H_exp, rtol=1e-13, atol=1e-15)
+    assert st.E == pytest.approx(float(((S2 - H20 @ H20.T) ** 2).sum()) / float((S2 * S2).sum()), rel=1e-10)
+    with pytest.raises(ValueError):
+        c.rebind(S2[:10, :10])
