@@ -340,6 +340,8 @@ inline int64_t syrk_grid(int64_t n_ti, int64_t n_tj) {
     return (blocks + 7) / 8 * 8 * 64;
 }
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 // A full square S (no row panel) is symmetric, so the S-building GEMMs
 // compute only the 128 x 128 tiles with ti <= tj; the work-group of an
 // off-diagonal tile also stores its transpose.  The transposed value is
