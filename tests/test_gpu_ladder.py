@@ -61,6 +61,24 @@ def test_rebind_before_the_first_step_equals_a_fresh_state(stores, src, dst, k):
     assert np.array_equal(H_a, H_b)
 
 
+@pytest.mark.parametrize("src,dst", [("fp32", "fp8"), ("fp8", "fp32")])
+def test_rebind_block_svrg_equals_a_fresh_state(stores, src, dst):
+    """Block-SVRG keeps a second image (of 2H for the doubly covered blocks):
+    both images follow the storage type, sampled steps included."""
+    c = ctx()
+    n, k = stores["fp32"].desc.n, 32
+    kw = dict(method=sym.BLOCK_SVRG, block_rows=256, snapshot_s=5, delta=10, phi0=0.5)
+    H0 = torch.empty(n, k, device=dev())
+    sym.symnmf_init_H(c, stores["fp32"], k, 7, H0)
+    fresh = sym.symnmf_state_create(c, stores[dst], k, _params(stores["fp32"], k, **kw), H0)
+    moved = sym.symnmf_state_create(c, stores[src], k, _params(stores["fp32"], k, **kw), H0)
+    sym.symnmf_state_rebind(c, moved, stores[dst])
+    f_a, H_a = _run(c, stores[dst], fresh, 23)
+    f_b, H_b = _run(c, stores[dst], moved, 23)
+    assert [x == y or (math.isnan(x) and math.isnan(y)) for x, y in zip(f_a, f_b)] == [True] * 23
+    assert np.array_equal(H_a, H_b)
+
+
 def test_rebind_rejects_another_matrix_or_precision(stores):
     c = ctx()
     X = synth.c1_instance(1, T=500, n=400, groups=4).X.numpy()
