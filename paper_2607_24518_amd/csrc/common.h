@@ -307,6 +307,8 @@ struct UpdateArgs {
     double cgrad;         // 4 (full / row steps) or 2 (block steps)
     int32_t store_mu;     // full SVRG step: mu <- g
     int32_t fp8;          // FP8 storage: scale partials, add the diagonal back
+    int32_t block_step;   // Block-SVRG sampled step: the diagonal term S_ii h_i carries the
+                          // weight of column i's chunk for the row's class (0, 0, 2)
     const float* panel_scale;
     const float* diag;    // FP8: S_ii of every panel row
     int64_t panel_rows;

@@ -113,8 +113,14 @@ __global__ __launch_bounds__(UT, sizeof(HT) == 4 ? 7 : 1) void update_kernel(Upd
             if (act >= 0) {
                 for (int64_t w = w_lo; w <= w_hi; ++w)
                     sh += part[((slot_mul * w + slot_base) * TR + r0 + r) * (int64_t)k + c];
-                if (a.fp8)   // codes carry S * scale off the diagonal; S_ii is kept exactly
-                    sh = sh / (HT)a.panel_scale[prow / a.panel_rows] + (HT)a.diag[prow] * h;
+                if (a.fp8) {   // codes carry S * scale off the diagonal; S_ii is kept exactly
+                    // and enters with the weight the plan gives column i of this row:
+                    // 1 on full and row-sampled steps; on a block step 0 for rows in I
+                    // only or J only (their own block is not among the streamed
+                    // chunks) and 2 for rows in both sets
+                    const HT dw = (p.full || !a.block_step) ? (HT)1 : (cls == 2 ? (HT)2 : (HT)0);
+                    sh = sh / (HT)a.panel_scale[prow / a.panel_rows] + dw * (HT)a.diag[prow] * h;
+                }
                 if (full_k) {
                     hg = hgv[jj < NJ ? jj : 0];
                 } else {

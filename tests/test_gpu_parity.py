@@ -359,22 +359,32 @@ def test_svrg_trajectories_fp64(method, extra):
     assert np.max(np.abs(H - solver.H)) < 1e-9
 
 
-@pytest.mark.parametrize("dtype,k", [("fp32", 16), ("fp32", 32), ("bf16", 32)])
-def test_block_svrg_mfma_path(dtype, k):
+@pytest.mark.parametrize("dtype,k,indep", [("fp32", 16, 1), ("fp32", 32, 1), ("bf16", 32, 1), ("bf16", 32, 0),
+                                           ("fp8", 32, 1), ("fp8", 32, 0), ("fp8", 16, 1)])
+def test_block_svrg_mfma_path(dtype, k, indep):
+    """Sampled Block-SVRG steps on every storage type, independent I and J or
+    I = J.  On FP8 storage the diagonal is kept apart from the codes, so the
+    update has to give S_ii h_i the weight of column i in the row's block
+    gradient: 0 for rows in I only or J only, 2 for rows in both (every
+    sampled row when I = J)."""
     X = _corr_instance(n=1300, T=600, groups=8, seed=2)
     Snp = o.abs_corr(X)
     H0 = o.init_H(Snp.mean(), 1300, k, 3, as_float32=True)
     eta = 0.5 * math.sqrt(Snp.mean() / k)
     p = sym.symnmf_params_default(method=sym.BLOCK_SVRG, eta=eta, block_rows=256, snapshot_s=4, delta=8, seed=5,
-                                  phi0=0.5)
+                                  phi0=0.5, independent_blocks=indep)
     c = ctx()
-    S = sym.symnmf_S_load(c, to_dev(Snp, torch.float64), dtype=sym.DTYPES[dtype])
+    S = sym.symnmf_S_load(c, to_dev(Snp, torch.float64), dtype=sym.DTYPES[dtype], fp8_panel_rows=128)
     Sq = stored_numpy(S)
     hist, H, _ = _run_gpu(S, k, p, H0, 6)
-    op = o.Params(method=o.BLOCK_SVRG, eta=eta, block_rows=256, snapshot_s=4, delta=8, seed=5, phi0=0.5)
+    op = o.Params(method=o.BLOCK_SVRG, eta=eta, block_rows=256, snapshot_s=4, delta=8, seed=5, phi0=0.5,
+                  independent_blocks=bool(indep))
     solver = o.Solver(Sq, k, op, H0)
+    kinds = []
     for _ in range(6):
+        kinds.append(solver.step_kind())
         solver.step()
+    assert kinds.count("block") >= 3
     assert np.max(np.abs(H - solver.H)) < 2e-4 * np.max(np.abs(solver.H))
 
 
@@ -469,24 +479,6 @@ def test_piecewise_reset_matches_formula(S600):
     Gn = torch.empty(600, 16, dtype=torch.float64, device=dev())
     sym.symnmf_state_read(ctx(), st, 2, Gn)
     assert np.max(np.abs(from_dev(Gn) - o.piecewise_reset(g, 10.0))) <= 1e-12 * np.max(np.abs(from_dev(Gn)))
-
-
-def test_piecewise_solve_decisions_match_oracle():
-    X = _corr_instance(n=300, T=400, groups=3, seed=4)
-    Snp = o.abs_corr(X)
-    k = 3
-    H0 = o.init_H(Snp.mean(), 300, k, 1)
-    eta = 0.3 * math.sqrt(Snp.mean() / k)
-    p = sym.symnmf_params_default(method=sym.PIECEWISE_ADAGRAD, eta=eta, max_iter=600, c=10.0, c_r=10.0)
-    c = ctx()
-    S = sym.symnmf_S_load(c, to_dev(Snp, torch.float64), dtype=sym.S_FP64)
-    st = sym.symnmf_state_create(c, S, k, p, to_dev(H0, torch.float64))
-    H = torch.empty(300, k, dtype=torch.float64, device=dev())
-    stats, conv = sym.symnmf_solve_to_tol(c, S, st, H_out=H)
-    solver = o.Solver(Snp, k, o.Params(method=o.PIECEWISE_ADAGRAD, eta=eta, max_iter=600), H0)
-    Ho, ost = solver.solve()
-    assert stats.t == ost.t and bool(conv) == ost.converged
-    assert np.max(np.abs(from_dev(H) - Ho)) < 1e-8
 
 
 def test_solve_to_tol_certifies_planted_factorisation():
