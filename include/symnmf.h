@@ -165,7 +165,8 @@ typedef struct {
     double E;                /* f / ||S_stored||_F^2                              */
     double kkt;              /* ||grad_proj f(H_t)||_F / (n k) (eq. kkt_stop)     */
     double stag;             /* (E_{t-delta} - E_t) / E_0 at checks, else NaN     */
-    double phi;              /* Block-SVRG coverage used by this step             */
+    double phi;              /* Block-SVRG coverage when the step ran (1 for other  */
+                             /*   methods; a snapshot step also reports it)       */
     double wall_ms;          /* host wall time since the state was created        */
     int32_t full;            /* 1: the step read all of S                         */
     int32_t reset_fired;     /* Piecewise reset applied after this step           */
@@ -258,6 +259,30 @@ symnmf_status symnmf_state_read(symnmf_ctx* ctx, symnmf_state* st, int32_t which
 symnmf_status symnmf_state_stats(symnmf_ctx* ctx, symnmf_state* st, symnmf_stats* out);
 /* Block-SVRG coverage phi (0 < phi <= 1). */
 symnmf_status symnmf_state_set_phi(symnmf_state* st, double phi);
+
+/* Control state of the check-time rules (appendix "Detailed Algorithm
+ * Descriptions": Piecewise AdaGrad's accumulator resets, Block-SVRG
+ * AdaptGrow's coverage growth), as left by the last check. */
+typedef struct {
+    int64_t t;               /* iterations taken                                   */
+    double phi;              /* Block-SVRG coverage of the next sampled step       */
+    int64_t stag_run;        /* consecutive stagnating checks counted for growth   */
+    int64_t pw_resets;       /* Piecewise resets applied so far                    */
+    int32_t pw_enabled;      /* 0 once a reset was refused for lack of progress     */
+    int32_t pw_cooling;      /* 1 after a reset: stagnation waits for sum(G) to     */
+                             /*   reach pw_cool_target                             */
+    double pw_cool_target;   /* twice sum(G) right after the last reset            */
+    double pw_E_reset;       /* E at the last reset                                */
+} symnmf_control;
+/* Host copy of the control state (no device work). */
+symnmf_status symnmf_state_control(symnmf_ctx* ctx, symnmf_state* st, symnmf_control* out);
+/* Statistics of the check iterations (t = 0 mod delta) evaluated so far by
+ * symnmf_solve_to_tol, symnmf_solve_trace or the ladder, in order, with the
+ * decisions taken at each (stag, reset_fired, converged, and phi, the coverage
+ * the checked step used).  Copies min(count, cap) records to ``out`` (host)
+ * and the number of records to *count.  No device work. */
+symnmf_status symnmf_state_checks(symnmf_ctx* ctx, symnmf_state* st, symnmf_stats* out, int64_t cap,
+                                  int64_t* count);
 
 /* f(H) and E = f/||S_stored||^2 for any H (device n x k, float32 or float64),
  * the measure every result is compared by.  S H is accumulated in FP64: for FP32/BF16/FP8 storage

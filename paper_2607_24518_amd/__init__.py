@@ -56,6 +56,14 @@ class symnmf_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class symnmf_control(ctypes.Structure):
+    _fields_ = [("t", c_i64), ("phi", c_dbl), ("stag_run", c_i64), ("pw_resets", c_i64), ("pw_enabled", c_i32),
+                ("pw_cooling", c_i32), ("pw_cool_target", c_dbl), ("pw_E_reset", c_dbl)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class symnmf_kmeans_stats(ctypes.Structure):
     _fields_ = [("iters", c_i64), ("J0", c_dbl), ("J", c_dbl), ("wall_ms", c_dbl), ("changed", c_i64),
                 ("converged", c_i32), ("empty", c_i32)]
@@ -97,6 +105,8 @@ SIGNATURES = {
     "symnmf_state_read": (c_i32, [c_vp, c_vp, c_i32, c_vp]),
     "symnmf_state_stats": (c_i32, [c_vp, c_vp, ctypes.POINTER(symnmf_stats)]),
     "symnmf_state_set_phi": (c_i32, [c_vp, c_dbl]),
+    "symnmf_state_control": (c_i32, [c_vp, c_vp, ctypes.POINTER(symnmf_control)]),
+    "symnmf_state_checks": (c_i32, [c_vp, c_vp, ctypes.POINTER(symnmf_stats), c_i64, ctypes.POINTER(c_i64)]),
     "symnmf_objective": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_i32, c_i64, ctypes.POINTER(c_dbl),
                                  ctypes.POINTER(c_dbl)]),
     "symnmf_solve_to_tol": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_vp, c_dbl, c_dbl,
@@ -314,6 +324,21 @@ def symnmf_state_set_phi(st: State, phi: float):
     code = lib().symnmf_state_set_phi(st.handle, phi)
     if code != OK:
         raise SymnmfError(code, "bad phi")
+
+
+def symnmf_state_control(ctx, st: State) -> symnmf_control:
+    out = symnmf_control()
+    _check(ctx, lib().symnmf_state_control(ctx, st.handle, ctypes.byref(out)))
+    return out
+
+
+def symnmf_state_checks(ctx, st: State):
+    """List of the stats of every check iteration evaluated so far."""
+    count = c_i64()
+    _check(ctx, lib().symnmf_state_checks(ctx, st.handle, None, 0, ctypes.byref(count)))
+    arr = (symnmf_stats * max(count.value, 1))()
+    _check(ctx, lib().symnmf_state_checks(ctx, st.handle, arr, count.value, ctypes.byref(count)))
+    return [arr[i] for i in range(count.value)]
 
 
 def symnmf_objective(ctx, S: Matrix, H, k: int):

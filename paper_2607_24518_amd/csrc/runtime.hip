@@ -110,13 +110,14 @@ struct symnmf_state {
     bool pw_enabled = true, pw_cool = false;
     double pw_cool_target = 0.0, pw_E_reset = 0.0;
     int64_t pw_resets = 0;
+    std::vector<symnmf_stats> checks;   // statistics of every check iteration evaluated so far
     std::chrono::steady_clock::time_point t0;
     symnmf_stats last{};
 };
 
 extern "C" {
 
-int32_t symnmf_abi_version(void) { return 3; }
+int32_t symnmf_abi_version(void) { return 4; }
 
 void symnmf_params_default(symnmf_params* p) {
     std::memset(p, 0, sizeof(*p));
@@ -611,6 +612,7 @@ static symnmf_status do_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* s
     a.cgrad = kind == 2 ? 2.0 : 4.0;
     a.store_mu = (kind == 0 && st->Mu) ? 1 : 0;
     a.fp8 = S->dtype == SYMNMF_S_FP8;
+    a.block_step = kind == 2 ? 1 : 0;
     a.panel_scale = S->panel_scale;
     a.diag = S->diag;
     a.panel_rows = S->fp8_panel_rows > 0 ? S->fp8_panel_rows : 1;
@@ -634,7 +636,7 @@ static symnmf_status do_step(symnmf_ctx* ctx, const symnmf_S* S, symnmf_state* s
                                 st->gram_fixed, st->gram64[st->cur], st->gram64[1 - st->cur], st->gram_eff, st->h_f64,
                                 st->ring + slot * 4, sm));
     st->ring_full[slot] = kind == 0;
-    st->ring_phi[slot] = kind == 2 ? st->phi : 1.0;
+    st->ring_phi[slot] = st->phi;
     st->cur = 1 - st->cur;
     st->t = t + 1;
     return SYMNMF_OK;
@@ -925,6 +927,7 @@ static symnmf_status check_iteration(symnmf_state* st, symnmf_stats* sv) {
     }
     st->E_prev = sv->E;
     st->have_prev = true;
+    st->checks.push_back(*sv);
     return SYMNMF_OK;
 }
 
@@ -1037,6 +1040,31 @@ static symnmf_status rebind_state(symnmf_state* st, const symnmf_S* S) {
     st->P_tall = P_tall;
     st->have_prev = false;
     st->stag_run = 0;
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_state_checks(symnmf_ctx* ctx, symnmf_state* st, symnmf_stats* out, int64_t cap,
+                                  int64_t* count) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!st || !count || (cap > 0 && !out) || cap < 0) return fail(ctx, SYMNMF_EINVAL, "state_checks: bad argument");
+    const int64_t m = (int64_t)st->checks.size();
+    *count = m;
+    for (int64_t i = 0; i < std::min(m, cap); ++i) out[i] = st->checks[i];
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_state_control(symnmf_ctx* ctx, symnmf_state* st, symnmf_control* out) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!st || !out) return fail(ctx, SYMNMF_EINVAL, "state_control: null argument");
+    std::memset(out, 0, sizeof(*out));
+    out->t = st->t;
+    out->phi = st->phi;
+    out->stag_run = st->stag_run;
+    out->pw_resets = st->pw_resets;
+    out->pw_enabled = st->pw_enabled ? 1 : 0;
+    out->pw_cooling = st->pw_cool ? 1 : 0;
+    out->pw_cool_target = st->pw_cool_target;
+    out->pw_E_reset = st->pw_E_reset;
     return SYMNMF_OK;
 }
 

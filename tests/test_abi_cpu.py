@@ -52,7 +52,8 @@ def test_struct_sizes_match_header_layout(binding):
     assert ctypes.sizeof(binding.symnmf_S) == 8 * 3 + 8 * 6 + 4 * 2 + 8 * 4
     assert ctypes.sizeof(binding.symnmf_stats) == 8 * 7 + 4 * 4
     assert ctypes.sizeof(binding.symnmf_params) == 8 + 8 * 10 + 8 * 3 + 8 + 8 * 3 + 8 * 4 + 8 + 8 + 8 * 3
-    assert binding.symnmf_abi_version() == 3
+    assert ctypes.sizeof(binding.symnmf_control) == 8 * 4 + 4 * 2 + 8 * 2
+    assert binding.symnmf_abi_version() == 4
 
 
 def test_kmeans_seed_rows_are_bit_identical_to_the_oracle(binding):

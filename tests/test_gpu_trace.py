@@ -1,7 +1,7 @@
 """symnmf_solve_trace against the other entry points: the kept iterates are the
 ones symnmf_solve_to_tol reaches with the same rules (Piecewise resets and
-Block-SVRG growth included), bit for bit, and the stop-rule certification
-time agrees with the oracle's."""
+Block-SVRG growth included, and asserted to happen), bit for bit, and the
+stop-rule certification time agrees with the oracle's."""
 import math
 
 import numpy as np
@@ -27,10 +27,14 @@ def c1():
 
 @pytest.mark.parametrize("method", [sym.ADAGRAD, sym.PIECEWISE_ADAGRAD, sym.BLOCK_SVRG])
 def test_trace_iterates_equal_solve_to_tol(c1, method):
+    """tau_g_inf = 1e-12 keeps the stop rule from certifying (no early stop),
+    tau_stag = 1e-4 lets stagnation be detected: a Piecewise reset fires
+    (near t = 80, then resets switch off) and Block-SVRG grows phi from 0.25
+    to 1 (near t = 150 and 190) inside the 300 traced iterations."""
     c, S = c1
     n, k = 512, 8
     eta = math.sqrt(S.desc.mean / k)
-    kw = dict(method=method, eta=eta, tau_g_inf=1e-12, tau_stag=0.0)   # no early stop
+    kw = dict(method=method, eta=eta, tau_g_inf=1e-12, tau_stag=1e-4)
     if method == sym.BLOCK_SVRG:
         kw.update(block_rows=256, snapshot_s=10, delta=10, phi0=0.25)
     H0 = torch.empty(n, k, device=dev())
@@ -40,6 +44,12 @@ def test_trace_iterates_equal_solve_to_tol(c1, method):
     st = sym.symnmf_state_create(c, S, k, sym.symnmf_params_default(max_iter=10 ** 9, **kw), H0)
     ms, cert = sym.symnmf_solve_trace(c, S, st, steps, every, store)
     assert len(ms) == steps // every and all(b >= a for a, b in zip(ms, ms[1:]))
+    ctl = sym.symnmf_state_control(c, st)
+    if method == sym.PIECEWISE_ADAGRAD:
+        assert ctl.pw_resets >= 1
+        assert any(x.reset_fired for x in sym.symnmf_state_checks(c, st))
+    if method == sym.BLOCK_SVRG:
+        assert ctl.phi == 1.0
     for j in (0, 4, 9):
         t = (j + 1) * every
         st2 = sym.symnmf_state_create(c, S, k, sym.symnmf_params_default(max_iter=t, **kw), H0)

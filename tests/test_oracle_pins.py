@@ -337,19 +337,6 @@ def test_lower_median_and_reset_formula():
     assert o.lower_median(x) == np.sort(x)[500] == np.median(x)
 
 
-def test_piecewise_equals_adagrad_before_first_reset():
-    S, H0 = _c1_small()
-    pa = o.Params(eta=0.05, max_iter=200)
-    pp = o.Params(method=o.PIECEWISE_ADAGRAD, eta=0.05, max_iter=200)
-    a, b = o.Solver(S, 4, pa, H0), o.Solver(S, 4, pp, H0)
-    a.solve(max_iter=200)
-    b.solve(max_iter=200)
-    first = next((h.t for h in b.history if h.reset_fired), None)
-    upto = 200 if first is None else first
-    for x, y in zip(a.history[:upto + 1], b.history[:upto + 1]):
-        assert x.f == y.f
-
-
 def test_row_svrg_full_fraction_equals_adagrad():
     S, H0 = _c1_small()
     pa = o.Params(eta=0.05)
