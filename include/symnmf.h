@@ -358,6 +358,18 @@ symnmf_status symnmf_subspace_error(symnmf_ctx* ctx, const float* A, const float
  * Synchronises; the result goes to *out. */
 symnmf_status symnmf_median_sq(symnmf_ctx* ctx, const float* g, int64_t m, float* out);
 
+/* The same lower median of g_i^2 for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): no allocation, no synchronisation.  The result goes to
+ * out_dev[0] (device, one double holding the float32 value) on the context's
+ * stream.  Working memory is a fixed 4096-byte array of the library on each
+ * GPU (held until the process ends), cleared by the call's own kernels, so
+ * calls that overlap on one GPU (several streams or threads) race on it and
+ * must be serialised by the caller.  m <= 2^32 - 1 (32-bit histogram counts),
+ * else EINVAL; EDEVICE if the array's address could not be found on this
+ * device when the context was created. */
+symnmf_status symnmf_median_sq_noalloc(symnmf_ctx* ctx, const float* g, int64_t m, double* out_dev);
+
 /* Piecewise AdaGrad accumulator recalibration G_i <- max(c g_i^2, c median(g^2))
  * with g the gradient of the state's last step (appendix, Piecewise AdaGrad).
  * Synchronises; *median_out (may be NULL) receives median(g^2). */

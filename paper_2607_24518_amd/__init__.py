@@ -119,6 +119,7 @@ SIGNATURES = {
                                           ctypes.POINTER(c_i64)]),
     "symnmf_subspace_error": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_i64, ctypes.POINTER(c_dbl)]),
     "symnmf_median_sq": (c_i32, [c_vp, c_vp, c_i64, ctypes.POINTER(ctypes.c_float)]),
+    "symnmf_median_sq_noalloc": (c_i32, [c_vp, c_vp, c_i64, c_vp]),
     "symnmf_piecewise_reset": (c_i32, [c_vp, c_vp, c_dbl, ctypes.POINTER(ctypes.c_float)]),
     "symnmf_sample_blocks": (None, [c_u64, c_i64, c_i32, c_i64, c_i64, ctypes.POINTER(c_i32)]),
     "symnmf_selfcheck_fp8": (c_i32, [c_vp]),
@@ -404,6 +405,13 @@ def symnmf_median_sq(ctx, g, m=None):
     m = g.numel() if m is None else m
     _check(ctx, lib().symnmf_median_sq(ctx, _ptr(g), m, ctypes.byref(out)))
     return out.value
+
+
+def symnmf_median_sq_noalloc(ctx, g, out_dev, m=None):
+    """out_dev: device float64 tensor (first element receives the median); nothing waits."""
+    m = g.numel() if m is None else m
+    _check(ctx, lib().symnmf_median_sq_noalloc(ctx, _ptr(g), m, _ptr(out_dev)))
+    return out_dev
 
 
 def symnmf_piecewise_reset(ctx, st: State, c: float):

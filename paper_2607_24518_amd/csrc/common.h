@@ -364,8 +364,18 @@ hipError_t launch_piecewise_apply(void* G, const void* g, int h_f64, int64_t m, 
 // non-negative values).  The value goes to out_dev[0] (double).  tmp: device
 // scratch of select_tmp_bytes().
 int64_t select_tmp_bytes();
+// the histogram counters are 32-bit: at most 2^32 - 1 values per selection
+constexpr int64_t SELECT_MAX_M = 0xffffffffll;
 hipError_t launch_select(const void* x, int x_f64, int square, int64_t m, int64_t rank, void* tmp,
                          double* out_dev, hipStream_t stream);
+
+// Allocation-free entry points: the device address of the file-scope scratch
+// array of select.hip on ``device``.  noalloc_scratch_init (device current)
+// looks it up once per device; noalloc_scratch returns it (null and *err set
+// when the lookup failed or was never made).
+constexpr int64_t NOALLOC_SCRATCH_BYTES = 4096;
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch(int device, hipError_t* err);
 
 // build_s.hip
 struct BuildOut {

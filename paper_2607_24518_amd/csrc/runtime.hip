@@ -166,6 +166,9 @@ symnmf_status symnmf_create(symnmf_ctx** out, int32_t device, void* hip_stream) 
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->cus = prop.multiProcessorCount;
+    // device address of the allocation-free entry points' scratch array (looked
+    // up once per device; a failure is reported by those entry points)
+    (void)noalloc_scratch_init(device);
     if (const char* e = std::getenv("SYMNMF_WGS_PER_CU")) {
         const int v = std::atoi(e);
         if (v >= 1 && v <= 16) ctx->wgs_per_cu = v;
@@ -830,6 +833,22 @@ symnmf_status symnmf_median_sq(symnmf_ctx* ctx, const float* g, int64_t m, float
     if (res) (void)hipFree(res);
     if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "median_sq: %s", hipGetErrorString(e));
     *out = (float)v;
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_median_sq_noalloc(symnmf_ctx* ctx, const float* g, int64_t m, double* out_dev) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!g || !out_dev || m < 1) return fail(ctx, SYMNMF_EINVAL, "median_sq_noalloc: bad argument");
+    if (m > SELECT_MAX_M)
+        return fail(ctx, SYMNMF_EINVAL, "median_sq_noalloc: m = %lld exceeds the maximum of %lld values",
+                    (long long)m, (long long)SELECT_MAX_M);
+    hipError_t e = hipSuccess;
+    void* scr = noalloc_scratch(ctx->device, &e);
+    if (!scr)
+        return fail(ctx, SYMNMF_EDEVICE, "median_sq_noalloc: no scratch address on device %d: %s", ctx->device,
+                    hipGetErrorString(e));
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    HIP_OK(ctx, launch_select(g, 0, 1, m, (m - 1) / 2, scr, out_dev, ctx->stream));
     return SYMNMF_OK;
 }
 

@@ -6,6 +6,8 @@
 // Pass d (8 bits per pass, from the top) histograms the digit of the keys that
 // match the prefix fixed so far, then one thread walks the histogram to the
 // bin holding the target rank, extends the prefix and rebases the rank.
+#include <mutex>
+
 #include "common.h"
 
 namespace symnmf {
@@ -98,9 +100,51 @@ static hipError_t run_select(const T* x, int square, int64_t m, int64_t rank, Se
 
 hipError_t launch_select(const void* x, int x_f64, int square, int64_t m, int64_t rank, void* tmp,
                          double* out_dev, hipStream_t stream) {
-    if (m < 1 || rank < 0 || rank >= m) return hipErrorInvalidValue;
+    if (m < 1 || m > SELECT_MAX_M || rank < 0 || rank >= m) return hipErrorInvalidValue;
     if (x_f64) return run_select<double>((const double*)x, square, m, rank, (SelState*)tmp, out_dev, stream);
     return run_select<float>((const float*)x, square, m, rank, (SelState*)tmp, out_dev, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free median entry point (symnmf_median_sq_noalloc):
+// a file-scope device array, one copy per GPU, kept until the process ends.
+// In host code the symbol names a host-side stand-in, not device memory, so
+// the host never passes it to a kernel: it uses the device address that
+// hipGetSymbolAddress returns, fetched once per device (with that device
+// current) when the first context on the device is created.
+// ---------------------------------------------------------------------------
+static_assert(sizeof(SelState) <= NOALLOC_SCRATCH_BYTES, "selection state must fit the scratch array");
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[MAX_DEVICES] = {};
+void* g_scratch_ptr[MAX_DEVICES] = {};
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_err[device] = e;
+        g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+        g_scratch_done[device] = true;
+    }
+    return g_scratch_err[device];
+}
+
+void* noalloc_scratch(int device, hipError_t* err) {
+    if (device < 0 || device >= MAX_DEVICES) {
+        if (err) *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (err) *err = g_scratch_done[device] ? g_scratch_err[device] : hipErrorNotInitialized;
+    return g_scratch_ptr[device];
 }
 
 }  // namespace symnmf
