@@ -119,6 +119,60 @@ def abs_corr_panel(Z, row0: int, rows: int):
     return P
 
 
+class StoredRows:
+    """A dense S too large for FP64 host memory (n = 10^5: 80 GB), held as
+    float32 - every entry rounded once from its FP64 value - and used with
+    FP64 arithmetic only: S @ H converts one slab of rows at a time to FP64
+    and multiplies it by the FP64 H (a library matmul), so the product is the
+    FP64 product of the stored entries.  ||S||_F^2 and the mean are FP64 sums
+    of the stored entries.  A solver run on a StoredRows solves the problem
+    of the float32-rounded matrix exactly in FP64 (the rounding moves S by at
+    most 2^-24 relative per entry)."""
+
+    SLAB = 128
+
+    def __init__(self, data32):
+        self.data = data32
+        self.shape = data32.shape
+        self.fro2 = 0.0
+        self.sum = 0.0
+        for r0 in range(0, self.shape[0], 4096):
+            blk = self.data[r0:r0 + 4096].astype(np.float64)
+            self.fro2 += float((blk * blk).sum())
+            self.sum += float(blk.sum())
+
+    @classmethod
+    def abs_corr(cls, X, panel_rows: int = 1024):
+        """|corr| of the columns of X (same definition as abs_corr), built
+        row panel by row panel from the standardised columns in FP64."""
+        Z = standardise_columns(X)
+        n = Z.shape[1]
+        data = np.empty((n, n), dtype=np.float32)
+        for r0 in range(0, n, panel_rows):
+            rows = min(panel_rows, n - r0)
+            data[r0:r0 + rows] = abs_corr_panel(Z, r0, rows)
+        return cls(data)
+
+    def mean(self):
+        return self.sum / (self.shape[0] * self.shape[1])
+
+    def rows(self, r0: int, r1: int):
+        return self.data[r0:r1].astype(np.float64)
+
+    def __matmul__(self, H):
+        from concurrent.futures import ThreadPoolExecutor
+        from threadpoolctl import threadpool_limits
+        H = np.asarray(H, dtype=np.float64)
+        out = np.empty((self.shape[0], H.shape[1]))
+
+        def slab(r0):
+            out[r0:r0 + self.SLAB] = self.data[r0:r0 + self.SLAB].astype(np.float64) @ H
+
+        with threadpool_limits(1), ThreadPoolExecutor() as ex:
+            list(ex.map(slab, range(0, self.shape[0], self.SLAB)))
+        return out
+
+
 def gradient_panel(S_panel, H, row0: int):
     """Rows [row0, row0+rows) of grad f = 4 (H (H^T H) - S H) from the
     matching row panel of S and the full H."""
@@ -282,10 +336,14 @@ def objective_explicit(S, H):
 
 def objective_trace(S, H, SH=None):
     """f(H) = ||S||_F^2 - 2 tr(H^T S H) + ||H^T H||_F^2 (eq. trace_loss)."""
-    S = np.asarray(S, dtype=np.float64)
+    if isinstance(S, StoredRows):
+        fro2 = S.fro2
+    else:
+        S = np.asarray(S, dtype=np.float64)
+        fro2 = float((S * S).sum())
     SH = S @ H if SH is None else SH
     G = H.T @ H
-    return float((S * S).sum() - 2.0 * (H * SH).sum() + (G * G).sum())
+    return float(fro2 - 2.0 * (H * SH).sum() + (G * G).sum())
 
 
 def gradient(S, H, SH=None):
@@ -514,11 +572,15 @@ class Solver:
     """
 
     def __init__(self, S, k: int, params: Params, H0):
-        self.S = np.asarray(S, dtype=np.float64)
+        if isinstance(S, StoredRows):       # full steps only (S @ H); see StoredRows
+            self.S = S
+            self.fro2 = S.fro2
+        else:
+            self.S = np.asarray(S, dtype=np.float64)
+            self.fro2 = float((self.S * self.S).sum())
         self.n = self.S.shape[0]
         self.k = k
         self.p = params
-        self.fro2 = float((self.S * self.S).sum())
         self.H = np.array(H0, dtype=np.float64).reshape(self.n, k)
         self.theta = softplus_inverse(self.H) if params.softplus else None
         if params.softplus:

@@ -1,0 +1,115 @@
+"""Trajectory parity at the benchmark's full size: |corr| n = 100000, k = 32,
+T = 2500 (32 overlapping groups, market loading 0.4, returns generated on the
+CPU with seed 0), in the launch configuration the benchmark times.
+
+The FP64 oracle's first 30 iterations from the float32 counter-RNG H0 are in
+tests/golden/abs_corr_n100000_k32_trajectory.json (written by
+make_abs_corr_n100000_fixture.py, which calls only the oracle and the input
+generator; S held as float32-rounded entries, every product FP64):
+* projected AdaGrad on FP32 storage: f(H_t) of every iterate within 1e-5
+  relative of the oracle's (the FP32 target at this size, eq. trace_loss),
+  and the sampled rows of H_30;
+* ADMM on FP64 storage with an FP64 state - the path that produces the
+  time-to-tolerance reference factor: f(W_t) of every iterate to 1e-6
+  relative and sampled rows of W_30 and U_30 to 1e-5 of max W.  The oracle's
+  S is the float32 rounding of the FP64 S the library builds here, which
+  alone moves f by |2 <S - H H^T, dS>| <= 2 sqrt(f) 2^-24 ||S||_F, about
+  8e-7 relative on this workload;
+* ADMM on FP32 storage: f(W_t) within 1e-4 relative.  ADMM carries the S.W
+  products into W itself (eq. admm_H), so the rounding of the FP32 sums over
+  10^5 terms (about sqrt(10^5 / 4) 2^-24 ~ 1e-5 per entry) moves every step
+  by ~1e-6 in f, and the steps add up (4e-5 after 30 steps measured; an FP64
+  run from H0 perturbed by 1e-7 stays within 2e-7, so the iteration does not
+  amplify errors: the FP32 sums are the cause).  AdaGrad normalises its step
+  by the accumulator and stays within 1e-6.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as o
+import paper_2607_24518_amd as sym
+import synth
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import ctx, dev, from_dev, to_dev  # noqa: E402
+
+FIXTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "abs_corr_n100000_k32_trajectory.json")
+
+
+@pytest.fixture(scope="module")
+def fx():
+    with open(FIXTURE) as fh:
+        d = json.load(fh)
+    X = synth.overlap_returns(d["seed"], T=d["T"], n=d["n"], groups=d["groups"], device="cpu").X.numpy()
+    ck = d["X_checksums"]
+    assert [float(X[t, j]) for t, j in ((0, 0), (17, 4242), (2499, 99999), (1234, 56789))] == ck["samples"], \
+        "the returns generator gives another panel on this machine: the fixture does not apply"
+    Xd = X.astype(np.float64)
+    assert float(Xd.sum()) == pytest.approx(ck["sum"], rel=1e-12)
+    del Xd
+    c = ctx()
+    Xg = to_dev(X)
+    del X
+    H0 = o.init_H(d["mean"], d["n"], d["k"], d["init_seed"], as_float32=True)
+    return d, c, Xg, H0
+
+
+def _run(c, S, k, params, H0, steps, f64=False):
+    st = sym.symnmf_state_create(c, S, k, params, to_dev(H0, torch.float64 if f64 else torch.float32))
+    f = [sym.symnmf_step(c, S, st).f for _ in range(steps)]
+    return st, np.array(f)
+
+
+def test_fp32_adagrad_trajectory_at_full_size(fx):
+    d, c, Xg, H0 = fx
+    n, k, N = d["n"], d["k"], d["steps"]
+    S = sym.symnmf_build_S(c, Xg, dtype=sym.S_FP32)
+    assert S.desc.mean == pytest.approx(d["mean"], rel=1e-6)
+    st, f = _run(c, S, k, sym.symnmf_params_default(eta=d["eta"]), H0, N)
+    ref = np.array(d["adagrad"]["f"])
+    rel = np.abs(f - ref) / ref
+    print("FP32 AdaGrad, relative objective error per step: max %.3e at t=%d" % (rel.max(), rel.argmax()))
+    assert rel.max() <= 1e-5
+    H = torch.empty(n, k, device=dev())
+    sym.symnmf_state_read(c, st, 0, H)
+    rows = np.array(d["rows"])
+    Hr = from_dev(H)[rows]
+    Hr_ref = np.array(d["adagrad"]["H_rows"])
+    dev_max = np.max(np.abs(Hr - Hr_ref)) / np.max(np.abs(Hr_ref))
+    print("FP32 AdaGrad, sampled rows of H_30: max deviation %.3e of max |H|" % dev_max)
+    assert dev_max <= 1e-3
+    ADMM = sym.symnmf_params_default(method=sym.ADMM, rho=d["rho"])
+    _, fa = _run(c, S, k, ADMM, H0, N)
+    ref = np.array(d["admm"]["f"])
+    rel = np.abs(fa - ref) / ref
+    print("FP32 ADMM, relative objective error per step: max %.3e" % rel.max())
+    assert rel.max() <= 1e-4
+
+
+def test_fp64_admm_trajectory_at_full_size(fx):
+    d, c, Xg, H0 = fx
+    n, k, N = d["n"], d["k"], d["steps"]
+    S = sym.symnmf_build_S(c, Xg, dtype=sym.S_FP64)
+    assert S.desc.fro2 == pytest.approx(d["fro2"], rel=1e-6)
+    st, f = _run(c, S, k, sym.symnmf_params_default(method=sym.ADMM, rho=d["rho"]), H0.astype(np.float64), N,
+                 f64=True)
+    ref = np.array(d["admm"]["f"])
+    rel = np.abs(f - ref) / ref
+    print("FP64 ADMM on FP64 S, relative objective error per step: max %.3e" % rel.max())
+    assert rel.max() <= 1e-6
+    W = torch.empty(n, k, dtype=torch.float64, device=dev())
+    U = torch.empty(n, k, dtype=torch.float64, device=dev())
+    sym.symnmf_state_read(c, st, 0, W)
+    sym.symnmf_state_read(c, st, 3, U)
+    rows = np.array(d["rows"])
+    Wr, Ur = from_dev(W)[rows], from_dev(U)[rows]
+    Wref, Uref = np.array(d["admm"]["H_rows"]), np.array(d["admm"]["U_rows"])
+    print("FP64 ADMM rows: W %.3e, U %.3e of max |W|" % (np.max(np.abs(Wr - Wref)) / np.max(Wref),
+                                                        np.max(np.abs(Ur - Uref)) / np.max(Wref)))
+    assert np.max(np.abs(Wr - Wref)) <= 1e-5 * np.max(Wref)
+    assert np.max(np.abs(Ur - Uref)) <= 1e-5 * np.max(Wref)
