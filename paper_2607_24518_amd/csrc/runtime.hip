@@ -511,6 +511,9 @@ symnmf_status symnmf_state_create(symnmf_ctx* ctx, const symnmf_S* S, int64_t k,
 #undef ALLOC
     hipStream_t sm = ctx->stream;
     hipError_t e = launch_copy_h(H0, h0_is_f64, st->H[0], h_f64, st->n * k, sm);
+    // a step writes the panel rows of the other buffer only: the fixed rows
+    // outside the panel must be present in both iterate buffers
+    if (e == hipSuccess && panel) e = launch_copy_h(H0, h0_is_f64, st->H[1], h_f64, st->n * k, sm);
     if (e == hipSuccess && p->softplus) {
         // Theta and softplus(Theta) for the panel rows
         void* Hp = (char*)st->H[0] + st->row0 * k * st->hsz;

@@ -132,12 +132,29 @@ def tpdm4096():
     return X, o.tpdm(X, q=0.05, lower_tail=True)
 
 
-@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-12), ("fp32", 3e-6)])
+@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-12), ("fp32", 3e-6), ("bf16", None), ("fp8", None)])
 def test_tpdm_4096_build(tpdm4096, dtype, tol):
+    """The TPDM in every storage format.  BF16: within half an ulp of the
+    oracle's S plus the error of the split-precision FP32 GEMM; FP8: S_ii
+    exactly, off-diagonal entries within one E4M3 step (2^-4 relative for
+    normal codes, 2^-9 / scale in the subnormal range) of S times the panel
+    scale, which is 448 over the panel's largest off-diagonal entry."""
     X, ref = tpdm4096
-    S = sym.symnmf_build_S(ctx(), to_dev(X), kind=sym.TPDM, dtype=sym.DTYPES[dtype], q=0.05, lower_tail=1)
+    S = sym.symnmf_build_S(ctx(), to_dev(X), kind=sym.TPDM, dtype=sym.DTYPES[dtype], q=0.05, lower_tail=1,
+                           fp8_panel_rows=256)
     M = stored_numpy(S)
-    assert np.max(np.abs(M - ref)) < tol
+    if dtype == "bf16":
+        ulp = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(ref), 1e-30))) - 7)
+        assert np.all(np.abs(M - ref) <= 0.5 * ulp + 3e-6)
+        assert np.all(M == M.T)
+    elif dtype == "fp8":
+        assert np.all(np.diag(M) == 1.0)
+        off = ~np.eye(4096, dtype=bool)
+        scale = np.repeat(o.fp8_panel_scales(ref, 256), 256)[:, None]
+        assert np.all((np.abs(M - ref) <= 2.0 ** -4 * np.abs(ref) + 2.0 ** -9 / scale * 1.01 + 1e-7)[off])
+        assert S.desc.fro2_stored == pytest.approx((M * M).sum(), rel=1e-9)
+    else:
+        assert np.max(np.abs(M - ref)) < tol
 
 
 @pytest.mark.parametrize("method", ["adagrad", "rmsprop"])
