@@ -1,0 +1,747 @@
+"""Measurement studies of the SymNMF library on one MI355X, beside the step-rate
+benchmark of bench.py:
+
+* ``--ttt``: time to a relative objective tolerance, (f(H_t) - f_ref) / f_ref
+  <= tol, for several variants (storage of S, method, precision ladder) of
+  one instance and one initial factor; f_ref is the FP64 oracle's reference
+  objective where one is committed (tests/golden), else the lowest objective
+  of an FP64 ADMM run on the device; every result also gets its subspace
+  error against an FP64 reference factor;
+* ``--warm``: the learned warm start against random initialisation;
+* ``--kmeans``: spherical K-means on the rows of S;
+* ``--logspace``: projected vs softplus convergence counts on the appendix's
+  benchmark matrices.
+
+Each prints one JSON line on stdout; progress goes to stderr.  The library is
+the only compute path used here (no oracle).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def log(msg):
+    print(f"[studies] {msg}", file=sys.stderr, flush=True)
+
+
+def ttt_trace(ctx, S, k, params, init, max_steps, every, store, S_hi=None, tau_switch=None):
+    """Iterate from init(H) for max_steps with every rule of the solve applied
+    at the checks (symnmf_solve_trace), keeping every ``every``-th iterate in
+    ``store``.  With S_hi, the precision ladder: the state moves from S to
+    S_hi at the first check whose stagnation measure is below tau_switch
+    (symnmf_solve_trace_ladder).  Returns (seconds of every kept iterate from
+    the start of the initialisation, first certified t or -1, initialisation
+    seconds, switch t or -1); times come from HIP events on the solver
+    stream."""
+    import torch
+    import paper_2607_24518_amd as sym
+
+    n = S.desc.n
+    nsave = max_steps // every
+    torch.cuda.synchronize()
+    ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev_a.record()
+    H = torch.empty(n, k, device=store.device)
+    init(H)
+    st = sym.symnmf_state_create(ctx, S, k, params, H)
+    ev_b.record()
+    switched = -1
+    if S_hi is None:
+        ms, certified = sym.symnmf_solve_trace(ctx, S, st, nsave * every, every, store)
+    else:
+        ms, certified, switched = sym.symnmf_solve_trace_ladder(ctx, S, S_hi, st, nsave * every, every, store,
+                                                                tau_switch)
+    torch.cuda.synchronize()
+    t_init = ev_a.elapsed_time(ev_b) / 1000.0
+    del st
+    return [t_init + m / 1000.0 for m in ms], certified, t_init, switched
+
+
+def ttt_scan(objective_of, store, nsave, f_ref, tol, every, times):
+    """First kept iterate with (objective_of(H) - f_ref) / f_ref <= tol: a coarse scan
+    every 32 kept iterates, then bisection inside the first bracket (the
+    objective of these runs decreases except for small oscillations)."""
+    cache = {}
+
+    def rel(j):
+        if j not in cache:
+            cache[j] = (objective_of(store[j]) - f_ref) / f_ref
+        return cache[j]
+
+    hit = None
+    prev = -1
+    for j in list(range(31, nsave, 32)) + [nsave - 1]:
+        if rel(j) <= tol:
+            lo, hi = prev + 1, j
+            while lo < hi:
+                mid = (lo + hi) // 2
+                if rel(mid) <= tol:
+                    hi = mid
+                else:
+                    lo = mid + 1
+            hit = lo
+            break
+        prev = j
+    entry = {"final_rel": rel(nsave - 1), "steps_run": nsave * every, "rel_first_kept": rel(0)}
+    if hit is not None:
+        entry.update(iters=(hit + 1) * every, seconds=times[hit])
+    return entry
+
+
+def ttt_run(ctx, S, k, params, init, objective_of, f_ref, tol, max_steps, every, store, S_hi=None,
+            tau_switch=None):
+    """Trace from init(H), then the time to (objective_of(H_t) - f_ref) / f_ref <= tol."""
+    times, certified, t_init, switched = ttt_trace(ctx, S, k, params, init, max_steps, every, store, S_hi,
+                                                   tau_switch)
+    entry = ttt_scan(objective_of, store, max_steps // every, f_ref, tol, every, times)
+    entry.update(init_seconds=round(t_init, 4), certified_at=certified, times=times)
+    if S_hi is not None:
+        entry.update(switched_at=switched)
+    return entry
+
+
+METHODS = {"adagrad": 0, "rmsprop": 1, "piecewise": 2, "rowsvrg": 3, "blocksvrg": 4, "admm": 5, "adam": 6,
+           "nadam": 7, "adan": 8, "mu": 9}
+# step size of each Adam-type rule in units of sqrt(mean(S) / k), from an oracle
+# sweep on the 512-instrument instance (c in {0.01, 0.03, 0.1, 0.3}: the value
+# with the smallest KKT measure after 5000 iterations)
+ADAM_ETA = {"adam": 0.1, "nadam": 0.03, "adan": 0.01}
+
+
+def variant_params(variant, eta_base, seed=0):
+    """Solver parameters of a variant name "<storage>[-<method>][-softplus][-principal]";
+    "admm<rho>" selects ADMM with that penalty (plain "admm": rho = 500)."""
+    import paper_2607_24518_amd as sym
+
+    parts = variant.split("-")
+    rho = 500.0
+    for q in parts[1:]:
+        if q.startswith("admm") and q[4:]:
+            rho = float(q[4:])
+    parts = ["admm" if q.startswith("admm") else q for q in parts]
+    method = next((q for q in parts[1:] if q in METHODS), "adagrad")
+    kw = dict(method=METHODS[method], eta=eta_base, softplus=int("softplus" in parts), max_iter=10 ** 9, seed=seed)
+    if method == "admm":
+        kw.update(rho=rho)
+    if method == "rmsprop":
+        kw.update(eta=0.03 * eta_base, eps=1e-8, alpha=0.99, mu=0.5)
+    if method in ADAM_ETA:
+        kw.update(eta=ADAM_ETA[method] * eta_base)
+    if method == "adan":
+        kw.update(beta1=0.98, beta2=0.92, beta3=0.99)
+    if method == "mu":
+        kw.update(eps=2.0 ** -23)
+    if method in ("rowsvrg", "blocksvrg"):
+        kw.update(block_rows=1024, snapshot_s=10, delta=10, phi0=0.75, row_frac=0.5)
+    if "principal" in parts:            # Block-SVRG with J = I
+        kw.update(independent_blocks=0)
+    return sym.symnmf_params_default(**kw)
+
+
+def ttt_instance(args):
+    """Returns of the time-to-tolerance workload (generated on the CPU, so the
+    instance is the one the oracle's committed reference was computed on) and
+    the S kind."""
+    import synth
+
+    if args.ttt_kind == "tpdm":
+        inst = synth.tpdm_returns(args.seed, T=args.T, n=args.n, groups=args.groups, nu=2.5, common=True,
+                                  device="cpu")
+        return inst.X, 1
+    return synth.overlap_returns(args.seed, T=args.T, n=args.n, groups=args.groups, device="cpu").X, 0
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def committed_reference(kind, n, T, groups, k, seed):
+    """The FP64 oracle's reference run of this workload, if one is committed
+    (tests/golden/*_reference.json, written by the oracle-only script next
+    to it), else None."""
+    name = {0: "abs_corr", 1: "tpdm"}[kind]
+    path = os.path.join(GOLDEN, f"{name}_n{n}_k{k}_reference.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if (d["n"], d["T"], d["groups"], d["k"], d["seed"]) != (n, T, groups, k, seed) or not d.get("complete"):
+        return None
+    return d
+
+
+def init_factor(ctx, S, k, seed, H, mean=None):
+    """Counter-RNG initial factor H0 = u sqrt(mean / k) (symnmf_init_H); with
+    ``mean`` given, the scale uses that mean instead of the stored S's (so a
+    device run starts from the oracle's H0 bit for bit)."""
+    import ctypes
+    import paper_2607_24518_amd as sym
+
+    if mean is None:
+        return sym.symnmf_init_H(ctx, S, k, seed, H)
+    d = sym.symnmf_S()
+    ctypes.memmove(ctypes.byref(d), ctypes.byref(S.desc), ctypes.sizeof(d))
+    d.mean = mean
+    return sym.symnmf_init_H(ctx, sym.Matrix(d, S.buf), k, seed, H)
+
+
+def fp64_reference(ctx, X, kind, k, rho, iters, H0, build):
+    """FP64 ADMM (FP64 storage and state) from H0 for ``iters`` iterations:
+    (objective of the last iterate, lowest objective seen, the last iterate
+    as FP32 n x k, seconds)."""
+    import torch
+    import paper_2607_24518_amd as sym
+
+    t0 = time.time()
+    S64 = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP64, **build)
+    st = sym.symnmf_state_create(ctx, S64, k, sym.symnmf_params_default(method=sym.ADMM, rho=rho,
+                                                                         max_iter=10 ** 9), H0.double())
+    best = math.inf
+    for t in range(iters):
+        s = sym.symnmf_step(ctx, S64, st, want_stats=(t % 10 == 0 or t == iters - 1))
+        if s is not None:
+            best = min(best, s.f)
+            if t % 100 == 0:
+                log(f"FP64 reference t={t} f={s.f:.12e} kkt={s.kkt:.3e}")
+    W = torch.empty(S64.desc.n, k, dtype=torch.float64, device=H0.device)
+    sym.symnmf_state_read(ctx, st, 0, W)
+    f_last = sym.symnmf_objective(ctx, S64, W, k)[0]
+    del st, S64
+    torch.cuda.empty_cache()
+    return f_last, min(best, f_last), W.float().contiguous(), time.time() - t0
+
+
+def time_to_tolerance(args):
+    """Time to (f(H_t) - f_ref) / f_ref <= tol for several variants (storage,
+    method) of the same instance and initial H0.
+
+    f(H_t) is the objective on the FP32-stored S (MFMA products, FP64 sums
+    across chunks) whatever S the variant iterates on.  f_ref: the committed
+    FP64 oracle reference of the workload if there is one (the device repeats
+    the oracle's FP64 ADMM run from the same H0 and reports how close it
+    lands), else the last objective of a device FP64 ADMM run of
+    --ttt-ref-iters iterations.  The reference factor of the subspace errors
+    is that device FP64 run's last iterate.  Every variant's iterates are
+    kept in HBM and judged after its timed run; the time of iterate H_t runs
+    from the start of its initialisation to the copy of H_t (HIP events on
+    the solver stream), with every check-time rule of the method applied.
+    """
+    import torch
+    import paper_2607_24518_amd as sym
+
+    dev = torch.device("cuda:0")
+    n, k = args.n, args.k
+    Xh, kind = ttt_instance(args)
+    X = Xh.to(dev)
+    del Xh
+    ctx = sym.symnmf_create(0)
+    build = dict(kind=kind, q=0.05, lower_tail=1, fp8_panel_rows=256)
+    stores = {"fp32": sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32, **build)}
+    variants = [v for v in args.ttt_variants.split(",") if v]
+    S32 = stores["fp32"]
+    ref = committed_reference(kind, n, args.T, args.groups, k, args.seed)
+    mean = ref["mean"] if ref else None
+    H0 = torch.empty(n, k, device=dev)
+    init_factor(ctx, S32, k, 0, H0, mean)
+    ref_iters = ref["iterations"] if ref else args.ttt_ref_iters
+    f_dev, f_dev_best, Wref, ref_s = fp64_reference(ctx, X, kind, k, ref["rho"] if ref else args.ttt_ref_rho,
+                                                    ref_iters, H0, build)
+    if ref:
+        f_ref = ref["f_ref"]
+        results = {"f_ref": f_ref, "reference": f"FP64 oracle ADMM (rho {ref['rho']:g}) after {ref['iterations']} "
+                                                f"iterations (tests/golden)",
+                   "device_fp64_same_run": {"f": f_dev, "rel_to_f_ref": (f_dev - f_ref) / f_ref,
+                                            "seconds": round(ref_s, 2)}}
+    else:
+        f_ref = f_dev_best
+        results = {"f_ref": f_ref, "reference": f"device FP64 ADMM (rho {args.ttt_ref_rho:g}) after {ref_iters} "
+                                                f"iterations", "reference_seconds": round(ref_s, 2)}
+    log(f"f_ref {f_ref:.12e}; device FP64 run {f_dev:.12e}")
+    results.update(tol=args.ttt_tol, variants={})
+    for v in variants:
+        for dt in v.split("-")[0].split(">"):       # "fp8>bf16": the precision ladder
+            if dt not in stores:
+                stores[dt] = sym.symnmf_build_S(ctx, X, dtype=sym.DTYPES[dt], **build)
+    del X
+    eta = math.sqrt(S32.desc.mean / k)
+
+    def objective_of(H):
+        return sym.symnmf_objective(ctx, S32, H, k)[0]
+
+    every = max(1, args.ttt_save_every)
+    store = torch.empty(args.ttt_max // every, n, k, device=dev)
+    for v in variants:
+        ladder = v.split("-")[0].split(">")
+        S = stores[ladder[0]]
+        S_hi = stores[ladder[1]] if len(ladder) > 1 else None
+        entry = ttt_run(ctx, S, k, variant_params(v, eta), lambda H: H.copy_(H0), objective_of,
+                        f_ref, args.ttt_tol, args.ttt_max, every, store, S_hi, args.ttt_switch)
+        entry.pop("times")
+        nsave = args.ttt_max // every
+        entry["subspace_error_final"] = sym.symnmf_subspace_error(ctx, store[nsave - 1], Wref)
+        if "iters" in entry:
+            entry["subspace_error_at_tol"] = sym.symnmf_subspace_error(ctx, store[entry["iters"] // every - 1], Wref)
+        results["variants"][v] = entry
+        log(f"variant {v}: {entry}")
+    return results
+
+
+WARM_WIDTH, WARM_HIDDEN, WARM_OMEGA_SEED = 64, 256, 7
+
+
+def warm_start_study(args):
+    """Learned warm start against random initialisation.
+
+    Training: for every training seed the returns are generated, S (FP32) is
+    built and solved from the network-free warm start (stop rule or
+    --warm-solve-iters), and the pair (canonical sketch coordinates, solved H)
+    is kept on the device;
+    the network is then trained with the scale-free Gram loss.
+    Evaluation on held-out seeds (and optionally on the n = 100000 |corr|
+    workload): time to relative objective tolerance from (a) the random init,
+    (b) the network-free coordinates, (c) the network, each timed from the
+    start of its initialisation (sketch, coordinates and network included);
+    f_ref is the objective of the random-init run's certified iterate (or of
+    its last iterate when the stop rule does not certify one).  A
+    warm run that has not reached the tolerance within twice the random run's
+    iterations falls back to the random run, and its time counts both.
+    """
+    import numpy as np
+    import torch
+    import paper_2607_24518_amd as sym
+    import synth
+
+    dev = torch.device("cuda:0")
+    ctx = sym.symnmf_create(0)
+    k, n = args.warm_k, args.warm_n
+    W, HID = WARM_WIDTH, WARM_HIDDEN
+
+    def returns(seed, n_cols):
+        if args.warm_family == "panel":
+            return synth.panel_returns(seed, T=args.warm_T, n=n_cols, groups=args.warm_groups, block=65536,
+                                       device=dev).X
+        return synth.overlap_returns(seed, T=args.warm_T, n=n_cols, groups=args.warm_groups, device=dev).X
+
+    def features(S, nn):
+        Y = torch.empty(nn, W, device=dev)
+        sym.symnmf_sketch(ctx, S, WARM_OMEGA_SEED, W, Y)
+        Xc = torch.empty(nn, W, device=dev)
+        sym.symnmf_canonical(ctx, Y, k, Xc)
+        return Xc
+
+    out = {"family": args.warm_family, "n_train": args.warm_sizes or n, "n_heldout": n, "k": k, "T": args.warm_T,
+           "groups": args.warm_groups, "width": W, "hidden": HID}
+    # 1. training pairs
+    t0 = time.time()
+    pairs = []
+    train_seeds = list(range(args.warm_seed0, args.warm_seed0 + args.warm_train))
+    ref_iters = []
+    sizes = [int(v) for v in args.warm_sizes.split(",")] if args.warm_sizes else [n]
+    for i, seed in enumerate(train_seeds):
+        ni = sizes[i % len(sizes)]
+        X = returns(seed, ni)
+        S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
+        del X
+        eta = math.sqrt(S.desc.mean / k)
+        # target: the solver's factorization from the network-free warm start
+        # (it reaches lower objectives than random initialisation)
+        H0 = torch.empty(ni, k, device=dev)
+        sym.symnmf_warm_start(ctx, S, None, W, k, WARM_OMEGA_SEED, H0)
+        st = sym.symnmf_state_create(ctx, S, k, sym.symnmf_params_default(eta=eta, max_iter=args.warm_solve_iters),
+                                     H0)
+        Hs = torch.empty(ni, k, device=dev)
+        rs, conv = sym.symnmf_solve_to_tol(ctx, S, st, H_out=Hs)
+        del st
+        ref_iters.append(int(rs.t))
+        pairs.append((features(S, ni), Hs))
+        del S
+        if (i + 1) % 10 == 0 or i + 1 == len(train_seeds):
+            log(f"training instance {i + 1}/{len(train_seeds)} solved (t={rs.t} conv={conv} E={rs.E:.4e}) "
+                f"{time.time() - t0:.0f} s")
+    out["train_solve_iters_median"] = float(np.median(ref_iters))
+    out["train_data_seconds"] = round(time.time() - t0, 1)
+    # 2. training
+    t0 = time.time()
+    params = torch.empty(sym.symnmf_mlp_param_count(W, HID, k), device=dev)
+    sym.symnmf_mlp_init(ctx, W, HID, k, args.warm_seed0, params)
+    net = sym.symnmf_mlp_create(ctx, W, HID, k, params)
+    rng = np.random.default_rng(args.warm_seed0)
+    hist = []
+    steps_total = args.warm_epochs * len(pairs)
+    step = 0
+    for ep in range(args.warm_epochs):
+        losses = []
+        for j in rng.permutation(len(pairs)):
+            lr = args.warm_lr * 0.5 * (1.0 + math.cos(math.pi * step / steps_total))   # cosine decay
+            losses.append(sym.symnmf_mlp_train_step(ctx, net, pairs[j][0], pairs[j][1], lr=lr,
+                                                    weight_decay=args.warm_wd, loss_kind=1))
+            step += 1
+        hist.append(float(np.mean(losses)))
+        if ep % 5 == 0 or ep + 1 == args.warm_epochs:
+            log(f"epoch {ep}: mean Gram loss {hist[-1]:.5f} ({time.time() - t0:.0f} s)")
+    out["train_loss_first_epoch"] = hist[0]
+    out["train_loss_last_epoch"] = hist[-1]
+    out["train_seconds"] = round(time.time() - t0, 1)
+    del pairs
+    torch.cuda.empty_cache()
+
+    # 3. evaluation
+    def evaluate(S, k_eval, model, label, seed, rand_steps, warm_steps, extra=None):
+        """random init run first (it is also the reference: f_ref is its
+        certified iterate, or its last one), then the two warm starts; with
+        ``extra`` ({name: S stored otherwise}) the three initialisations are
+        also run on those stores, evaluated on S."""
+        nn = S.desc.n
+        eta = math.sqrt(S.desc.mean / k_eval)
+        params = variant_params("fp32", eta)
+
+        def objective_of(H):
+            return sym.symnmf_objective(ctx, S, H, k_eval)[0]
+
+        every = 2
+        store = torch.empty(rand_steps // every, nn, k_eval, device=dev)
+        times, cert, t_init, _ = ttt_trace(ctx, S, k_eval, params, lambda H: sym.symnmf_init_H(ctx, S, k_eval, seed, H),
+                                        rand_steps, every, store)
+        ref_slot = (cert + 1) // every - 1 if cert >= 0 else rand_steps // every - 1
+        f_ref = objective_of(store[ref_slot])
+        res = {"f_ref": f_ref, "ref_iters": (ref_slot + 1) * every, "ref_certified": cert >= 0}
+        res["random"] = ttt_scan(objective_of, store, rand_steps // every, f_ref, args.ttt_tol, every, times)
+        inits = {
+            "coords": lambda H: sym.symnmf_warm_start(ctx, S, None, W, k_eval, WARM_OMEGA_SEED, H),
+            "mlp": lambda H: sym.symnmf_warm_start(ctx, S, model, W, k_eval, WARM_OMEGA_SEED, H),
+        }
+        r_it, r_s = res["random"].get("iters"), res["random"].get("seconds")
+        for name, init in inits.items():
+            wt, wcert, w_init, _ = ttt_trace(ctx, S, k_eval, params, init, warm_steps, every, store)
+            e = ttt_scan(objective_of, store, warm_steps // every, f_ref, args.ttt_tol, every, wt)
+            e["init_seconds"] = round(w_init, 4)
+            if r_it is not None:
+                if e.get("iters") is None or e["iters"] > 2 * r_it:
+                    # fallback: the warm run is abandoned after 2x the random
+                    # iterations (or its cap) and the random run is started
+                    idx = min(2 * r_it // every, len(wt)) - 1
+                    e["fallback"] = True
+                    e["seconds_with_fallback"] = wt[idx] + r_s
+                else:
+                    e["fallback"] = False
+                    e["seconds_with_fallback"] = e["seconds"]
+                e["speedup_vs_random"] = round(r_s / e["seconds_with_fallback"], 3)
+            res[name] = e
+        for xname, Sx in (extra or {}).items():
+            xinits = {
+                "random": lambda H: sym.symnmf_init_H(ctx, Sx, k_eval, seed, H),
+                "coords": lambda H: sym.symnmf_warm_start(ctx, Sx, None, W, k_eval, WARM_OMEGA_SEED, H),
+                "mlp": lambda H: sym.symnmf_warm_start(ctx, Sx, model, W, k_eval, WARM_OMEGA_SEED, H),
+            }
+            for name, init in xinits.items():
+                steps = rand_steps if name == "random" else warm_steps
+                wt, _, w_init, _ = ttt_trace(ctx, Sx, k_eval, params, init, steps, every, store)
+                e = ttt_scan(objective_of, store, steps // every, f_ref, args.ttt_tol, every, wt)
+                e["init_seconds"] = round(w_init, 4)
+                if r_s is not None and e.get("seconds"):
+                    e["speedup_vs_fp32_random"] = round(r_s / e["seconds"], 3)
+                res[f"{xname}-{name}"] = e
+        del store
+        log(f"{label}: " + json.dumps(res))
+        return res
+
+    held = []
+    for seed in range(args.warm_heldout0, args.warm_heldout0 + args.warm_heldout):
+        X = returns(seed, n)
+        S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
+        del X
+        held.append(evaluate(S, k, net, f"held-out seed {seed}", seed, args.warm_max, args.warm_warm_max))
+        del S
+    out["heldout"] = held
+    for name in ("coords", "mlp"):
+        sp = [h[name]["speedup_vs_random"] for h in held if "speedup_vs_random" in h[name]]
+        if sp:
+            out[f"{name}_speedup_median"] = float(np.median(sp))
+            out[f"{name}_wins"] = int(sum(1 for v in sp if v > 1.0))
+            out[f"{name}_fallbacks"] = int(sum(1 for h in held if h[name].get("fallback")))
+    if args.warm_c3:
+        X = synth.overlap_returns(0, T=2500, n=100000, groups=32, device=dev).X
+        S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
+        extra = {dt: sym.symnmf_build_S(ctx, X, dtype=sym.DTYPES[dt], fp8_panel_rows=256)
+                 for dt in args.warm_c3_dtypes.split(",") if dt and dt != "fp32"}
+        del X
+        out["c3_abs_corr_n100000"] = evaluate(S, k, net, "n=100000 |corr|", 1, args.warm_c3_max, args.warm_c3_max,
+                                              extra)
+    return out
+
+
+def logspace_study(args):
+    """Projected (P) vs softplus (L) convergence counts on the appendix's
+    benchmark matrices, as in the paper's LogSpace table: runs satisfying the
+    three-criterion stop rule within --logspace-budget iterations, out of
+    3 seeds x 2 matrix types per size, k = floor(sqrt(n)) (capped at 64)."""
+    import torch
+    import paper_2607_24518_amd as sym
+    import synth
+    dev = torch.device("cuda:0")
+    ctx = sym.symnmf_create(0)
+    sizes = [int(v) for v in args.logspace_sizes.split(",")]
+    methods = {"rmsprop": dict(method=sym.RMSPROP, c=0.03, eps=1e-8, alpha=0.99, mu=0.5),
+               "adam": dict(method=sym.ADAM, c=ADAM_ETA["adam"]),
+               "adagrad": dict(method=sym.ADAGRAD, c=1.0)}
+    table, runs = {}, []
+    for n in sizes:
+        k = min(math.isqrt(n), 64)
+        for kind in ("corr", "tpdm"):
+            for seed in (7, 42, 99):
+                X = synth.paper_benchmark(seed, n, kind, device=dev).X
+                if kind == "corr":
+                    S = sym.symnmf_build_S(ctx, X, kind=sym.ABS_CORR, dtype=sym.S_FP32)
+                else:
+                    S = sym.symnmf_build_S(ctx, X, kind=sym.TPDM, dtype=sym.S_FP32, q=0.01, lower_tail=0,
+                                           raw_marginals=1)
+                del X
+                H0 = torch.empty(n, k, device=dev)
+                sym.symnmf_init_H(ctx, S, k, seed, H0)
+                base = math.sqrt(S.desc.mean / k)
+                for name, m in methods.items():
+                    for form in (0, 1):
+                        kw = {q: v for q, v in m.items() if q != "c"}
+                        p = sym.symnmf_params_default(eta=m["c"] * base, softplus=form, max_iter=args.logspace_budget,
+                                                      seed=seed, **kw)
+                        st = sym.symnmf_state_create(ctx, S, k, p, H0)
+                        t0 = time.perf_counter()
+                        try:
+                            stats, conv = sym.symnmf_solve_to_tol(ctx, S, st)
+                        except sym.SymnmfError as e:     # e.g. a non-finite gradient: not converged
+                            log(f"logspace n={n} {kind} seed={seed} {name} form={form}: {e}")
+                            stats, conv = sym.symnmf_state_stats(ctx, st), False
+                        wall = time.perf_counter() - t0
+                        key = f"n{n}_{name}_{'L' if form else 'P'}"
+                        table[key] = table.get(key, 0) + int(bool(conv))
+                        rec = {"n": n, "k": k, "kind": kind, "seed": seed, "method": name, "form": "L" if form else "P",
+                               "converged": bool(conv), "t": int(stats.t), "E": stats.E, "kkt": stats.kkt,
+                               "seconds": round(wall, 3)}
+                        runs.append(rec)
+                        log(f"logspace {rec}")
+                        del st
+                del S
+                torch.cuda.empty_cache()
+    return {"converged_of_6": table, "runs": runs}
+
+
+def kmeans_paper_benchmark(args, ctx, Ks):
+    """K-means on the appendix's own benchmark matrices (floor(sqrt(n))
+    groups plus the common factor, 40000 samples; |corr| and the raw-marginal
+    TPDM with the top 1 % of samples), one instance and seeding per seed, as
+    in the paper's K-means table (means over seeds 7, 42, 99)."""
+    import torch
+    import paper_2607_24518_amd as sym
+    import synth
+    dev = torch.device("cuda:0")
+    n = args.n
+    runs = []
+    for kind in args.kmeans_kinds.split(","):
+        for seed in [int(v) for v in args.kmeans_seeds.split(",")]:
+            log(f"paper benchmark {kind} n={n} seed={seed}")
+            X = synth.paper_benchmark(seed, n, kind, device=dev).X
+            torch.cuda.synchronize()
+            for dname in args.kmeans_dtypes.split(","):
+                if kind == "corr":
+                    S = sym.symnmf_build_S(ctx, X, kind=sym.ABS_CORR, dtype=sym.DTYPES[dname])
+                else:
+                    S = sym.symnmf_build_S(ctx, X, kind=sym.TPDM, dtype=sym.DTYPES[dname], q=0.01, lower_tail=0,
+                                           raw_marginals=1)
+                spec = None
+                if dname == "fp32":
+                    t0 = time.perf_counter()
+                    spec = sym.symnmf_spectral(ctx, S, max_iter=300, tol=1e-9)
+                    spec["seconds"] = round(time.perf_counter() - t0, 3)
+                    spec["bound"] = (spec["r_eff"] - 1.0) ** 2
+                    log(f"spectral {kind} seed={seed}: {spec}")
+                for K in Ks:
+                    labels = torch.zeros(n, dtype=torch.int32, device=dev)
+                    for rep in range(args.kmeans_reps):
+                        t0 = time.perf_counter()
+                        rows = (sym.symnmf_kmeans_seed_pp(ctx, S, K, seed) if args.kmeans_seeding == "kpp"
+                                else None)
+                        seed_s = time.perf_counter() - t0
+                        st = sym.symnmf_kmeans(ctx, S, K, labels, seed=seed, init_rows=rows, tol=1e-4,
+                                               max_iter=args.kmeans_max_iter, allow_notconv=True)
+                        wall = time.perf_counter() - t0
+                    sil = sym.symnmf_silhouette(ctx, S, labels, K)
+                    rec = {"kind": kind, "seed": seed, "S_storage": dname, "K": K, "seconds": round(wall, 4),
+                           "seeding": args.kmeans_seeding, "seeding_s": round(seed_s, 4),
+                           "iters": st["iters"], "converged": bool(st["converged"]), "J": st["J"],
+                           "silhouette": round(sil, 4), "spectral": spec}
+                    log(f"kmeans {rec}")
+                    runs.append(rec)
+                del S
+                torch.cuda.empty_cache()
+            del X
+            torch.cuda.empty_cache()
+    means = {}
+    for r in runs:
+        key = f"{r['kind']}_{r['S_storage']}_K{r['K']}"
+        means.setdefault(key, []).append(r)
+    def mean_spec(v, key):
+        vals = [r["spectral"][key] for r in v if r.get("spectral")]
+        return round(sum(vals) / len(vals), 4) if vals else None
+
+    summary = {k: {"seconds": round(sum(r["seconds"] for r in v) / len(v), 4),
+                   "seeding_s": round(sum(r["seeding_s"] for r in v) / len(v), 4),
+                   "lambda1": mean_spec(v, "lambda1"), "r_eff": mean_spec(v, "r_eff"),
+                   "collapse": mean_spec(v, "collapse"), "bound": mean_spec(v, "bound"),
+                   "iters": round(sum(r["iters"] for r in v) / len(v), 2),
+                   "silhouette": round(sum(r["silhouette"] for r in v) / len(v), 4),
+                   "converged": all(r["converged"] for r in v), "seeds": len(v)} for k, v in means.items()}
+    return {"runs": runs, "means": summary}
+
+
+def kmeans_bench(args):
+    """Spherical K-means on the rows of the n = 10^5 |corr| S: wall time of
+    symnmf_kmeans to the stop rule (relative drop of sum(1 - cos) below 1e-4)
+    and of the silhouette, per storage type and cluster count."""
+    import torch
+    import paper_2607_24518_amd as sym
+    import synth
+    dev = torch.device("cuda:0")
+    n = args.n
+    ctx = sym.symnmf_create(0)
+    Ks = [int(v) for v in args.kmeans.split(",") if v]
+    runs = []
+    if args.kmeans_family == "paper":
+        return kmeans_paper_benchmark(args, ctx, Ks)
+    log(f"generating returns T={args.T} n={n} groups={args.groups}")
+    X = synth.overlap_returns(args.seed, T=args.T, n=n, groups=args.groups, device=dev).X
+    for dname in args.kmeans_dtypes.split(","):
+        S = sym.symnmf_build_S(ctx, X, kind=sym.ABS_CORR, dtype=sym.DTYPES[dname], fp8_panel_rows=256)
+        torch.cuda.synchronize()
+        sbytes = {"fp32": 4, "bf16": 2, "fp8": 1}[dname]
+        for K in Ks:
+            labels = torch.zeros(n, dtype=torch.int32, device=dev)
+            w = 16 if K <= 16 else (32 if K <= 32 else 64)
+            slices = (K + w - 1) // w
+            for rep in range(args.kmeans_reps):
+                t0 = time.perf_counter()
+                rows = (sym.symnmf_kmeans_seed_pp(ctx, S, K, args.kmeans_seed) if args.kmeans_seeding == "kpp"
+                        else None)
+                seed_s = time.perf_counter() - t0
+                st = sym.symnmf_kmeans(ctx, S, K, labels, seed=args.kmeans_seed, init_rows=rows, tol=1e-4,
+                                       max_iter=args.kmeans_max_iter, allow_notconv=True)
+                wall = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            sil = sym.symnmf_silhouette(ctx, S, labels, K)
+            sil_s = time.perf_counter() - t0
+            passes = 2 * slices * (st["iters"] + 1)            # stream passes of the Lloyd iterations
+            rec = {"S_storage": dname, "K": K, "slice_width": w, "slices": slices, "seconds": round(wall, 4),
+                   "seeding": args.kmeans_seeding, "seeding_s": round(seed_s, 4),
+                   "iters": st["iters"], "converged": bool(st["converged"]), "J0": st["J0"], "J": st["J"],
+                   "empty_clusters": st["empty"], "silhouette": round(sil, 5), "silhouette_s": round(sil_s, 4),
+                   "stream_passes": passes, "ms_per_pass_incl_overheads": round(1e3 * wall / (passes + 1), 3),
+                   "S_GB_per_pass": round(n * n * sbytes / 1e9, 2)}
+            log(f"kmeans {rec}")
+            runs.append(rec)
+        del S
+        torch.cuda.empty_cache()
+    return {"runs": runs}
+
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--k", type=int, default=32)
+    ap.add_argument("--T", type=int, default=2500)
+    ap.add_argument("--groups", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--ttt", action="store_true", help="time-to-tolerance comparison")
+    ap.add_argument("--ttt-variants", default="fp32-admm,bf16-admm,fp8-admm,fp32,bf16,fp32-adam,bf16-adam")
+    ap.add_argument("--ttt-kind", default="abs_corr", choices=["abs_corr", "tpdm"])
+    ap.add_argument("--ttt-tol", type=float, default=1e-4)
+    ap.add_argument("--ttt-switch", type=float, default=1e-5,
+                    help="precision ladder (variants 'lo>hi-...'): move to the precise storage at the first check "
+                         "whose stagnation measure (E_{t-delta} - E_t) / E_0 is below this")
+    ap.add_argument("--ttt-max", type=int, default=6000)
+    ap.add_argument("--ttt-save-every", type=int, default=2)
+    ap.add_argument("--ttt-ref-iters", type=int, default=3000,
+                    help="iterations of the device FP64 ADMM reference where no oracle reference is committed")
+    ap.add_argument("--ttt-ref-rho", type=float, default=500.0)
+    ap.add_argument("--warm", action="store_true", help="learned warm start study instead of the step rate")
+    ap.add_argument("--warm-family", default="panel", choices=["panel", "overlap"])
+    ap.add_argument("--warm-n", type=int, default=20000)
+    ap.add_argument("--warm-sizes", default="", help="training instance sizes, cycled (default: --warm-n)")
+    ap.add_argument("--warm-k", type=int, default=64)
+    ap.add_argument("--warm-T", type=int, default=1000)
+    ap.add_argument("--warm-groups", type=int, default=64)
+    ap.add_argument("--warm-train", type=int, default=200)
+    ap.add_argument("--warm-seed0", type=int, default=1000)
+    ap.add_argument("--warm-heldout", type=int, default=20)
+    ap.add_argument("--warm-heldout0", type=int, default=2000)
+    ap.add_argument("--warm-solve-iters", type=int, default=1500)
+    ap.add_argument("--warm-ref-iters", type=int, default=8000)
+    ap.add_argument("--warm-epochs", type=int, default=40)
+    ap.add_argument("--warm-lr", type=float, default=1e-3)
+    ap.add_argument("--warm-wd", type=float, default=1e-4)
+    ap.add_argument("--warm-max", type=int, default=8000, help="steps of the random-init (reference) run")
+    ap.add_argument("--warm-warm-max", type=int, default=3000, help="steps of each warm-started run")
+    ap.add_argument("--warm-c3", action="store_true", help="also evaluate on the n=100000 |corr| workload")
+    ap.add_argument("--warm-c3-max", type=int, default=6000)
+    ap.add_argument("--warm-c3-dtypes", default="fp32", help="storage types of the n=100000 evaluation, e.g. fp32,bf16")
+    ap.add_argument("--kmeans", default="", help="spherical K-means study instead of the step rate: cluster counts, "
+                                                 "e.g. 32,316")
+    ap.add_argument("--kmeans-dtypes", default="fp32,bf16")
+    ap.add_argument("--kmeans-seed", type=int, default=7)
+    ap.add_argument("--kmeans-max-iter", type=int, default=100)
+    ap.add_argument("--kmeans-reps", type=int, default=2, help="runs per case; the last is reported")
+    ap.add_argument("--kmeans-family", default="overlap", choices=["overlap", "paper"],
+                    help="overlapping-groups returns, or the appendix's benchmark matrices (--kmeans-kinds)")
+    ap.add_argument("--kmeans-kinds", default="corr,tpdm")
+    ap.add_argument("--kmeans-seeding", default="forgy", choices=["forgy", "kpp"],
+                    help="Forgy rows or k-means++ rows (symnmf_kmeans_seed_pp, timed with the run)")
+    ap.add_argument("--kmeans-seeds", default="7,42,99")
+    ap.add_argument("--logspace", action="store_true", help="projected vs softplus convergence counts instead of the "
+                                                           "step rate")
+    ap.add_argument("--logspace-sizes", default="100,1000,10000")
+    ap.add_argument("--logspace-budget", type=int, default=20000)
+    args = ap.parse_args()
+    if args.logspace:
+        res = logspace_study(args)
+        print(json.dumps({"metric": "runs certified by the stop rule within the iteration budget, projected vs "
+                                    "softplus", "unit": "runs of 6", "n_gpus": 1, "data": "synthetic",
+                          "budget": args.logspace_budget, **res}), flush=True)
+        return
+    if args.kmeans:
+        res = kmeans_bench(args)
+        print(json.dumps({"metric": "spherical K-means on the rows of S: wall time to the stop rule", "unit": "s",
+                          "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": (f"paper_benchmark_n{args.n}_T40000" if args.kmeans_family == "paper"
+                                                  else f"abs_corr_n{args.n}_T{args.T}_groups{args.groups}"),
+                                     "stop": "relative drop of sum(1 - cos) below 1e-4"},
+                          **res}), flush=True)
+        return
+    if args.warm:
+        res = warm_start_study(args)
+        print(json.dumps({"metric": "time to relative objective tolerance, learned warm start vs random init",
+                          "unit": "s", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                          "tol": args.ttt_tol, **res}), flush=True)
+        return
+    if args.ttt:
+        res = time_to_tolerance(args)
+        base = res["variants"].get("fp32-admm", {}).get("seconds")
+        for v in res["variants"].values():
+            if base and v.get("seconds"):
+                v["speedup_vs_fp32_admm"] = round(base / v["seconds"], 3)
+        print(json.dumps({"metric": "time to relative objective tolerance", "unit": "s",
+                          "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": f"{args.ttt_kind}_n{args.n}_k{args.k}_T{args.T}"}, **res}),
+              flush=True)
+        return
+    ap.error("choose a study: --ttt, --warm, --kmeans or --logspace")
+
+
+if __name__ == "__main__":
+    main()

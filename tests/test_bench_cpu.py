@@ -1,6 +1,7 @@
-"""Host logic of bench.py (CPU): the algorithmic byte counts behind the
-roofline figures, the parsing of time-to-tolerance variants (storage,
-precision ladder, method), and the refusal of more than one GPU."""
+"""Host logic of bench.py and studies.py (CPU): the algorithmic byte counts
+behind the roofline figures, the parsing of time-to-tolerance variants
+(storage, precision ladder, method), the committed reference lookup, and the
+refusal of more than one GPU."""
 import json
 import os
 import subprocess
@@ -12,6 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 import paper_2607_24518_amd as sym  # noqa: E402
+import studies  # noqa: E402
 
 
 def test_algorithmic_bytes():
@@ -27,7 +29,7 @@ def test_algorithmic_bytes():
     ("fp32", sym.ADAGRAD, 1.0), ("fp8>bf16-piecewise", sym.PIECEWISE_ADAGRAD, 1.0),
     ("fp8>fp32-blocksvrg", sym.BLOCK_SVRG, 1.0), ("bf16-adam", sym.ADAM, 0.1), ("fp32-admm1000", sym.ADMM, 1.0)])
 def test_variant_parsing(variant, method, eta_scale):
-    p = bench.variant_params(variant, 0.05)
+    p = studies.variant_params(variant, 0.05)
     assert p.method == method and p.eta == pytest.approx(0.05 * eta_scale)
     ladder = variant.split("-")[0].split(">")
     assert all(dt in sym.DTYPES for dt in ladder)
@@ -43,3 +45,11 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_committed_reference_lookup():
+    # only a complete reference of exactly this workload is used
+    assert studies.committed_reference(0, 100000, 2500, 32, 32, 1) is None
+    d = studies.committed_reference(0, 100000, 2500, 32, 32, 0)
+    if d is not None:
+        assert d["complete"] and d["f_ref"] > 0 and d["iterations"] >= 100
