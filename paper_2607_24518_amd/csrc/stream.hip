@@ -122,6 +122,105 @@ __global__ __launch_bounds__(256) void stream_generic(const ST* __restrict__ S, 
 }
 
 // ---------------------------------------------------------------------------
+// FP64 storage (row-major, leading dimension ld), FP64 H and FP64 accumulation
+// on the FP64 matrix cores, k = 16 NT.  v_mfma_f64_16x16x4_f64 (lane l,
+// r = l % 16, g = l / 16): A[r][g], B[g][r], D[4v+g][r] (v = 0..3: the four
+// output rows of a lane are interleaved, unlike the FP32 16x16x4 form).  A wave
+// owns 64 rows of the tile (4 row groups of 16); per sub-step of 8 columns a
+// lane loads 16 bytes (2 doubles) of its row in each row group, and the two
+// MFMAs of an element e reduce over the columns 2g + e of the sub-step, with
+// the matching H rows read from the chunk staged in LDS (scaled by the unit's
+// weight).  S loads run one sub-step pair ahead.  Units and partials follow
+// the plan as in stream_generic.
+// ---------------------------------------------------------------------------
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__global__ __launch_bounds__(256, 2) void stream_f64_mfma(const double* __restrict__ S, int64_t ld,
+                                                          const double* __restrict__ H,
+                                                          double* __restrict__ part, PlanView p) {
+    constexpr int K = 16 * NT;
+    constexpr int SS = KC / 8;                             // sub-steps of 8 columns per unit
+    __shared__ double Hs[KC * K];
+    int64_t U; int32_t na;
+    plan_bounds(p, U, na);
+    if (U == 0) return;
+    const int64_t Pe = U < p.P ? U : p.P;
+    const int64_t w = blockIdx.x;
+    if (w >= Pe) return;
+    int64_t u = wg_start(w, U, Pe);
+    const int64_t u1 = wg_start(w + 1, U, Pe);
+    int32_t a = find_active(p, u, na);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, lr = lane & 15, lg = lane >> 4;
+    while (u < u1) {
+        const int64_t abase = unit_off(p, a);
+        const int64_t run_end = min(u1, unit_off(p, a + 1));
+        const int64_t tile = tile_of(p, a);
+        doublex4 acc[4][NT];
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[rg][nt] = doublex4{0.0, 0.0, 0.0, 0.0};
+        const double* rowp[4];
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg)
+            rowp[rg] = S + (tile * TR + 64 * wv + 16 * rg + lr) * ld + 2 * lg;
+        for (; u < run_end; ++u) {
+            int32_t chunk; float wt;
+            unit_chunk(p, a, u - abase, chunk, wt);
+            __syncthreads();
+            const double* hsrc = H + (int64_t)chunk * KC * K;
+            for (int f = t; f < KC * K; f += 256) Hs[f] = hsrc[f] * (double)wt;
+            __syncthreads();
+            const int64_t col0 = (int64_t)chunk * KC;
+            doublex2 cur[2][4], nxt[2][4];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int rg = 0; rg < 4; ++rg) cur[q][rg] = *(const doublex2*)(rowp[rg] + col0 + 8 * q);
+            for (int s = 0; s < SS; s += 2) {
+                if (s + 2 < SS) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+#pragma unroll
+                        for (int rg = 0; rg < 4; ++rg)
+                            nxt[q][rg] = *(const doublex2*)(rowp[rg] + col0 + 8 * (s + 2 + q));
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int kk = 8 * (s + q) + 2 * lg + e;
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) {
+                            const double b = Hs[kk * K + 16 * nt + lr];
+#pragma unroll
+                            for (int rg = 0; rg < 4; ++rg)
+                                acc[rg][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[q][rg][e], b, acc[rg][nt],
+                                                                                   0, 0, 0);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int rg = 0; rg < 4; ++rg) cur[q][rg] = nxt[q][rg];
+            }
+        }
+        double* dst = part + (w + a) * (int64_t)TR * K;
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    dst[(64 * wv + 16 * rg + 4 * v + lg) * K + 16 * nt + lr] = acc[rg][nt][v];
+        ++a;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // H images.  KIND 0 (FP32 S): floats in the order Hs[nt][s][g][c][m];
 // KIND 1 (BF16 S): three bf16 planes, each Hb[nt][s][g][c][i];
 // KIND 2 (FP8 S): three bf16 planes, each Hb[nt][s][h][g][c][i].
@@ -626,6 +725,16 @@ hipError_t launch_stream(const void* S, int32_t stype, int64_t ld, const void* H
         case SYMNMF_S_FP8: return launch_generic_s<uint8_t>(S, ld, H, h_f64, k, part, acc_f64, p, stream);
         case SYMNMF_S_FP64:
             if (!h_f64) return hipErrorInvalidValue;
+            if ((k == 16 || k == 32) && std::getenv("SYMNMF_F64_GENERIC") == nullptr) {
+                dim3 grid(p.P), block(256);
+                if (k == 16)
+                    hipLaunchKernelGGL((stream_f64_mfma<1>), grid, block, 0, stream, (const double*)S, ld,
+                                       (const double*)H, (double*)part, p);
+                else
+                    hipLaunchKernelGGL((stream_f64_mfma<2>), grid, block, 0, stream, (const double*)S, ld,
+                                       (const double*)H, (double*)part, p);
+                return hipGetLastError();
+            }
             return launch_generic<double, double, double>(S, ld, H, k, part, p, stream);
     }
     return hipErrorInvalidValue;
