@@ -181,6 +181,27 @@ void symnmf_params_default(symnmf_params* p);
  * (a hipStream_t; NULL = the null stream).  Allocates nothing on the device. */
 symnmf_status symnmf_create(symnmf_ctx** ctx, int32_t device, void* hip_stream);
 void symnmf_destroy(symnmf_ctx* ctx);
+
+/* Device scratch.  The calls that need temporary device buffers (S build and
+ * load, objective, median, sketch, canonical coordinates, warm start,
+ * subspace error, K-means, silhouette, spectral diagnostic) take them from a
+ * pool held by the context; the state and the network objects own their own
+ * workspace instead.  symnmf_set_workspace(ctx, dev, bytes) makes the pool a
+ * caller-owned device buffer: the library then allocates nothing for these
+ * calls, and a call that needs more than ``bytes`` returns ENOMEM (its message
+ * gives the size; the *_workspace queries below give it beforehand).  With no
+ * workspace attached (the default, or after symnmf_set_workspace(ctx, NULL,
+ * 0)) the pool takes device memory with hipMalloc when a call needs more than
+ * it holds and keeps it until symnmf_destroy, so a call no larger than an
+ * earlier one on the same context allocates nothing.  Buffers are carved in
+ * stack order and reused by the next call at once (calls on a context run in
+ * its stream's order); set_workspace synchronises the stream and fails with
+ * EINVAL while a call is using the pool.  The caller keeps an attached buffer
+ * alive until it is detached or the context is destroyed. */
+symnmf_status symnmf_set_workspace(symnmf_ctx* ctx, void* dev, int64_t bytes);
+/* Bytes the pool holds (attached or allocated) and the number of blocks the
+ * pool has taken from hipMalloc since the context was created. */
+symnmf_status symnmf_workspace_info(symnmf_ctx* ctx, int64_t* held, int64_t* allocs);
 const char* symnmf_last_error(const symnmf_ctx* ctx);
 
 /* Bytes of the buffer a stored S (rows x n, dtype) needs, scales included. */
@@ -205,12 +226,16 @@ int64_t symnmf_S_offset(int64_t r, int64_t c, int64_t rows_pad, int64_t ld, int3
  * (z = h + m, products h h + h m + m h, relative error ~2^-16 before the
  * storage rounding); FP64 storage uses FP64 FMAs.  The stored S is exactly
  * symmetric in every format.
- * buf: device, >= symnmf_S_bytes(...) bytes, caller owned.  Temporary device
- * memory is allocated and freed inside the call.  Synchronises (fills the FP64
+ * buf: device, >= symnmf_S_bytes(...) bytes, caller owned.  Scratch comes from
+ * the context pool (symnmf_build_S_workspace bytes).  Synchronises (fills the FP64
  * sums of ``out``).  EINVAL: T < 2, n < 1, bad row range, zero-variance
  * column, floor(qT) < 1, raw_marginals not 0/1, a raw-marginal X < 0 in the
  * tail orientation.  EUNSUPPORTED: the rank transform with T > 32768.
  * ENUMERIC: X holds a NaN or an infinity. */
+/* Scratch bytes symnmf_build_S needs for these parameters (the standardised
+ * or angular operand Z, FP64 sums, FP8 panel maxima, the TPDM rank workspace
+ * and the bf16 operand planes), or -1 for invalid parameters. */
+int64_t symnmf_build_S_workspace(const symnmf_sbuild_params* p);
 symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuild_params* p,
                              void* buf, int64_t buf_bytes, symnmf_S* out);
 
@@ -289,6 +314,8 @@ symnmf_status symnmf_state_checks(symnmf_ctx* ctx, symnmf_state* st, symnmf_stat
  * with float32 H and k in {16, 32} the MFMA products are summed in FP32 within
  * each 256-column chunk and in FP64 across chunks; otherwise every product is
  * accumulated in FP64.  The trace and Gram terms are FP64.  Synchronises. */
+/* Scratch bytes of symnmf_objective for this S and rank (-1: bad argument). */
+int64_t symnmf_objective_workspace(const symnmf_ctx* ctx, const symnmf_S* S, int64_t k, int32_t h_is_f64);
 symnmf_status symnmf_objective(symnmf_ctx* ctx, const symnmf_S* S, const void* H, int32_t h_is_f64,
                                int64_t k, double* f, double* E);
 
@@ -350,6 +377,8 @@ symnmf_status symnmf_solve_trace_ladder(symnmf_ctx* ctx, const symnmf_S* S_lo, c
  * 2k - 2 ||Q_A^T Q_B||_F^2 and Q_X = X (X^T X)^-1/2; only k x k FP64 work
  * after the products A^T A, B^T B, A^T B.  A, B: device n x k float32.
  * ENUMERIC when a factor is rank deficient.  Synchronises. */
+/* Scratch bytes of symnmf_subspace_error (-1: bad argument). */
+int64_t symnmf_subspace_error_workspace(int64_t n, int64_t k);
 symnmf_status symnmf_subspace_error(symnmf_ctx* ctx, const float* A, const float* B, int64_t n, int64_t k,
                                     double* out);
 
@@ -357,6 +386,8 @@ symnmf_status symnmf_subspace_error(symnmf_ctx* ctx, const float* A, const float
  * float32 array of m values, by radix selection on the bit patterns.
  * Synchronises; the result goes to *out. */
 symnmf_status symnmf_median_sq(symnmf_ctx* ctx, const float* g, int64_t m, float* out);
+/* Scratch bytes of symnmf_median_sq. */
+int64_t symnmf_median_workspace(void);
 
 /* The same lower median of g_i^2 for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
@@ -456,6 +487,11 @@ void symnmf_mlp_destroy(symnmf_mlp* mlp);
  * 1 = gradient of the last training step, 2 = AdamW first moment, 3 = second
  * moment.  Asynchronous. */
 symnmf_status symnmf_mlp_read(symnmf_ctx* ctx, const symnmf_mlp* mlp, int32_t which, float* dst);
+/* Grow the network's activation buffers (part of the network object's
+ * workspace, freed by symnmf_mlp_destroy) to ``rows`` rows for inference, and
+ * with ``training`` also for symnmf_mlp_train_step, so that later calls of at
+ * most that many rows allocate nothing. */
+symnmf_status symnmf_mlp_reserve(symnmf_ctx* ctx, symnmf_mlp* mlp, int64_t rows, int32_t training);
 /* Replace the parameters (device floats) and clear the AdamW state and step
  * count.  Asynchronous. */
 symnmf_status symnmf_mlp_write(symnmf_ctx* ctx, symnmf_mlp* mlp, const float* params);
@@ -480,8 +516,10 @@ symnmf_status symnmf_mlp_train_step(symnmf_ctx* ctx, symnmf_mlp* mlp, const floa
  * Omega_ij = sqrt(-2 ln(1 - u)) cos(2 pi v), u and v the top 53 bits of
  * SplitMix64 outputs 2e and 2e + 1 (e = i * width + j) of key omega_seed,
  * scaled by 2^-53.  1 <= width <= 64.  Runs the S.H stream once.
- * Temporary device memory is allocated and freed inside.  Synchronises. */
+ * Scratch from the context pool (symnmf_sketch_workspace).  Synchronises. */
 symnmf_status symnmf_sketch(symnmf_ctx* ctx, const symnmf_S* S, uint64_t omega_seed, int64_t width, float* Y);
+/* Scratch bytes of symnmf_sketch (-1: bad argument). */
+int64_t symnmf_sketch_workspace(const symnmf_ctx* ctx, const symnmf_S* S, int64_t width);
 
 /* Canonical coordinates of the rows of a sketch Y (n x w, device float32):
  * X (n x w, device float32) = [C, 0] with C = Z Z[anchors]^-1 (step 2 above;
@@ -490,6 +528,8 @@ symnmf_status symnmf_sketch(symnmf_ctx* ctx, const symnmf_S* S, uint64_t omega_s
  * selection order.  1 <= k <= w <= 64, n >= w.  ENUMERIC when Y^T Y has a
  * non-positive eigenvalue among the k largest or the anchor rows are linearly
  * dependent.  Synchronises. */
+/* Scratch bytes of symnmf_canonical (-1: bad argument). */
+int64_t symnmf_canonical_workspace(int64_t n, int64_t width, int64_t k);
 symnmf_status symnmf_canonical(symnmf_ctx* ctx, const float* Y, int64_t n, int64_t width, int64_t k, float* X,
                                int64_t* anchors);
 
@@ -498,6 +538,11 @@ symnmf_status symnmf_canonical(symnmf_ctx* ctx, const float* Y, int64_t n, int64
  * non-NULL) or the coordinates themselves clipped at zero (mlp NULL: the
  * network-free ablation), then the alpha rescaling; H0: device n x k float32.
  * The network's k must equal k.  Synchronises. */
+/* Scratch bytes of symnmf_warm_start (-1: bad argument): the sketch and the
+ * coordinates, plus the largest of the sketch, canonical and objective scratch
+ * used one after another (the network's activations are its own workspace,
+ * symnmf_mlp_reserve). */
+int64_t symnmf_warm_start_workspace(const symnmf_ctx* ctx, const symnmf_S* S, int64_t width, int64_t k);
 symnmf_status symnmf_warm_start(symnmf_ctx* ctx, const symnmf_S* S, symnmf_mlp* mlp, int64_t width, int64_t k,
                                 uint64_t omega_seed, float* H0);
 
@@ -576,8 +621,8 @@ symnmf_status symnmf_kmeans_centroids(symnmf_ctx* ctx, const symnmf_S* S, const 
  * J_{t-1} = 0) or max_iter pairs (the paper stops at a relative drop of
  * 1e-4).  labels: device int32, n entries; C (may be NULL): device n x K,
  * type as above, the last centroids.  stats (may be NULL).  ENOTCONV when
- * max_iter ends the run (labels, C and stats are still written).  Device
- * memory for the n x K factors is allocated and freed inside.
+ * max_iter ends the run (labels, C and stats are still written).  The
+ * n x K factors and the partials are scratch from the context pool.
  * Synchronises (once per iteration, to read J). */
 symnmf_status symnmf_kmeans(symnmf_ctx* ctx, const symnmf_S* S, int64_t K, uint64_t seed, const int64_t* init_rows,
                             double tol, int64_t max_iter, int32_t* labels, void* C, symnmf_kmeans_stats* stats);

@@ -98,6 +98,16 @@ SIGNATURES = {
     "symnmf_S_load": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i64, c_i64, c_i32, c_i64, c_vp, c_i64,
                               ctypes.POINTER(symnmf_S)]),
     "symnmf_init_H": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_i64, c_u64, c_vp]),
+    "symnmf_set_workspace": (c_i32, [c_vp, c_vp, c_i64]),
+    "symnmf_workspace_info": (c_i32, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
+    "symnmf_build_S_workspace": (c_i64, [ctypes.POINTER(symnmf_sbuild_params)]),
+    "symnmf_objective_workspace": (c_i64, [c_vp, ctypes.POINTER(symnmf_S), c_i64, c_i32]),
+    "symnmf_median_workspace": (c_i64, []),
+    "symnmf_sketch_workspace": (c_i64, [c_vp, ctypes.POINTER(symnmf_S), c_i64]),
+    "symnmf_canonical_workspace": (c_i64, [c_i64, c_i64, c_i64]),
+    "symnmf_warm_start_workspace": (c_i64, [c_vp, ctypes.POINTER(symnmf_S), c_i64, c_i64]),
+    "symnmf_subspace_error_workspace": (c_i64, [c_i64, c_i64]),
+    "symnmf_mlp_reserve": (c_i32, [c_vp, c_vp, c_i64, c_i32]),
     "symnmf_state_create": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_i64, ctypes.POINTER(symnmf_params), c_vp,
                                     c_i32, ctypes.POINTER(c_vp)]),
     "symnmf_state_destroy": (None, [c_vp]),
@@ -272,6 +282,55 @@ def symnmf_S_load(ctx, S_dense, dtype=S_FP32, row0=0, fp8_panel_rows=256) -> Mat
     _check(ctx, lib().symnmf_S_load(ctx, _ptr(S_dense), f64, n, row0, rows, dtype, fp8_panel_rows, _ptr(buf),
                                     nbytes, ctypes.byref(desc)))
     return Matrix(desc, buf)
+
+
+def symnmf_set_workspace(ctx, buf=None, nbytes=None):
+    """buf: a device tensor whose memory the context's scratch pool uses (kept alive by the caller), or None to
+    detach and let the library allocate its own pool."""
+    if buf is None:
+        _check(ctx, lib().symnmf_set_workspace(ctx, None, 0))
+    else:
+        nb = buf.numel() * buf.element_size() if nbytes is None else nbytes
+        _check(ctx, lib().symnmf_set_workspace(ctx, _ptr(buf), nb))
+
+
+def symnmf_workspace_info(ctx):
+    """(bytes held by the scratch pool, blocks it has taken from hipMalloc)."""
+    held, allocs = c_i64(), c_i64()
+    _check(ctx, lib().symnmf_workspace_info(ctx, ctypes.byref(held), ctypes.byref(allocs)))
+    return held.value, allocs.value
+
+
+def symnmf_build_S_workspace(n, T, kind=ABS_CORR, dtype=S_FP32, row0=0, rows=None, q=0.05, lower_tail=1,
+                             fp8_panel_rows=256, raw_marginals=0):
+    rows = n - row0 if rows is None else rows
+    p = symnmf_sbuild_params(kind=kind, dtype=dtype, n=n, T=T, row0=row0, rows=rows, q=q, lower_tail=lower_tail,
+                             raw_marginals=raw_marginals, fp8_panel_rows=fp8_panel_rows)
+    return lib().symnmf_build_S_workspace(ctypes.byref(p))
+
+
+def symnmf_objective_workspace(ctx, S: Matrix, k: int, h_is_f64: int = 0):
+    return lib().symnmf_objective_workspace(ctx, ctypes.byref(S.desc), k, h_is_f64)
+
+
+def symnmf_median_workspace():
+    return lib().symnmf_median_workspace()
+
+
+def symnmf_sketch_workspace(ctx, S: Matrix, width: int):
+    return lib().symnmf_sketch_workspace(ctx, ctypes.byref(S.desc), width)
+
+
+def symnmf_canonical_workspace(n: int, width: int, k: int):
+    return lib().symnmf_canonical_workspace(n, width, k)
+
+
+def symnmf_warm_start_workspace(ctx, S: Matrix, width: int, k: int):
+    return lib().symnmf_warm_start_workspace(ctx, ctypes.byref(S.desc), width, k)
+
+
+def symnmf_subspace_error_workspace(n: int, k: int):
+    return lib().symnmf_subspace_error_workspace(n, k)
 
 
 def symnmf_init_H(ctx, S: Matrix, k: int, seed: int, H):
@@ -492,6 +551,10 @@ def symnmf_mlp_destroy(m: Mlp):
     if m.handle is not None:
         lib().symnmf_mlp_destroy(m.handle)
         m.handle = None
+
+
+def symnmf_mlp_reserve(ctx, m: Mlp, rows: int, training: bool = False):
+    _check(ctx, lib().symnmf_mlp_reserve(ctx, m.handle, rows, 1 if training else 0))
 
 
 def symnmf_mlp_read(ctx, m: Mlp, which, dst):

@@ -454,24 +454,12 @@ inline unsigned blocks_for(int64_t m) { return (unsigned)std::max<int64_t>(1, st
 // Host side
 // --------------------------------------------------------------------------
 // Device allocations of one call, zero-filled, freed on scope exit.
+// Scratch of one K-means call, from the context pool (zeroed buffers).
 struct Scratch {
-    std::vector<void*> ptrs;
-    hipError_t err = hipSuccess;
-    hipStream_t sm;
-    explicit Scratch(hipStream_t s) : sm(s) {}
-    void* get(int64_t bytes) {
-        if (err != hipSuccess) return nullptr;
-        void* p = nullptr;
-        err = hipMalloc(&p, (size_t)std::max<int64_t>(bytes, 16));
-        if (err != hipSuccess) return nullptr;
-        ptrs.push_back(p);
-        err = hipMemsetAsync(p, 0, (size_t)std::max<int64_t>(bytes, 16), sm);
-        return p;
-    }
-    ~Scratch() {
-        if (!ptrs.empty()) (void)hipStreamSynchronize(sm);
-        for (void* p : ptrs) (void)hipFree(p);
-    }
+    CallScratch cs;
+    hipError_t& err;
+    explicit Scratch(symnmf_ctx* c) : cs(c), err(cs.err) {}
+    void* get(int64_t bytes) { return cs.get(bytes, true); }
 };
 
 // Everything one K-means call needs to multiply S by n x K factors.
@@ -959,7 +947,7 @@ symnmf_status symnmf_kmeans_seed_rows(uint64_t seed, int64_t n, int64_t K, int64
 symnmf_status symnmf_kmeans_seed_pp(symnmf_ctx* ctx, const symnmf_S* S, int64_t K, uint64_t seed, int64_t* rows) {
     if (!ctx) return SYMNMF_EINVAL;
     if (!rows) return fail(ctx, SYMNMF_EINVAL, "kmeans_seed_pp: rows is NULL");
-    Scratch sc(ctx->stream);
+    Scratch sc(ctx);
     KCall kc;
     // one-column passes: K = 1 sets up a 16-wide slice; the seed count is K
     symnmf_status r = kcall_setup(ctx, S, 1, sc, kc);
@@ -976,7 +964,7 @@ symnmf_status symnmf_kmeans_seed_pp(symnmf_ctx* ctx, const symnmf_S* S, int64_t 
 symnmf_status symnmf_row_norms(symnmf_ctx* ctx, const symnmf_S* S, double* norms) {
     if (!ctx) return SYMNMF_EINVAL;
     if (!norms) return fail(ctx, SYMNMF_EINVAL, "row_norms: norms is NULL");
-    Scratch sc(ctx->stream);
+    Scratch sc(ctx);
     KCall kc;
     symnmf_status r = kcall_setup(ctx, S, 1, sc, kc);
     if (r == SYMNMF_OK) r = compute_norms(ctx, kc, sc);
@@ -990,7 +978,7 @@ symnmf_status symnmf_kmeans_assign(symnmf_ctx* ctx, const symnmf_S* S, const voi
                                    void* best, double* J) {
     if (!ctx) return SYMNMF_EINVAL;
     if (!C || !labels) return fail(ctx, SYMNMF_EINVAL, "kmeans_assign: NULL argument");
-    Scratch sc(ctx->stream);
+    Scratch sc(ctx);
     KCall kc;
     symnmf_status r = kcall_setup(ctx, S, K, sc, kc);
     if (r != SYMNMF_OK) return r;
@@ -1016,7 +1004,7 @@ symnmf_status symnmf_kmeans_centroids(symnmf_ctx* ctx, const symnmf_S* S, const 
                                       const void* C_prev, void* C) {
     if (!ctx) return SYMNMF_EINVAL;
     if (!labels || !C) return fail(ctx, SYMNMF_EINVAL, "kmeans_centroids: NULL argument");
-    Scratch sc(ctx->stream);
+    Scratch sc(ctx);
     KCall kc;
     symnmf_status r = kcall_setup(ctx, S, K, sc, kc);
     if (r != SYMNMF_OK) return r;
@@ -1047,7 +1035,7 @@ symnmf_status symnmf_kmeans(symnmf_ctx* ctx, const symnmf_S* S, int64_t K, uint6
     if (!labels) return fail(ctx, SYMNMF_EINVAL, "kmeans: labels is NULL");
     if (!(tol >= 0.0) || !std::isfinite(tol) || max_iter < 0)
         return fail(ctx, SYMNMF_EINVAL, "kmeans: need tol >= 0 and max_iter >= 0");
-    Scratch sc(ctx->stream);
+    Scratch sc(ctx);
     KCall kc;
     symnmf_status r = kcall_setup(ctx, S, K, sc, kc);
     if (r != SYMNMF_OK) return r;
@@ -1072,7 +1060,7 @@ symnmf_status symnmf_spectral(symnmf_ctx* ctx, const symnmf_S* S, int64_t max_it
                               float* u1) {
     if (!ctx) return SYMNMF_EINVAL;
     if (max_iter < 1 || !(tol >= 0.0)) return fail(ctx, SYMNMF_EINVAL, "spectral: need max_iter >= 1, tol >= 0");
-    Scratch sc(ctx->stream);
+    Scratch sc(ctx);
     KCall kc;
     symnmf_status r = kcall_setup(ctx, S, 1, sc, kc);
     if (r != SYMNMF_OK) return r;
@@ -1085,7 +1073,7 @@ symnmf_status symnmf_spectral(symnmf_ctx* ctx, const symnmf_S* S, int64_t max_it
 symnmf_status symnmf_silhouette(symnmf_ctx* ctx, const symnmf_S* S, const int32_t* labels, int64_t K, double* sil) {
     if (!ctx) return SYMNMF_EINVAL;
     if (!labels || !sil) return fail(ctx, SYMNMF_EINVAL, "silhouette: NULL argument");
-    Scratch sc(ctx->stream);
+    Scratch sc(ctx);
     KCall kc;
     symnmf_status r = kcall_setup(ctx, S, K, sc, kc);
     if (r != SYMNMF_OK) return r;

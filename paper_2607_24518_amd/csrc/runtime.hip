@@ -35,6 +35,48 @@ struct ProfScope {
 };
 }  // namespace
 
+void* CallScratch::get(int64_t bytes, bool zero) {
+    const int64_t b = ws_round(bytes);
+    need += b;
+    if (err != hipSuccess) return nullptr;
+    symnmf_ctx* c = ctx_;
+    char* p = nullptr;
+    for (;;) {
+        if (c->ws_top_block < c->ws.size()) {
+            WsBlock& blk = c->ws[c->ws_top_block];
+            if (c->ws_top_off + b <= blk.bytes) {
+                p = blk.p + c->ws_top_off;
+                c->ws_top_off += b;
+                break;
+            }
+            ++c->ws_top_block;
+            c->ws_top_off = 0;
+            continue;
+        }
+        if (c->ws_attached) {
+            err = hipErrorOutOfMemory;
+            return nullptr;
+        }
+        const int64_t last = c->ws.empty() ? 0 : c->ws.back().bytes;
+        const int64_t nb = std::max<int64_t>({b, last, (int64_t)64 << 20});
+        void* q = nullptr;
+        err = hipMalloc(&q, (size_t)nb);
+        if (err != hipSuccess) return nullptr;
+        c->ws.push_back({(char*)q, nb, true});
+        ++c->ws_allocs;
+    }
+    if (zero) err = hipMemsetAsync(p, 0, (size_t)b, c->stream);
+    return err == hipSuccess ? p : nullptr;
+}
+
+symnmf_status scratch_fail(symnmf_ctx* ctx, const CallScratch& sc, const char* what) {
+    if (ctx->ws_attached && sc.err == hipErrorOutOfMemory)
+        return fail(ctx, SYMNMF_ENOMEM, "%s: the attached workspace is too small (the call needs %lld bytes)", what,
+                    (long long)sc.need);
+    return fail(ctx, sc.err == hipErrorOutOfMemory ? SYMNMF_ENOMEM : SYMNMF_EDEVICE, "%s: scratch: %s", what,
+                hipGetErrorString(sc.err));
+}
+
 namespace {
 
 constexpr int HCAP = 128;   // ring of per-step device statistics
@@ -177,7 +219,38 @@ symnmf_status symnmf_create(symnmf_ctx** out, int32_t device, void* hip_stream) 
     return SYMNMF_OK;
 }
 
-void symnmf_destroy(symnmf_ctx* ctx) { delete ctx; }
+void symnmf_destroy(symnmf_ctx* ctx) {
+    if (!ctx) return;
+    if (!ctx->ws.empty()) (void)hipStreamSynchronize(ctx->stream);
+    for (auto& b : ctx->ws)
+        if (b.owned) (void)hipFree(b.p);
+    delete ctx;
+}
+
+symnmf_status symnmf_set_workspace(symnmf_ctx* ctx, void* dev, int64_t bytes) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if ((dev == nullptr) != (bytes == 0) || bytes < 0)
+        return fail(ctx, SYMNMF_EINVAL, "set_workspace: give a device buffer and its size, or NULL and 0");
+    if (ctx->ws_top_block != 0 || ctx->ws_top_off != 0)
+        return fail(ctx, SYMNMF_EINVAL, "set_workspace: a call is using the pool");
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    if (!ctx->ws.empty()) HIP_OK(ctx, hipStreamSynchronize(ctx->stream));   // kernels may still read the old pool
+    for (auto& b : ctx->ws)
+        if (b.owned) (void)hipFree(b.p);
+    ctx->ws.clear();
+    ctx->ws_attached = dev != nullptr;
+    if (dev) ctx->ws.push_back({(char*)dev, bytes, false});
+    return SYMNMF_OK;
+}
+
+symnmf_status symnmf_workspace_info(symnmf_ctx* ctx, int64_t* held, int64_t* allocs) {
+    if (!ctx) return SYMNMF_EINVAL;
+    int64_t h = 0;
+    for (auto& b : ctx->ws) h += b.bytes;
+    if (held) *held = h;
+    if (allocs) *allocs = ctx->ws_allocs;
+    return SYMNMF_OK;
+}
 
 const char* symnmf_last_error(const symnmf_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
@@ -232,6 +305,45 @@ static BuildOut build_out(void* buf, const Layout& L, int64_t n, int64_t row0, i
     return o;
 }
 
+// Scratch of symnmf_build_S: Z (K x ldz), the FP64 sums, the FP8 panel maxima,
+// the input-check flags, the TPDM rank workspace and the bf16 operand planes.
+struct BuildWs {
+    int64_t K, Kpad, ldz, z, sums, pmax, bad, work, planes;
+};
+static bool build_ws(const symnmf_sbuild_params* p, BuildWs& w) {
+    if (!p || p->n < 1 || p->T < 2 || p->rows < 1 || elem_bytes(p->dtype) == 0) return false;
+    if (p->dtype == SYMNMF_S_FP8 && p->fp8_panel_rows < 1) return false;
+    w.K = p->T;
+    if (p->kind == SYMNMF_TPDM) w.K = (int64_t)std::floor(p->q * (double)p->T);
+    if (w.K < 1) return false;
+    const Layout L = s_layout(p->rows, p->n, p->dtype, p->fp8_panel_rows);
+    const int64_t zsz = p->dtype == SYMNMF_S_FP64 ? 8 : 4;
+    w.ldz = round_up(std::max(p->n, p->row0 + L.rows_pad), 256);
+    w.Kpad = round_up(w.K, 16);
+    w.z = w.Kpad * w.ldz * zsz;
+    BuildOut o;
+    o.rows = p->rows;
+    o.rows_pad = L.rows_pad;
+    o.ld = L.ld;
+    o.n = p->n;
+    o.row0 = p->row0;
+    o.dtype = p->dtype;
+    o.panel_rows = p->dtype == SYMNMF_S_FP8 ? p->fp8_panel_rows : 1;
+    w.sums = syrk_sum_words(o) * 8;
+    w.pmax = (p->dtype == SYMNMF_S_FP8 ? (p->rows + p->fp8_panel_rows - 1) / p->fp8_panel_rows : 1) * 4;
+    w.bad = 4;
+    w.work = p->kind == SYMNMF_TPDM ? tpdm_work_bytes(p->T, p->n, p->raw_marginals) : 0;
+    w.planes = (p->dtype == SYMNMF_S_BF16 || p->dtype == SYMNMF_S_FP8) ? syrk_split_ws_bytes(w.K, w.ldz) : 0;
+    return true;
+}
+
+int64_t symnmf_build_S_workspace(const symnmf_sbuild_params* p) {
+    BuildWs w;
+    if (!build_ws(p, w)) return -1;
+    return ws_sum({w.z, w.sums, w.pmax, w.bad}) + (w.work ? ws_round(w.work) : 0) +
+           (w.planes ? ws_round(w.planes) : 0);
+}
+
 symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuild_params* p, void* buf,
                              int64_t buf_bytes, symnmf_S* out) {
     if (!ctx) return SYMNMF_EINVAL;
@@ -263,34 +375,20 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
     HIP_OK(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     const int z_f64 = p->dtype == SYMNMF_S_FP64;
-    const int64_t zsz = z_f64 ? 8 : 4;
-    const int64_t ldz = round_up(std::max(n, p->row0 + L.rows_pad), 256);
-    const int64_t Kpad = round_up(K, 16);
+    BuildWs w;
+    if (!build_ws(p, w)) return fail(ctx, SYMNMF_EINVAL, "build_S: bad parameters");
+    const int64_t ldz = w.ldz, Kpad = w.Kpad;
     const BuildOut o = build_out(buf, L, n, p->row0, p->rows, p->dtype, p->fp8_panel_rows);
-    const int64_t nsum = syrk_sum_words(o);
-    const int64_t panels = p->dtype == SYMNMF_S_FP8 ? (p->rows + p->fp8_panel_rows - 1) / p->fp8_panel_rows : 1;
-    void *Z = nullptr, *work = nullptr, *sums = nullptr, *pmax = nullptr, *bad = nullptr;
-    auto cleanup = [&]() {
-        if (Z) (void)hipFree(Z);
-        if (work) (void)hipFree(work);
-        if (sums) (void)hipFree(sums);
-        if (pmax) (void)hipFree(pmax);
-        if (bad) (void)hipFree(bad);
-    };
+    CallScratch sc(ctx);
+    void* Z = sc.get(w.z);
+    void* sums = sc.get(w.sums);
+    void* pmax = sc.get(w.pmax);
+    void* bad = sc.get(w.bad);
+    void* work = w.work ? sc.get(w.work) : nullptr;
+    void* planes = w.planes ? sc.get(w.planes) : nullptr;
+    if (sc.err != hipSuccess) return scratch_fail(ctx, sc, "build_S");
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    chk(hipMalloc(&Z, Kpad * ldz * zsz));
-    chk(hipMalloc(&sums, nsum * 8));
-    chk(hipMalloc(&pmax, panels * 4));
-    chk(hipMalloc(&bad, 4));
-    if (p->kind == SYMNMF_TPDM) chk(hipMalloc(&work, tpdm_work_bytes(T, n, p->raw_marginals)));
-    if (e != hipSuccess) {
-        cleanup();
-        return fail(ctx, SYMNMF_ENOMEM, "build_S: device allocation failed: %s", hipGetErrorString(e));
-    }
-    chk(hipMemsetAsync(Z, 0, Kpad * ldz * zsz, st));
-    chk(hipMemsetAsync(pmax, 0, panels * 4, st));
-    chk(hipMemsetAsync(bad, 0, 4, st));
     chk(hipMemsetAsync(buf, 0, L.total, st));
     if (p->kind == SYMNMF_ABS_CORR) chk(launch_standardise(X, T, n, Z, z_f64, ldz, (int32_t*)bad, st));
     else {
@@ -302,23 +400,18 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
     chk(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
     chk(hipStreamSynchronize(st));
     if (e == hipSuccess && (hbad & BAD_NONFINITE)) {
-        cleanup();
         return fail(ctx, SYMNMF_ENUMERIC, "build_S: X holds a non-finite value");
     }
     if (e == hipSuccess && (hbad & BAD_NEGATIVE)) {
-        cleanup();
         return fail(ctx, SYMNMF_EINVAL, "build_S: raw TPDM marginals need X >= 0 in the chosen tail orientation");
     }
     if (e == hipSuccess && hbad) {
-        cleanup();
         return fail(ctx, SYMNMF_EINVAL, "build_S: %d zero-variance column(s)", hbad);
     }
     // S-building GEMM: split-precision bf16 MFMA for BF16 / FP8 storage, FP32
     // MFMA for FP32, FP64 FMAs for FP64
     const bool split = p->dtype == SYMNMF_S_BF16 || p->dtype == SYMNMF_S_FP8;
-    void* planes = nullptr;
     if (split && e == hipSuccess) {
-        chk(hipMalloc(&planes, syrk_split_ws_bytes(K, ldz)));
         chk(launch_syrk_split_store((const float*)Z, K, ldz, o, (double*)sums, (uint32_t*)pmax, planes, st));
     } else {
         chk(launch_syrk_store(Z, z_f64, Kpad, ldz, o, (double*)sums, (uint32_t*)pmax, st));
@@ -326,8 +419,6 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
     double hs[3] = {0, 0, 0};
     chk(hipMemcpyAsync(hs, sums, 24, hipMemcpyDeviceToHost, st));
     chk(hipStreamSynchronize(st));
-    if (planes) (void)hipFree(planes);
-    cleanup();
     if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "build_S: %s", hipGetErrorString(e));
     if (!std::isfinite(hs[0]) || !std::isfinite(hs[1])) return fail(ctx, SYMNMF_ENUMERIC, "build_S: non-finite S");
     return fill_descriptor(ctx, buf, n, p->row0, p->rows, p->dtype, p->kind, p->fp8_panel_rows, L, hs, out);
@@ -347,17 +438,15 @@ symnmf_status symnmf_S_load(symnmf_ctx* ctx, const void* src, int32_t src_is_f64
     hipStream_t st = ctx->stream;
     const BuildOut o = build_out(buf, L, n, row0, rows, dtype, fp8_panel_rows);
     const int64_t panels = dtype == SYMNMF_S_FP8 ? (rows + fp8_panel_rows - 1) / fp8_panel_rows : 1;
-    void *sums = nullptr, *pmax = nullptr;
-    HIP_OK(ctx, hipMalloc(&sums, (4 + 3 * L.rows_pad) * 8));
-    HIP_OK(ctx, hipMalloc(&pmax, panels * 4));
-    hipError_t e = hipMemsetAsync(pmax, 0, panels * 4, st);
-    if (e == hipSuccess) e = hipMemsetAsync(buf, 0, L.total, st);
+    CallScratch sc(ctx);
+    void* sums = sc.get((4 + 3 * L.rows_pad) * 8);
+    void* pmax = sc.get(panels * 4);
+    if (sc.err != hipSuccess) return scratch_fail(ctx, sc, "S_load");
+    hipError_t e = hipMemsetAsync(buf, 0, L.total, st);
     if (e == hipSuccess) e = launch_store_dense(src, src_is_f64, o, (double*)sums, (uint32_t*)pmax, st);
     double hs[3] = {0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(hs, sums, 24, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(sums);
-    (void)hipFree(pmax);
     if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "S_load: %s", hipGetErrorString(e));
     if (!std::isfinite(hs[0]) || !std::isfinite(hs[1])) return fail(ctx, SYMNMF_ENUMERIC, "S_load: non-finite S");
     return fill_descriptor(ctx, buf, n, row0, rows, dtype, SYMNMF_ABS_CORR, fp8_panel_rows, L, hs, out);
@@ -730,6 +819,33 @@ symnmf_status symnmf_state_read(symnmf_ctx* ctx, symnmf_state* st, int32_t which
 
 }  // extern "C"
 
+// Scratch of objective_terms: FP64 copy of H, the S.H partials, the per-slice
+// FP64 partials, the Gram, three effective Grams, the statistics; on the MFMA
+// path also the FP32 H and its chunk images.
+struct ObjWs {
+    int64_t hd, part, tg, ttr, tk, tb, g, gi, sc, hf, img;
+    bool mfma;
+};
+static ObjWs objective_ws(const symnmf_ctx* ctx, const symnmf_S* S, int64_t k, int32_t h_is_f64) {
+    ObjWs w;
+    const int64_t tiles = S->rows_pad / TR, chunks = S->ld / KC;
+    const int32_t P = ctx->cus * (ctx->wgs_per_cu > 0 ? ctx->wgs_per_cu : 2);
+    const int64_t hrows = std::max(round_up(S->n, PAD), S->row0 + S->rows_pad);
+    w.hd = hrows * k * 8;
+    w.part = ((int64_t)P + tiles) * TR * k * 8;
+    w.tg = tiles * k * k * 8;          // one partial per 256-row tile (objective_tiles_kernel)
+    w.ttr = tiles * 8;
+    w.tk = tiles * 8;
+    w.tb = tiles * 4;
+    w.g = k * k * 8;
+    w.gi = 3 * k * k * 8;
+    w.sc = 4 * 8;
+    w.mfma = !h_is_f64 && stream_acc64_supported(S->dtype, k);
+    w.hf = w.mfma ? hrows * k * 4 : 0;
+    w.img = w.mfma ? h_image_words(S->dtype, k, chunks) * 4 : 0;
+    return w;
+}
+
 symnmf_status objective_terms(symnmf_ctx* ctx, const symnmf_S* S, const void* H, int32_t h_is_f64, int64_t k,
                               double* tr, double* gram_norm2) {
     if (!ctx) return SYMNMF_EINVAL;
@@ -738,67 +854,57 @@ symnmf_status objective_terms(symnmf_ctx* ctx, const symnmf_S* S, const void* H,
     hipStream_t sm = ctx->stream;
     const int64_t tiles = S->rows_pad / TR, chunks = S->ld / KC;
     const int32_t P = ctx->cus * (ctx->wgs_per_cu > 0 ? ctx->wgs_per_cu : 2);
-    const int64_t hrows = std::max(round_up(S->n, PAD), S->row0 + S->rows_pad);
-    void *Hd = nullptr, *part = nullptr, *tg = nullptr, *ttr = nullptr, *tk = nullptr, *tb = nullptr, *g = nullptr,
-         *gi = nullptr, *sc = nullptr;
+    const ObjWs w = objective_ws(ctx, S, k, h_is_f64);
+    CallScratch scr(ctx);
+    void* Hd = scr.get(w.hd);
+    void* part = scr.get(w.part, false);
+    void* tg = scr.get(w.tg, false);
+    void* ttr = scr.get(w.ttr, false);
+    void* tk = scr.get(w.tk, false);
+    void* tb = scr.get(w.tb, false);
+    void* g = scr.get(w.g, false);
+    void* gi = scr.get(w.gi, false);
+    void* sc = scr.get(w.sc, false);
+    void* Hf = w.mfma ? scr.get(w.hf) : nullptr;
+    void* img = w.mfma ? scr.get(w.img, false) : nullptr;
+    if (scr.err != hipSuccess) return scratch_fail(ctx, scr, "objective");
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    chk(hipMalloc(&Hd, hrows * k * 8));
-    chk(hipMalloc(&part, ((int64_t)P + tiles) * TR * k * 8));
-    chk(hipMalloc(&tg, tiles * k * k * 8));
-    chk(hipMalloc(&ttr, tiles * 8));
-    chk(hipMalloc(&tk, tiles * 8));
-    chk(hipMalloc(&tb, tiles * 4));
-    chk(hipMalloc(&g, k * k * 8));
-    chk(hipMalloc(&gi, 3 * k * k * 8));
-    chk(hipMalloc(&sc, 4 * 8));
-    if (e == hipSuccess) {
-        chk(hipMemsetAsync(Hd, 0, hrows * k * 8, sm));
-        chk(launch_copy_h(H, h_is_f64, Hd, 1, S->n * k, sm));
-        PlanView pv = plan_view(nullptr, 1, (int32_t)tiles, (int32_t)chunks, P);
-        if (!h_is_f64 && stream_acc64_supported(S->dtype, k)) {
-            // MFMA products, FP32 within each 256-column chunk, FP64 across chunks
-            void *Hf = nullptr, *img = nullptr;
-            chk(hipMalloc(&Hf, hrows * k * 4));
-            chk(hipMalloc(&img, h_image_words(S->dtype, k, chunks) * 4));
-            chk(hipMemsetAsync(Hf, 0, hrows * k * 4, sm));
-            chk(launch_copy_h(H, 0, Hf, 0, S->n * k, sm));
-            chk(launch_h_image((const float*)Hf, S->dtype, k, chunks, 1.0f, (uint32_t*)img, sm));
-            chk(launch_stream_acc64(S->data, S->dtype, k, img, (double*)part, pv, sm));
-            chk(hipStreamSynchronize(sm));
-            if (Hf) (void)hipFree(Hf);
-            if (img) (void)hipFree(img);
-        } else {
-            chk(launch_stream(S->data, S->dtype, S->ld, Hd, 1, k, part, 1, pv, sm));
-        }
-        UpdateArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.rows = S->rows;
-        a.rows_pad = S->rows_pad;
-        a.n = S->n;
-        a.k = k;
-        a.row0 = S->row0;
-        a.H = Hd;
-        a.part = part;
-        a.fp8 = S->dtype == SYMNMF_S_FP8;
-        a.panel_scale = S->panel_scale;
-        a.diag = S->diag;
-        a.panel_rows = S->fp8_panel_rows > 0 ? S->fp8_panel_rows : 1;
-        a.tile_gram = (double*)tg;
-        a.tile_tr = (double*)ttr;
-        a.tile_kkt = (double*)tk;
-        a.tile_bad = (int32_t*)tb;
-        chk(launch_objective_tiles(a, pv, sm));
-        chk(launch_finalize(tiles, k, (double*)tg, (double*)ttr, (double*)tk, (int32_t*)tb, nullptr, nullptr,
-                            (double*)g, gi, 1, (double*)sc, sm));
+    chk(launch_copy_h(H, h_is_f64, Hd, 1, S->n * k, sm));
+    PlanView pv = plan_view(nullptr, 1, (int32_t)tiles, (int32_t)chunks, P);
+    if (w.mfma) {
+        // MFMA products, FP32 within each 256-column chunk, FP64 across chunks
+        chk(launch_copy_h(H, 0, Hf, 0, S->n * k, sm));
+        chk(launch_h_image((const float*)Hf, S->dtype, k, chunks, 1.0f, (uint32_t*)img, sm));
+        chk(launch_stream_acc64(S->data, S->dtype, k, img, (double*)part, pv, sm));
+    } else {
+        chk(launch_stream(S->data, S->dtype, S->ld, Hd, 1, k, part, 1, pv, sm));
     }
+    UpdateArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.rows = S->rows;
+    a.rows_pad = S->rows_pad;
+    a.n = S->n;
+    a.k = k;
+    a.row0 = S->row0;
+    a.H = Hd;
+    a.part = part;
+    a.fp8 = S->dtype == SYMNMF_S_FP8;
+    a.panel_scale = S->panel_scale;
+    a.diag = S->diag;
+    a.panel_rows = S->fp8_panel_rows > 0 ? S->fp8_panel_rows : 1;
+    a.tile_gram = (double*)tg;
+    a.tile_tr = (double*)ttr;
+    a.tile_kkt = (double*)tk;
+    a.tile_bad = (int32_t*)tb;
+    chk(launch_objective_tiles(a, pv, sm));
+    chk(launch_finalize(tiles, k, (double*)tg, (double*)ttr, (double*)tk, (int32_t*)tb, nullptr, nullptr,
+                        (double*)g, gi, 1, (double*)sc, sm));
     std::vector<double> gram(k * k);
     double d[4] = {0, 0, 0, 0};
     if (e == hipSuccess) chk(hipMemcpyAsync(gram.data(), g, k * k * 8, hipMemcpyDeviceToHost, sm));
     if (e == hipSuccess) chk(hipMemcpyAsync(d, sc, 32, hipMemcpyDeviceToHost, sm));
     if (e == hipSuccess) chk(hipStreamSynchronize(sm));
-    for (void* p : {Hd, part, tg, ttr, tk, tb, g, gi, sc})
-        if (p) (void)hipFree(p);
     if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "objective: %s", hipGetErrorString(e));
     double gn = 0.0;
     for (double v : gram) gn += v * v;
@@ -808,6 +914,13 @@ symnmf_status objective_terms(symnmf_ctx* ctx, const symnmf_S* S, const void* H,
 }
 
 extern "C" {
+
+int64_t symnmf_objective_workspace(const symnmf_ctx* ctx, const symnmf_S* S, int64_t k, int32_t h_is_f64) {
+    if (!ctx || !S || k < 1 || k > KMAX) return -1;
+    const ObjWs w = objective_ws(ctx, S, k, h_is_f64);
+    return ws_sum({w.hd, w.part, w.tg, w.ttr, w.tk, w.tb, w.g, w.gi, w.sc}) +
+           (w.mfma ? ws_sum({w.hf, w.img}) : 0);
+}
 
 symnmf_status symnmf_objective(symnmf_ctx* ctx, const symnmf_S* S, const void* H, int32_t h_is_f64, int64_t k,
                                double* f, double* E) {
@@ -821,19 +934,20 @@ symnmf_status symnmf_objective(symnmf_ctx* ctx, const symnmf_S* S, const void* H
     return SYMNMF_OK;
 }
 
+int64_t symnmf_median_workspace(void) { return ws_sum({select_tmp_bytes(), 8}); }
+
 symnmf_status symnmf_median_sq(symnmf_ctx* ctx, const float* g, int64_t m, float* out) {
     if (!ctx) return SYMNMF_EINVAL;
     if (!g || m < 1 || !out) return fail(ctx, SYMNMF_EINVAL, "median_sq: bad argument");
     HIP_OK(ctx, hipSetDevice(ctx->device));
-    void *tmp = nullptr, *res = nullptr;
-    HIP_OK(ctx, hipMalloc(&tmp, select_tmp_bytes()));
-    hipError_t e = hipMalloc(&res, 8);
+    CallScratch sc(ctx);
+    void* tmp = sc.get(select_tmp_bytes(), false);
+    void* res = sc.get(8, false);
+    if (sc.err != hipSuccess) return scratch_fail(ctx, sc, "median_sq");
     double v = 0.0;
-    if (e == hipSuccess) e = launch_select(g, 0, 1, m, (m - 1) / 2, tmp, (double*)res, ctx->stream);
+    hipError_t e = launch_select(g, 0, 1, m, (m - 1) / 2, tmp, (double*)res, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&v, res, 8, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    (void)hipFree(tmp);
-    if (res) (void)hipFree(res);
     if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "median_sq: %s", hipGetErrorString(e));
     *out = (float)v;
     return SYMNMF_OK;
@@ -1250,14 +1364,13 @@ void symnmf_sample_blocks(uint64_t seed, int64_t t, int32_t stream, int64_t nblo
 // decodes differently from the E4M3 definition (0 expected), or -1 on error.
 int32_t symnmf_selfcheck_fp8(symnmf_ctx* ctx) {
     if (!ctx) return -1;
-    void* bad = nullptr;
-    if (hipMalloc(&bad, 4) != hipSuccess) return -1;
+    CallScratch sc(ctx);
+    void* bad = sc.get(4);
+    if (sc.err != hipSuccess) return -1;
     int32_t h = -1;
-    hipError_t e = hipMemsetAsync(bad, 0, 4, ctx->stream);
-    if (e == hipSuccess) e = launch_fp8_decode_check((int32_t*)bad, ctx->stream);
+    hipError_t e = launch_fp8_decode_check((int32_t*)bad, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    (void)hipFree(bad);
     return e == hipSuccess ? h : -1;
 }
 

@@ -171,6 +171,15 @@ void symnmf_mlp_destroy(symnmf_mlp* m) {
     delete m;
 }
 
+symnmf_status symnmf_mlp_reserve(symnmf_ctx* ctx, symnmf_mlp* m, int64_t rows, int32_t training) {
+    if (!ctx || !m || m->ctx != ctx || rows < 1) return ctx ? fail(ctx, SYMNMF_EINVAL, "mlp_reserve: bad argument")
+                                                          : SYMNMF_EINVAL;
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    symnmf_status s = ensure_fwd(m, rows);
+    if (s == SYMNMF_OK && training) s = ensure_train(m, rows);
+    return s;
+}
+
 symnmf_status symnmf_mlp_read(symnmf_ctx* ctx, const symnmf_mlp* m, int32_t which, float* dst) {
     if (!ctx) return SYMNMF_EINVAL;
     if (!m || !dst || m->ctx != ctx) return fail(ctx, SYMNMF_EINVAL, "mlp_read: bad argument");
@@ -273,6 +282,54 @@ symnmf_status symnmf_mlp_train_step(symnmf_ctx* ctx, symnmf_mlp* m, const float*
     return SYMNMF_OK;
 }
 
+// Scratch of symnmf_sketch: Omega (every column of S), the S.Omega partials and
+// the chunk images of Omega.
+struct SketchWs {
+    int64_t om, part, img;
+};
+static SketchWs sketch_ws(const symnmf_ctx* ctx, const symnmf_S* S, int64_t width) {
+    SketchWs w;
+    const int64_t tiles = S->rows_pad / TR, chunks = S->ld / KC;
+    const int32_t P = ctx->cus * (ctx->wgs_per_cu > 0 ? ctx->wgs_per_cu : stream_wgs_per_cu(S->dtype, width));
+    const int64_t hrows = std::max(S->ld, S->row0 + S->rows_pad);
+    w.om = hrows * width * 4;
+    w.part = ((int64_t)P + tiles) * TR * width * 4;
+    w.img = stream_uses_mfma(S->dtype, 0, 0, width) ? h_image_words(S->dtype, width, chunks) * 4 : 0;
+    return w;
+}
+
+// Scratch of symnmf_canonical.
+static int64_t canonical_ws(int64_t n, int64_t width, int64_t k) {
+    const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    return ws_sum({xty_work_doubles(n, width, width) * 8, width * width * 8, width * width * 8, width * k * 8, k * 8, 8,
+                   n * k * 8, nb * 8, nb * 8, k * 8, width * k * 8});
+}
+
+int64_t symnmf_sketch_workspace(const symnmf_ctx* ctx, const symnmf_S* S, int64_t width) {
+    if (!ctx || !S || width < 1 || width > KMAX) return -1;
+    const SketchWs w = sketch_ws(ctx, S, width);
+    return ws_sum({w.om, w.part}) + (w.img ? ws_round(w.img) : 0);
+}
+
+int64_t symnmf_canonical_workspace(int64_t n, int64_t width, int64_t k) {
+    if (n < 1 || width < 1 || width > KMAX || k < 1 || k > width) return -1;
+    return canonical_ws(n, width, k);
+}
+
+int64_t symnmf_warm_start_workspace(const symnmf_ctx* ctx, const symnmf_S* S, int64_t width, int64_t k) {
+    if (!ctx || !S || width < 1 || width > KMAX || k < 1 || k > width) return -1;
+    // Y and the coordinates, then (one at a time) the sketch, the canonical
+    // coordinates and the objective terms of the alpha rescaling
+    const int64_t inner = std::max({symnmf_sketch_workspace(ctx, S, width), canonical_ws(S->n, width, k),
+                                    symnmf_objective_workspace(ctx, S, k, 0)});
+    return ws_sum({S->n * width * 4, S->n * width * 4}) + inner;
+}
+
+int64_t symnmf_subspace_error_workspace(int64_t n, int64_t k) {
+    if (n < 1 || k < 1 || k > KMAX) return -1;
+    return ws_round((6 * k * k + k + 1 + xty_work_doubles(n, k, k)) * 8 + 16);
+}
+
 symnmf_status symnmf_sketch(symnmf_ctx* ctx, const symnmf_S* S, uint64_t omega_seed, int64_t width, float* Y) {
     if (!ctx) return SYMNMF_EINVAL;
     if (!S || !Y || width < 1 || width > KMAX) return fail(ctx, SYMNMF_EINVAL, "sketch: bad argument");
@@ -283,13 +340,15 @@ symnmf_status symnmf_sketch(symnmf_ctx* ctx, const symnmf_S* S, uint64_t omega_s
     const int32_t P = ctx->cus * (ctx->wgs_per_cu > 0 ? ctx->wgs_per_cu : stream_wgs_per_cu(S->dtype, width));
     const bool mfma = stream_uses_mfma(S->dtype, 0, 0, width) != 0;
     const int64_t hrows = std::max(S->ld, S->row0 + S->rows_pad);
-    void *Om = nullptr, *part = nullptr, *img = nullptr;
+    const SketchWs ws = sketch_ws(ctx, S, width);
+    CallScratch sc(ctx);
+    void* Om = sc.get(ws.om, false);
+    void* part = sc.get(ws.part, false);
+    void* img = mfma ? sc.get(ws.img, false) : nullptr;
+    if (sc.err != hipSuccess) return scratch_fail(ctx, sc, "sketch");
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    chk(hipMalloc(&Om, hrows * width * 4));
-    chk(hipMalloc(&part, ((int64_t)P + tiles) * TR * width * 4));
-    if (mfma) chk(hipMalloc(&img, h_image_words(S->dtype, width, chunks) * 4));
-    if (e == hipSuccess) {
+    {
         chk(launch_omega(omega_seed, S->n, hrows, (int)width, (float*)Om, sm));
         if (mfma) chk(launch_h_image((const float*)Om, S->dtype, width, chunks, 1.0f, (uint32_t*)img, sm));
         PlanView pv = plan_view(nullptr, 1, (int32_t)tiles, (int32_t)chunks, P);
@@ -299,7 +358,6 @@ symnmf_status symnmf_sketch(symnmf_ctx* ctx, const symnmf_S* S, uint64_t omega_s
                             S->fp8_panel_rows > 0 ? S->fp8_panel_rows : 1, Y, sm));
         chk(hipStreamSynchronize(sm));
     }
-    free_all({Om, part, img});
     if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "sketch: %s", hipGetErrorString(e));
     return SYMNMF_OK;
 }
@@ -312,23 +370,23 @@ symnmf_status symnmf_canonical(symnmf_ctx* ctx, const float* Y, int64_t n, int64
     HIP_OK(ctx, hipSetDevice(ctx->device));
     hipStream_t sm = ctx->stream;
     const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
-    void *work = nullptr, *G = nullptr, *V = nullptr, *M = nullptr, *lam = nullptr, *status = nullptr, *R = nullptr,
-         *bval = nullptr, *bidx = nullptr, *pick = nullptr, *W = nullptr;
+    CallScratch sc(ctx);
+    void* work = sc.get(xty_work_doubles(n, width, width) * 8, false);
+    void* G = sc.get(width * width * 8, false);
+    void* V = sc.get(width * width * 8, false);
+    void* M = sc.get(width * k * 8, false);
+    void* lam = sc.get(k * 8, false);
+    void* status = sc.get(8);
+    void* R = sc.get(n * k * 8, false);
+    void* bval = sc.get(nb * 8, false);
+    void* bidx = sc.get(nb * 8, false);
+    void* pick = sc.get(k * 8, false);
+    void* W = sc.get(width * k * 8, false);
+    if (sc.err != hipSuccess) return scratch_fail(ctx, sc, "canonical");
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    chk(hipMalloc(&work, xty_work_doubles(n, width, width) * 8));
-    chk(hipMalloc(&G, width * width * 8));
-    chk(hipMalloc(&V, width * width * 8));
-    chk(hipMalloc(&M, width * k * 8));
-    chk(hipMalloc(&lam, k * 8));
-    chk(hipMalloc(&status, 8));
-    chk(hipMalloc(&R, n * k * 8));
-    chk(hipMalloc(&bval, nb * 8));
-    chk(hipMalloc(&bidx, nb * 8));
-    chk(hipMalloc(&pick, k * 8));
-    chk(hipMalloc(&W, width * k * 8));
     int32_t st[2] = {0, 0};
-    if (e == hipSuccess) {
+    {
         chk(launch_xty(Y, width, width, Y, width, width, n, (double*)work, (double*)G, sm));
         chk(launch_jacobi_topk((const double*)G, width, k, (double*)V, (double*)M, (double*)lam, (int32_t*)status, sm));
         chk(launch_project_rows(Y, n, width, (const double*)M, k, k, 1, R, sm));
@@ -340,7 +398,6 @@ symnmf_status symnmf_canonical(symnmf_ctx* ctx, const float* Y, int64_t n, int64
         chk(hipMemcpyAsync(st, status, 8, hipMemcpyDeviceToHost, sm));
         chk(hipStreamSynchronize(sm));
     }
-    free_all({work, G, V, M, lam, status, R, bval, bidx, pick, W});
     if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "canonical: %s", hipGetErrorString(e));
     if (st[0] == 1) return fail(ctx, SYMNMF_ENUMERIC, "canonical: Y^T Y has a non-positive eigenvalue among the top k");
     if (st[0] == 2) return fail(ctx, SYMNMF_ENUMERIC, "canonical: Jacobi sweeps did not converge");
@@ -360,12 +417,10 @@ symnmf_status symnmf_warm_start(symnmf_ctx* ctx, const symnmf_S* S, symnmf_mlp* 
     HIP_OK(ctx, hipSetDevice(ctx->device));
     hipStream_t sm = ctx->stream;
     const int64_t n = S->n;
-    float *Y = nullptr, *X = nullptr;
-    HIP_OK(ctx, hipMalloc((void**)&Y, n * width * 4));
-    if (hipMalloc((void**)&X, n * width * 4) != hipSuccess) {
-        (void)hipFree(Y);
-        return fail(ctx, SYMNMF_ENOMEM, "warm_start: out of device memory");
-    }
+    CallScratch sc(ctx);
+    float* Y = (float*)sc.get(n * width * 4, false);
+    float* X = (float*)sc.get(n * width * 4, false);
+    if (sc.err != hipSuccess) return scratch_fail(ctx, sc, "warm_start");
     symnmf_status s = symnmf_sketch(ctx, S, omega_seed, width, Y);
     if (s == SYMNMF_OK) s = symnmf_canonical(ctx, Y, n, width, k, X, nullptr);
     if (s == SYMNMF_OK) {
@@ -375,9 +430,6 @@ symnmf_status symnmf_warm_start(symnmf_ctx* ctx, const symnmf_S* S, symnmf_mlp* 
     }
     double tr = 0.0, gn = 0.0;
     if (s == SYMNMF_OK) s = objective_terms(ctx, S, H0, 0, k, &tr, &gn);
-    (void)hipStreamSynchronize(sm);
-    (void)hipFree(Y);
-    (void)hipFree(X);
     if (s != SYMNMF_OK) return s;
     if (!(gn > 0.0) || !std::isfinite(gn) || !std::isfinite(tr))
         return fail(ctx, SYMNMF_ENUMERIC, "warm_start: the initial factor is zero or non-finite");
@@ -394,10 +446,11 @@ symnmf_status symnmf_subspace_error(symnmf_ctx* ctx, const float* A, const float
     HIP_OK(ctx, hipSetDevice(ctx->device));
     hipStream_t sm = ctx->stream;
     const int64_t kk = k * k;
-    double* d = nullptr;
     // AtA, BtB, AtB, V, MA, MB, lam(k), overlap(1), work
     const int64_t work = xty_work_doubles(n, k, k);
-    HIP_OK(ctx, hipMalloc((void**)&d, (6 * kk + k + 1 + work) * 8 + 16));
+    CallScratch sc(ctx);
+    double* d = (double*)sc.get((6 * kk + k + 1 + work) * 8 + 16);
+    if (sc.err != hipSuccess) return scratch_fail(ctx, sc, "subspace_error");
     double *AtA = d, *BtB = d + kk, *AtB = d + 2 * kk, *V = d + 3 * kk, *MA = d + 4 * kk, *MB = d + 5 * kk;
     double *lam = d + 6 * kk, *ov = lam + k, *wk = ov + 1;
     int32_t* status = (int32_t*)(wk + work);
@@ -414,7 +467,6 @@ symnmf_status symnmf_subspace_error(symnmf_ctx* ctx, const float* A, const float
     chk(hipMemcpyAsync(&overlap, ov, 8, hipMemcpyDeviceToHost, sm));
     chk(hipMemcpyAsync(st, status, 8, hipMemcpyDeviceToHost, sm));
     chk(hipStreamSynchronize(sm));
-    (void)hipFree(d);
     if (e != hipSuccess) return fail(ctx, SYMNMF_EDEVICE, "subspace_error: %s", hipGetErrorString(e));
     if (st[0] || st[1]) return fail(ctx, SYMNMF_ENUMERIC, "subspace_error: a factor does not have full column rank");
     *out = std::sqrt(std::max(0.0, 2.0 * (double)k - 2.0 * overlap) / (2.0 * (double)k));
