@@ -156,7 +156,8 @@ def ttt_leg(sym, torch, ctx, X, stores, k, H0, max_steps):
     ref = studies.committed_reference(0, n, 2500, 32, k, 0)
     if ref is None:
         return None
-    f_dev, _, Wref, ref_s = studies.fp64_reference(ctx, X, 0, k, ref["rho"], ref["iterations"], H0, {"kind": 0})
+    f_dev, _, Wref, ref_s, _, _ = studies.fp64_reference(ctx, X, 0, k, H0, {"kind": 0},
+                                                         [[(f"admm{ref['rho']:g}", ref["iterations"])]])
     f_ref = ref["f_ref"]
     S32 = stores["fp32"]
 

@@ -487,6 +487,14 @@ void symnmf_mlp_destroy(symnmf_mlp* mlp);
  * 1 = gradient of the last training step, 2 = AdamW first moment, 3 = second
  * moment.  Asynchronous. */
 symnmf_status symnmf_mlp_read(symnmf_ctx* ctx, const symnmf_mlp* mlp, int32_t which, float* dst);
+/* Output form of the network: residual = 0, A = softplus(z) (the default);
+ * residual = 1, A = max(C + z, 0) with C the first k columns of the network
+ * input (the canonical coordinates) and z the last layer's output, so the
+ * network learns a correction to the network-free start max(C, 0) and
+ * reproduces it exactly when the last layer is zero.  Applies to
+ * symnmf_mlp_forward, symnmf_mlp_train_step and symnmf_warm_start.  EINVAL
+ * for residual not in {0, 1} or k > width. */
+symnmf_status symnmf_mlp_set_output(symnmf_ctx* ctx, symnmf_mlp* mlp, int32_t residual);
 /* Grow the network's activation buffers (part of the network object's
  * workspace, freed by symnmf_mlp_destroy) to ``rows`` rows for inference, and
  * with ``training`` also for symnmf_mlp_train_step, so that later calls of at

@@ -12,7 +12,11 @@ Pieces, in the order the warm start applies them:
    sum_i (Y v_c)_i^3 > 0); the successive projection algorithm (Gillis &
    Vavasis 2014) picks k anchor rows of Z; rows are expressed in the anchor
    basis, C = Z A^-1, and padded with zeros to the network width.
-3. MLP 64 -> 256 -> 256 -> k with exact GELU x Phi(x), softplus output.
+3. MLP 64 -> 256 -> 256 -> k with exact GELU x Phi(x), softplus output; or,
+   in the residual form, A = max(C + z, 0) with C the first k input
+   coordinates and z the last layer's output (the network then learns a
+   correction to the network-free start max(C, 0), which it reproduces
+   exactly when the last layer is zero).
 4. Scale: H0 = alpha A with alpha^2 = tr(A^T S A) / ||A^T A||_F^2, the
    minimiser of ||S - alpha^2 A A^T||_F^2 over alpha.
 Training: permutation-invariant Gram loss
@@ -137,14 +141,17 @@ def init_params_counter(k: int, seed: int, width: int = 64, hidden: int = 256):
     return P
 
 
-def forward(P, X):
+def forward(P, X, residual: bool = False):
     z1 = X @ P["W1"].T + P["b1"]
     a1 = gelu(z1)
     z2 = a1 @ P["W2"].T + P["b2"]
     a2 = gelu(z2)
     z3 = a2 @ P["W3"].T + P["b3"]
-    A = softplus(z3)
-    return A, dict(X=X, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3)
+    if residual:
+        A = np.maximum(X[:, :z3.shape[1]] + z3, 0.0)
+    else:
+        A = softplus(z3)
+    return A, dict(X=X, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3, residual=residual)
 
 
 def gram_loss(A, B):
@@ -169,7 +176,11 @@ def gram_cos_loss(A, B):
 
 
 def backward(P, cache, dA):
-    d3 = dA * sigmoid(cache["z3"])
+    if cache.get("residual"):
+        k = dA.shape[1]
+        d3 = dA * (cache["X"][:, :k] + cache["z3"] > 0.0)
+    else:
+        d3 = dA * sigmoid(cache["z3"])
     g = {"W3": d3.T @ cache["a2"], "b3": d3.sum(axis=0)}
     da2 = d3 @ P["W3"]
     d2 = da2 * gelu_grad(cache["z2"])
@@ -215,7 +226,7 @@ def bf16_weights(P):
     return {name: (to_bf16(v) if name.startswith("W") else v) for name, v in P.items()}
 
 
-def warm_start(S, k: int, seed: int, P=None, width: int = 64):
+def warm_start(S, k: int, seed: int, P=None, width: int = 64, residual: bool = False):
     """H0 = alpha A with A = network(canonical coordinates of S Omega) using the
     BF16-rounded weights, or A = the coordinates clipped at zero when P is None."""
     S = np.asarray(S, dtype=np.float64)
@@ -224,5 +235,5 @@ def warm_start(S, k: int, seed: int, P=None, width: int = 64):
     if P is None:
         A = np.maximum(X[:, :k], 0.0)
     else:
-        A, _ = forward(bf16_weights(P), X)
+        A, _ = forward(bf16_weights(P), X, residual)
     return alpha_rescale(S, A) * A, anchors

@@ -108,6 +108,7 @@ SIGNATURES = {
     "symnmf_warm_start_workspace": (c_i64, [c_vp, ctypes.POINTER(symnmf_S), c_i64, c_i64]),
     "symnmf_subspace_error_workspace": (c_i64, [c_i64, c_i64]),
     "symnmf_mlp_reserve": (c_i32, [c_vp, c_vp, c_i64, c_i32]),
+    "symnmf_mlp_set_output": (c_i32, [c_vp, c_vp, c_i32]),
     "symnmf_state_create": (c_i32, [c_vp, ctypes.POINTER(symnmf_S), c_i64, ctypes.POINTER(symnmf_params), c_vp,
                                     c_i32, ctypes.POINTER(c_vp)]),
     "symnmf_state_destroy": (None, [c_vp]),
@@ -551,6 +552,10 @@ def symnmf_mlp_destroy(m: Mlp):
     if m.handle is not None:
         lib().symnmf_mlp_destroy(m.handle)
         m.handle = None
+
+
+def symnmf_mlp_set_output(ctx, m: Mlp, residual: bool):
+    _check(ctx, lib().symnmf_mlp_set_output(ctx, m.handle, 1 if residual else 0))
 
 
 def symnmf_mlp_reserve(ctx, m: Mlp, rows: int, training: bool = False):

@@ -426,6 +426,10 @@ hipError_t launch_gemm(int ta, int tb, int b_bf16, int epi, const float* A, cons
 // dZ = dA * f'(Z): mode 1 GELU, mode 2 softplus
 hipError_t launch_act_backward(const float* dA, const float* Z, float* dZ, int64_t m, int mode, hipStream_t stream);
 hipError_t launch_colsum(const float* X, int64_t m, int64_t ncol, float* out, hipStream_t stream);
+// residual output A = max(C + z, 0) (A holds z on entry; C = first k columns of X) and its backward
+hipError_t launch_residual_relu(const float* X, int64_t ldx, float* A, int64_t rows, int64_t k, hipStream_t stream);
+hipError_t launch_residual_relu_backward(const float* dA, const float* X, int64_t ldx, const float* Z, float* dZ,
+                                         int64_t rows, int64_t k, hipStream_t stream);
 hipError_t launch_adamw(float* P, const float* G, float* M, float* V, int64_t m, int64_t n_decay, float lr, float b1,
                         float b2, float eps, float wd, int64_t t, hipStream_t stream);
 hipError_t launch_to_bf16(const float* x, uint16_t* y, int64_t m, hipStream_t stream);

@@ -208,6 +208,45 @@ hipError_t launch_act_backward(const float* dA, const float* Z, float* dZ, int64
     return hipGetLastError();
 }
 
+// Residual output A = max(C + z, 0), C the first k columns of the network input
+// X (leading dimension ldx): A holds z on entry (rows x k).
+__global__ void residual_relu_kernel(const float* __restrict__ X, int64_t ldx, float* __restrict__ A, int64_t rows,
+                                     int k) {
+    const int64_t m = rows * k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / k;
+        const float v = X[r * ldx + (i - r * k)] + A[i];
+        A[i] = v > 0.0f ? v : 0.0f;
+    }
+}
+
+// dZ = dA [C + z > 0]
+__global__ void residual_relu_backward_kernel(const float* __restrict__ dA, const float* __restrict__ X, int64_t ldx,
+                                              const float* __restrict__ Z, float* __restrict__ dZ, int64_t rows,
+                                              int k) {
+    const int64_t m = rows * k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / k;
+        dZ[i] = X[r * ldx + (i - r * k)] + Z[i] > 0.0f ? dA[i] : 0.0f;
+    }
+}
+
+hipError_t launch_residual_relu(const float* X, int64_t ldx, float* A, int64_t rows, int64_t k, hipStream_t stream) {
+    int64_t blocks = (rows * k + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(residual_relu_kernel, dim3(blocks), dim3(256), 0, stream, X, ldx, A, rows, (int)k);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_relu_backward(const float* dA, const float* X, int64_t ldx, const float* Z, float* dZ,
+                                         int64_t rows, int64_t k, hipStream_t stream) {
+    int64_t blocks = (rows * k + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(residual_relu_backward_kernel, dim3(blocks), dim3(256), 0, stream, dA, X, ldx, Z, dZ, rows,
+                       (int)k);
+    return hipGetLastError();
+}
+
 // column sums of an (m x ncol) FP32 matrix (bias gradients), FP64 accumulation
 __global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ X, int64_t m, int ncol, float* __restrict__ out) {
     __shared__ double red[4][64];

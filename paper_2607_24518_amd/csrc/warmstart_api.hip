@@ -15,6 +15,7 @@ struct symnmf_mlp {
     float *P = nullptr, *G = nullptr, *Mm = nullptr, *V = nullptr;
     uint16_t* Wb = nullptr;   // BF16 copies of W1, W2, W3
     bool bf16_stale = true;
+    int32_t residual = 0;     // output max(C + z, 0) over the input's first k columns instead of softplus(z)
     int64_t t = 0;            // AdamW steps taken
     float* split_ws = nullptr;
     int64_t split_floats = 0;
@@ -93,8 +94,9 @@ symnmf_status forward(symnmf_mlp* m, const float* X, int64_t rows, bool bf16, bo
                             1.0f, nullptr, 0, sm));
     HIP_OK(ctx, launch_gemm(0, 0, b, 1, m->a1, W2, m->P + m->off_b2(), m->a2, train ? m->z2 : nullptr, rows, m->h,
                             m->h, 1.0f, nullptr, 0, sm));
-    HIP_OK(ctx, launch_gemm(0, 0, b, 2, m->a2, W3, m->P + m->off_b3(), A, train ? m->z3 : nullptr, rows, m->k, m->h,
-                            1.0f, nullptr, 0, sm));
+    HIP_OK(ctx, launch_gemm(0, 0, b, m->residual ? 0 : 2, m->a2, W3, m->P + m->off_b3(), A, train ? m->z3 : nullptr,
+                            rows, m->k, m->h, 1.0f, nullptr, 0, sm));
+    if (m->residual) HIP_OK(ctx, launch_residual_relu(X, m->w, A, rows, m->k, sm));
     return SYMNMF_OK;
 }
 
@@ -169,6 +171,15 @@ void symnmf_mlp_destroy(symnmf_mlp* m) {
     free_all({m->P, m->G, m->Mm, m->V, m->Wb, m->split_ws, m->small, m->a1, m->a2, m->z1, m->z2, m->z3, m->out, m->dA,
               m->d3, m->da2});
     delete m;
+}
+
+symnmf_status symnmf_mlp_set_output(symnmf_ctx* ctx, symnmf_mlp* m, int32_t residual) {
+    if (!ctx) return SYMNMF_EINVAL;
+    if (!m || m->ctx != ctx || (residual != 0 && residual != 1))
+        return fail(ctx, SYMNMF_EINVAL, "mlp_set_output: bad argument");
+    if (residual && m->k > m->w) return fail(ctx, SYMNMF_EINVAL, "mlp_set_output: the residual form needs k <= width");
+    m->residual = residual;
+    return SYMNMF_OK;
 }
 
 symnmf_status symnmf_mlp_reserve(symnmf_ctx* ctx, symnmf_mlp* m, int64_t rows, int32_t training) {
@@ -258,7 +269,8 @@ symnmf_status symnmf_mlp_train_step(symnmf_ctx* ctx, symnmf_mlp* m, const float*
     if (!std::isfinite(L)) return fail(ctx, SYMNMF_ENUMERIC, "mlp_train_step: non-finite loss");
     // backward
     HIP_OK(ctx, launch_gram_loss_grad(m->out, B, AtA, AtB, k, rows, (float)ca, (float)cb, m->dA, sm));
-    HIP_OK(ctx, launch_act_backward(m->dA, m->z3, m->d3, rows * k, 2, sm));
+    if (m->residual) HIP_OK(ctx, launch_residual_relu_backward(m->dA, X, w, m->z3, m->d3, rows, k, sm));
+    else HIP_OK(ctx, launch_act_backward(m->dA, m->z3, m->d3, rows * k, 2, sm));
     HIP_OK(ctx, launch_gemm(1, 1, 0, 0, m->d3, m->a2, nullptr, m->G + m->off_W3(), nullptr, k, h, rows, 1.0f,
                             m->split_ws, m->split_floats, sm));
     HIP_OK(ctx, launch_colsum(m->d3, rows, k, m->G + m->off_b3(), sm));

@@ -98,11 +98,17 @@ def ttt_scan(objective_of, store, nsave, f_ref, tol, every, times):
 
 
 def ttt_run(ctx, S, k, params, init, objective_of, f_ref, tol, max_steps, every, store, S_hi=None,
-            tau_switch=None):
-    """Trace from init(H), then the time to (objective_of(H_t) - f_ref) / f_ref <= tol."""
+            tau_switch=None, more_tols=()):
+    """Trace from init(H), then the time to (objective_of(H_t) - f_ref) / f_ref <= tol
+    (and to each of ``more_tols``, under "at_tol")."""
     times, certified, t_init, switched = ttt_trace(ctx, S, k, params, init, max_steps, every, store, S_hi,
                                                    tau_switch)
     entry = ttt_scan(objective_of, store, max_steps // every, f_ref, tol, every, times)
+    if more_tols:
+        entry["at_tol"] = {}
+        for t2 in more_tols:
+            e2 = ttt_scan(objective_of, store, max_steps // every, f_ref, t2, every, times)
+            entry["at_tol"][f"{t2:g}"] = {q: e2[q] for q in ("iters", "seconds") if q in e2} or None
     entry.update(init_seconds=round(t_init, 4), certified_at=certified, times=times)
     if S_hi is not None:
         entry.update(switched_at=switched)
@@ -148,14 +154,15 @@ def variant_params(variant, eta_base, seed=0):
 
 
 def ttt_instance(args):
-    """Returns of the time-to-tolerance workload (generated on the CPU, so the
-    instance is the one the oracle's committed reference was computed on) and
-    the S kind."""
+    """Returns of the time-to-tolerance workload and the S kind.  The |corr|
+    panel is generated on the CPU (the instance the oracle's committed
+    reference was computed on); the TPDM panel (T x n = 2e9 Student-t draws,
+    no oracle reference at this size) on the GPU."""
     import synth
 
     if args.ttt_kind == "tpdm":
         inst = synth.tpdm_returns(args.seed, T=args.T, n=args.n, groups=args.groups, nu=2.5, common=True,
-                                  device="cpu")
+                                  device="cuda:0")
         return inst.X, 1
     return synth.overlap_returns(args.seed, T=args.T, n=args.n, groups=args.groups, device="cpu").X, 0
 
@@ -193,30 +200,45 @@ def init_factor(ctx, S, k, seed, H, mean=None):
     return sym.symnmf_init_H(ctx, sym.Matrix(d, S.buf), k, seed, H)
 
 
-def fp64_reference(ctx, X, kind, k, rho, iters, H0, build):
-    """FP64 ADMM (FP64 storage and state) from H0 for ``iters`` iterations:
-    (objective of the last iterate, lowest objective seen, the last iterate
-    as FP32 n x k, seconds)."""
+def fp64_reference(ctx, X, kind, k, H0, build, plans):
+    """FP64 runs (FP64 storage and state) from H0.  ``plans``: list of
+    reference plans, each a list of stages (variant name, iterations) run one
+    after the other, every stage starting from the previous stage's last
+    iterate (e.g. [("admm500", 1500)] or [("adam", 12000), ("admm50", 3000)]).
+    The plan that ends lowest is the reference: (objective of its last
+    iterate, lowest objective it saw, its last iterate as FP32 n x k, seconds,
+    its description, the relative drop of f over its last 1000 iterations)."""
     import torch
     import paper_2607_24518_amd as sym
 
     t0 = time.time()
     S64 = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP64, **build)
-    st = sym.symnmf_state_create(ctx, S64, k, sym.symnmf_params_default(method=sym.ADMM, rho=rho,
-                                                                         max_iter=10 ** 9), H0.double())
-    best = math.inf
-    for t in range(iters):
-        s = sym.symnmf_step(ctx, S64, st, want_stats=(t % 10 == 0 or t == iters - 1))
-        if s is not None:
-            best = min(best, s.f)
-            if t % 100 == 0:
-                log(f"FP64 reference t={t} f={s.f:.12e} kkt={s.kkt:.3e}")
-    W = torch.empty(S64.desc.n, k, dtype=torch.float64, device=H0.device)
-    sym.symnmf_state_read(ctx, st, 0, W)
-    f_last = sym.symnmf_objective(ctx, S64, W, k)[0]
-    del st, S64
+    eta = math.sqrt(S64.desc.mean / k)
+    best_run = None
+    for plan in plans:
+        W = H0.double().clone()
+        best, hist = math.inf, []
+        for name, iters in plan:
+            st = sym.symnmf_state_create(ctx, S64, k, variant_params("fp64-" + name, eta), W)
+            for t in range(iters):
+                s = sym.symnmf_step(ctx, S64, st, want_stats=(t % 10 == 0 or t == iters - 1))
+                if s is not None:
+                    best = min(best, s.f)
+                    hist.append(s.f)
+                    if t % 1000 == 0:
+                        log(f"FP64 reference {name} t={t} f={s.f:.12e} kkt={s.kkt:.3e}")
+            sym.symnmf_state_read(ctx, st, 0, W)
+            del st
+        f_last = sym.symnmf_objective(ctx, S64, W, k)[0]
+        drop = (hist[-101] - hist[-1]) / hist[-1] if len(hist) > 100 else float("nan")
+        desc = " then ".join(f"{name} x {iters}" for name, iters in plan)
+        log(f"FP64 reference [{desc}]: last f={f_last:.12e}, drop over the last 1000 iterations {drop:.2e}")
+        if best_run is None or f_last < best_run[0]:
+            best_run = (f_last, min(best, f_last), W.float().contiguous(), desc, drop)
+        del W
+    del S64
     torch.cuda.empty_cache()
-    return f_last, min(best, f_last), W.float().contiguous(), time.time() - t0
+    return best_run[0], best_run[1], best_run[2], time.time() - t0, best_run[3], best_run[4]
 
 
 def time_to_tolerance(args):
@@ -251,9 +273,12 @@ def time_to_tolerance(args):
     mean = ref["mean"] if ref else None
     H0 = torch.empty(n, k, device=dev)
     init_factor(ctx, S32, k, 0, H0, mean)
-    ref_iters = ref["iterations"] if ref else args.ttt_ref_iters
-    f_dev, f_dev_best, Wref, ref_s = fp64_reference(ctx, X, kind, k, ref["rho"] if ref else args.ttt_ref_rho,
-                                                    ref_iters, H0, build)
+    if ref:
+        plans = [[(f"admm{ref['rho']:g}", ref["iterations"])]]
+    else:
+        plans = [[(st.split(":")[0], int(st.split(":")[1])) for st in pl.split("+")]
+                 for pl in args.ttt_ref_plans.split(",")]
+    f_dev, f_dev_best, Wref, ref_s, ref_desc, ref_drop = fp64_reference(ctx, X, kind, k, H0, build, plans)
     if ref:
         f_ref = ref["f_ref"]
         results = {"f_ref": f_ref, "reference": f"FP64 oracle ADMM (rho {ref['rho']:g}) after {ref['iterations']} "
@@ -262,8 +287,9 @@ def time_to_tolerance(args):
                                             "seconds": round(ref_s, 2)}}
     else:
         f_ref = f_dev_best
-        results = {"f_ref": f_ref, "reference": f"device FP64 ADMM (rho {args.ttt_ref_rho:g}) after {ref_iters} "
-                                                f"iterations", "reference_seconds": round(ref_s, 2)}
+        results = {"f_ref": f_ref, "reference": f"device FP64 run from H0: {ref_desc} (the lowest of the plans "
+                                                f"{args.ttt_ref_plans})",
+                   "reference_last_1000_drop": ref_drop, "reference_seconds": round(ref_s, 2)}
     log(f"f_ref {f_ref:.12e}; device FP64 run {f_dev:.12e}")
     results.update(tol=args.ttt_tol, variants={})
     for v in variants:
@@ -283,10 +309,12 @@ def time_to_tolerance(args):
         S = stores[ladder[0]]
         S_hi = stores[ladder[1]] if len(ladder) > 1 else None
         entry = ttt_run(ctx, S, k, variant_params(v, eta), lambda H: H.copy_(H0), objective_of,
-                        f_ref, args.ttt_tol, args.ttt_max, every, store, S_hi, args.ttt_switch)
+                        f_ref, args.ttt_tol, args.ttt_max, every, store, S_hi, args.ttt_switch,
+                        [float(x) for x in args.ttt_tols.split(",") if x])
         entry.pop("times")
         nsave = args.ttt_max // every
         entry["subspace_error_final"] = sym.symnmf_subspace_error(ctx, store[nsave - 1], Wref)
+        entry["below_reference"] = entry["final_rel"] < 0.0
         if "iters" in entry:
             entry["subspace_error_at_tol"] = sym.symnmf_subspace_error(ctx, store[entry["iters"] // every - 1], Wref)
         results["variants"][v] = entry
@@ -298,21 +326,27 @@ WARM_WIDTH, WARM_HIDDEN, WARM_OMEGA_SEED = 64, 256, 7
 
 
 def warm_start_study(args):
-    """Learned warm start against random initialisation.
+    """Learned warm start against random initialisation and against the
+    network-free start, with ADMM (rho 500) as the solver.
 
     Training: for every training seed the returns are generated, S (FP32) is
-    built and solved from the network-free warm start (stop rule or
+    built and solved by ADMM from the network-free start (stop rule or
     --warm-solve-iters), and the pair (canonical sketch coordinates, solved H)
-    is kept on the device;
-    the network is then trained with the scale-free Gram loss.
-    Evaluation on held-out seeds (and optionally on the n = 100000 |corr|
-    workload): time to relative objective tolerance from (a) the random init,
-    (b) the network-free coordinates, (c) the network, each timed from the
-    start of its initialisation (sketch, coordinates and network included);
-    f_ref is the objective of the random-init run's certified iterate (or of
-    its last iterate when the stop rule does not certify one).  A
-    warm run that has not reached the tolerance within twice the random run's
-    iterations falls back to the random run, and its time counts both.
+    is kept on the device.  The network has the residual output
+    A = max(C + z, 0) (C the coordinates, z its last layer), starts with a
+    zero last layer - i.e. exactly at the network-free start - and is trained
+    with the scale-free Gram loss.
+    Evaluation on held-out seeds: f_ref is the lowest objective of two
+    reference runs of --warm-ref-iters ADMM iterations (from random init and
+    from the network-free start; FP32 state, FP64-accumulated objective -
+    the FP64 state stops at k = 32); then the time to (f(H_t) - f_ref) / f_ref
+    <= tol from (a) random init, (b) the network-free coordinates, (c) the
+    network, each timed from the start of its initialisation (sketch,
+    coordinates and network included).  A warm run that has not reached the
+    tolerance within twice the random run's iterations falls back to the
+    random run, and its time counts both.  Optionally the same on the
+    n = 100000 |corr| workload (k = 32 model) against its committed FP64
+    oracle reference.
     """
     import numpy as np
     import torch
@@ -323,6 +357,7 @@ def warm_start_study(args):
     ctx = sym.symnmf_create(0)
     k, n = args.warm_k, args.warm_n
     W, HID = WARM_WIDTH, WARM_HIDDEN
+    tols = [float(x) for x in args.ttt_tols.split(",") if x]
 
     def returns(seed, n_cols):
         if args.warm_family == "panel":
@@ -337,8 +372,12 @@ def warm_start_study(args):
         sym.symnmf_canonical(ctx, Y, k, Xc)
         return Xc
 
+    def admm_params(S, max_iter=10 ** 9):
+        return sym.symnmf_params_default(method=sym.ADMM, rho=500.0, max_iter=max_iter)
+
     out = {"family": args.warm_family, "n_train": args.warm_sizes or n, "n_heldout": n, "k": k, "T": args.warm_T,
-           "groups": args.warm_groups, "width": W, "hidden": HID}
+           "groups": args.warm_groups, "width": W, "hidden": HID, "solver": "ADMM, rho 500",
+           "network_output": "residual: max(C + z, 0), zero last layer at the start"}
     # 1. training pairs
     t0 = time.time()
     pairs = []
@@ -350,13 +389,9 @@ def warm_start_study(args):
         X = returns(seed, ni)
         S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
         del X
-        eta = math.sqrt(S.desc.mean / k)
-        # target: the solver's factorization from the network-free warm start
-        # (it reaches lower objectives than random initialisation)
         H0 = torch.empty(ni, k, device=dev)
         sym.symnmf_warm_start(ctx, S, None, W, k, WARM_OMEGA_SEED, H0)
-        st = sym.symnmf_state_create(ctx, S, k, sym.symnmf_params_default(eta=eta, max_iter=args.warm_solve_iters),
-                                     H0)
+        st = sym.symnmf_state_create(ctx, S, k, admm_params(S, args.warm_solve_iters), H0)
         Hs = torch.empty(ni, k, device=dev)
         rs, conv = sym.symnmf_solve_to_tol(ctx, S, st, H_out=Hs)
         del st
@@ -372,7 +407,10 @@ def warm_start_study(args):
     t0 = time.time()
     params = torch.empty(sym.symnmf_mlp_param_count(W, HID, k), device=dev)
     sym.symnmf_mlp_init(ctx, W, HID, k, args.warm_seed0, params)
+    params[HID * W + HID * HID: HID * W + HID * HID + k * HID].zero_()          # W3 = 0
+    params[-k:].zero_()                                                         # b3 = 0
     net = sym.symnmf_mlp_create(ctx, W, HID, k, params)
+    sym.symnmf_mlp_set_output(ctx, net, True)
     rng = np.random.default_rng(args.warm_seed0)
     hist = []
     steps_total = args.warm_epochs * len(pairs)
@@ -394,61 +432,67 @@ def warm_start_study(args):
     torch.cuda.empty_cache()
 
     # 3. evaluation
-    def evaluate(S, k_eval, model, label, seed, rand_steps, warm_steps, extra=None):
-        """random init run first (it is also the reference: f_ref is its
-        certified iterate, or its last one), then the two warm starts; with
-        ``extra`` ({name: S stored otherwise}) the three initialisations are
-        also run on those stores, evaluated on S."""
+    def evaluate(S, k_eval, model, label, seed, ref_steps, steps, f_ref_given=None):
         nn = S.desc.n
-        eta = math.sqrt(S.desc.mean / k_eval)
-        params = variant_params("fp32", eta)
+        params = admm_params(S)
 
         def objective_of(H):
             return sym.symnmf_objective(ctx, S, H, k_eval)[0]
 
-        every = 2
-        store = torch.empty(rand_steps // every, nn, k_eval, device=dev)
-        times, cert, t_init, _ = ttt_trace(ctx, S, k_eval, params, lambda H: sym.symnmf_init_H(ctx, S, k_eval, seed, H),
-                                        rand_steps, every, store)
-        ref_slot = (cert + 1) // every - 1 if cert >= 0 else rand_steps // every - 1
-        f_ref = objective_of(store[ref_slot])
-        res = {"f_ref": f_ref, "ref_iters": (ref_slot + 1) * every, "ref_certified": cert >= 0}
-        res["random"] = ttt_scan(objective_of, store, rand_steps // every, f_ref, args.ttt_tol, every, times)
         inits = {
+            "random": lambda H: sym.symnmf_init_H(ctx, S, k_eval, seed, H),
             "coords": lambda H: sym.symnmf_warm_start(ctx, S, None, W, k_eval, WARM_OMEGA_SEED, H),
             "mlp": lambda H: sym.symnmf_warm_start(ctx, S, model, W, k_eval, WARM_OMEGA_SEED, H),
         }
-        r_it, r_s = res["random"].get("iters"), res["random"].get("seconds")
+        res = {}
+        if f_ref_given is None:
+            refs = []
+            for name in ("random", "coords"):
+                Hr = torch.empty(nn, k_eval, device=dev)
+                inits[name](Hr)
+                st = sym.symnmf_state_create(ctx, S, k_eval, params, Hr)
+                for _ in range(ref_steps):
+                    sym.symnmf_step(ctx, S, st, want_stats=False)
+                sym.symnmf_state_read(ctx, st, 0, Hr)
+                del st
+                refs.append(objective_of(Hr))
+            f_ref = min(refs)
+            res["reference_runs"] = {"random": refs[0], "coords": refs[1], "iterations": ref_steps}
+        else:
+            f_ref = f_ref_given
+        res["f_ref"] = f_ref
+        every = 2
+        store = torch.empty(steps // every, nn, k_eval, device=dev)
         for name, init in inits.items():
-            wt, wcert, w_init, _ = ttt_trace(ctx, S, k_eval, params, init, warm_steps, every, store)
-            e = ttt_scan(objective_of, store, warm_steps // every, f_ref, args.ttt_tol, every, wt)
+            H0 = torch.empty(nn, k_eval, device=dev)
+            init(H0)
+            f0 = objective_of(H0)
+            wt, _, w_init, _ = ttt_trace(ctx, S, k_eval, params, init, steps, every, store)
+            e = ttt_scan(objective_of, store, steps // every, f_ref, args.ttt_tol, every, wt)
             e["init_seconds"] = round(w_init, 4)
+            e["rel_initial"] = (f0 - f_ref) / f_ref
+            e["at_tol"] = {}
+            for t2 in tols:
+                e2 = ttt_scan(objective_of, store, steps // every, f_ref, t2, every, wt)
+                e["at_tol"][f"{t2:g}"] = {q: e2[q] for q in ("iters", "seconds") if q in e2} or None
+            e["times"] = wt
+            res[name] = e
+        r = res["random"]
+        r_it, r_s = r.get("iters"), r.get("seconds")
+        for name in ("coords", "mlp"):
+            e = res[name]
             if r_it is not None:
                 if e.get("iters") is None or e["iters"] > 2 * r_it:
-                    # fallback: the warm run is abandoned after 2x the random
-                    # iterations (or its cap) and the random run is started
-                    idx = min(2 * r_it // every, len(wt)) - 1
+                    idx = min(2 * r_it // every, len(e["times"])) - 1
                     e["fallback"] = True
-                    e["seconds_with_fallback"] = wt[idx] + r_s
+                    e["seconds_with_fallback"] = e["times"][idx] + r_s
                 else:
                     e["fallback"] = False
                     e["seconds_with_fallback"] = e["seconds"]
                 e["speedup_vs_random"] = round(r_s / e["seconds_with_fallback"], 3)
-            res[name] = e
-        for xname, Sx in (extra or {}).items():
-            xinits = {
-                "random": lambda H: sym.symnmf_init_H(ctx, Sx, k_eval, seed, H),
-                "coords": lambda H: sym.symnmf_warm_start(ctx, Sx, None, W, k_eval, WARM_OMEGA_SEED, H),
-                "mlp": lambda H: sym.symnmf_warm_start(ctx, Sx, model, W, k_eval, WARM_OMEGA_SEED, H),
-            }
-            for name, init in xinits.items():
-                steps = rand_steps if name == "random" else warm_steps
-                wt, _, w_init, _ = ttt_trace(ctx, Sx, k_eval, params, init, steps, every, store)
-                e = ttt_scan(objective_of, store, steps // every, f_ref, args.ttt_tol, every, wt)
-                e["init_seconds"] = round(w_init, 4)
-                if r_s is not None and e.get("seconds"):
-                    e["speedup_vs_fp32_random"] = round(r_s / e["seconds"], 3)
-                res[f"{xname}-{name}"] = e
+        for e in res.values():
+            if isinstance(e, dict):
+                e.pop("times", None)
         del store
         log(f"{label}: " + json.dumps(res))
         return res
@@ -458,7 +502,7 @@ def warm_start_study(args):
         X = returns(seed, n)
         S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
         del X
-        held.append(evaluate(S, k, net, f"held-out seed {seed}", seed, args.warm_max, args.warm_warm_max))
+        held.append(evaluate(S, k, net, f"held-out seed {seed}", seed, args.warm_ref_iters, args.warm_max))
         del S
     out["heldout"] = held
     for name in ("coords", "mlp"):
@@ -467,14 +511,19 @@ def warm_start_study(args):
             out[f"{name}_speedup_median"] = float(np.median(sp))
             out[f"{name}_wins"] = int(sum(1 for v in sp if v > 1.0))
             out[f"{name}_fallbacks"] = int(sum(1 for h in held if h[name].get("fallback")))
+        out[f"{name}_reached"] = int(sum(1 for h in held if h[name].get("iters") is not None))
+    out["random_reached"] = int(sum(1 for h in held if h["random"].get("iters") is not None))
+    both = [(h["coords"]["seconds"], h["mlp"]["seconds"]) for h in held
+            if h["coords"].get("seconds") and h["mlp"].get("seconds")]
+    if both:
+        out["mlp_vs_coords_speedup_median"] = float(np.median([a / b for a, b in both]))
     if args.warm_c3:
-        X = synth.overlap_returns(0, T=2500, n=100000, groups=32, device=dev).X
+        ref = committed_reference(0, 100000, 2500, 32, k, 0)
+        X = synth.overlap_returns(0, T=2500, n=100000, groups=32, device="cpu").X.to(dev)
         S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
-        extra = {dt: sym.symnmf_build_S(ctx, X, dtype=sym.DTYPES[dt], fp8_panel_rows=256)
-                 for dt in args.warm_c3_dtypes.split(",") if dt and dt != "fp32"}
         del X
-        out["c3_abs_corr_n100000"] = evaluate(S, k, net, "n=100000 |corr|", 1, args.warm_c3_max, args.warm_c3_max,
-                                              extra)
+        out["c3_abs_corr_n100000"] = evaluate(S, k, net, "n=100000 |corr|", 0, args.warm_ref_iters,
+                                              args.warm_c3_max, ref["f_ref"] if ref else None)
     return out
 
 
@@ -667,9 +716,10 @@ def main():
                          "whose stagnation measure (E_{t-delta} - E_t) / E_0 is below this")
     ap.add_argument("--ttt-max", type=int, default=6000)
     ap.add_argument("--ttt-save-every", type=int, default=2)
-    ap.add_argument("--ttt-ref-iters", type=int, default=3000,
-                    help="iterations of the device FP64 ADMM reference where no oracle reference is committed")
-    ap.add_argument("--ttt-ref-rho", type=float, default=500.0)
+    ap.add_argument("--ttt-ref-plans", default="admm500:3000,admm50:3000",
+                    help="device FP64 reference runs where no oracle reference is committed: comma-separated plans, "
+                         "each a '+'-joined list of method:iterations stages")
+    ap.add_argument("--ttt-tols", default="1e-2,1e-3", help="further tolerances scanned on the same runs")
     ap.add_argument("--warm", action="store_true", help="learned warm start study instead of the step rate")
     ap.add_argument("--warm-family", default="panel", choices=["panel", "overlap"])
     ap.add_argument("--warm-n", type=int, default=20000)
@@ -682,15 +732,13 @@ def main():
     ap.add_argument("--warm-heldout", type=int, default=20)
     ap.add_argument("--warm-heldout0", type=int, default=2000)
     ap.add_argument("--warm-solve-iters", type=int, default=1500)
-    ap.add_argument("--warm-ref-iters", type=int, default=8000)
+    ap.add_argument("--warm-ref-iters", type=int, default=3000, help="ADMM iterations of each reference run")
     ap.add_argument("--warm-epochs", type=int, default=40)
     ap.add_argument("--warm-lr", type=float, default=1e-3)
     ap.add_argument("--warm-wd", type=float, default=1e-4)
-    ap.add_argument("--warm-max", type=int, default=8000, help="steps of the random-init (reference) run")
-    ap.add_argument("--warm-warm-max", type=int, default=3000, help="steps of each warm-started run")
+    ap.add_argument("--warm-max", type=int, default=1500, help="ADMM steps traced from each initialisation")
     ap.add_argument("--warm-c3", action="store_true", help="also evaluate on the n=100000 |corr| workload")
-    ap.add_argument("--warm-c3-max", type=int, default=6000)
-    ap.add_argument("--warm-c3-dtypes", default="fp32", help="storage types of the n=100000 evaluation, e.g. fp32,bf16")
+    ap.add_argument("--warm-c3-max", type=int, default=1500)
     ap.add_argument("--kmeans", default="", help="spherical K-means study instead of the step rate: cluster counts, "
                                                  "e.g. 32,316")
     ap.add_argument("--kmeans-dtypes", default="fp32,bf16")

@@ -1,11 +1,16 @@
-"""What the trained network gains: a small end-to-end run of the learned warm
-start at test size.  A network is trained on the solver's own factorizations
-of generated instances and compared, on a held-out instance, with random
-initialisation by the iterations needed to reach the random run's final
-objective within 1e-4 (kept iterates judged with the FP64-accumulating
-objective).  The network-free coordinates are reported beside it."""
-import math
-
+"""What the trained network gains: an end-to-end run of the learned warm start
+on the n = 20000, k = 64 instances of the warm-start workload (column-block
+returns, T = 1000, 64 groups + market), with ADMM (rho 500) as the solver:
+the training of the full study (200 instances, 40 epochs) and 8 of its 20
+held-out seeds.  A network with the
+residual output A = max(C + z, 0) (C the canonical coordinates; zero last
+layer at the start, i.e. exactly the network-free start) is trained on the
+solver's own factorizations of generated instances and compared on held-out
+instances with random initialisation and with the network-free coordinates
+by the iterations needed to reach within 1e-4 of f_ref, the lower final
+objective of two longer reference runs (from random init and from the
+coordinates; kept iterates judged with the FP64-accumulating objective)."""
+import numpy as np
 import pytest
 import torch
 
@@ -16,7 +21,8 @@ pytestmark = pytest.mark.gpu
 
 from gpu_util import ctx, dev  # noqa: E402
 
-W, HID, K, N, T, GROUPS = 64, 256, 16, 2048, 1000, 16
+W, HID, K, N, T, GROUPS = 64, 256, 64, 20000, 1000, 64
+ADMM = dict(method=sym.ADMM, rho=500.0)
 
 
 def _S(c, seed):
@@ -24,29 +30,29 @@ def _S(c, seed):
     return sym.symnmf_build_S(c, X, dtype=sym.S_FP32)
 
 
-def _iters_to(c, S, H0, steps, f_ref, tol=1e-4):
-    """Iterations from H0 until f(H_t) <= f_ref (1 + tol), or None."""
-    eta = math.sqrt(S.desc.mean / K)
-    st = sym.symnmf_state_create(c, S, K, sym.symnmf_params_default(eta=eta, max_iter=10 ** 9), H0)
-    store = torch.empty(steps // 10, N, K, device=dev())
-    sym.symnmf_solve_trace(c, S, st, steps, 10, store)
+def _run(c, S, H0, steps, every):
+    st = sym.symnmf_state_create(c, S, K, sym.symnmf_params_default(max_iter=10 ** 9, **ADMM), H0)
+    store = torch.empty(steps // every, N, K, device=dev())
+    sym.symnmf_solve_trace(c, S, st, steps, every, store)
+    return store
+
+
+def _iters_to(c, S, store, every, f_ref, tol=1e-4):
     for j in range(store.shape[0]):
         f, _ = sym.symnmf_objective(c, S, store[j], K)
         if (f - f_ref) / f_ref <= tol:
-            return (j + 1) * 10
+            return (j + 1) * every
     return None
 
 
-def test_trained_network_beats_random_initialisation():
+def test_trained_network_beats_random_init_and_the_network_free_start():
     c = ctx()
-    # training pairs: canonical coordinates and the solver's factorization
     pairs = []
-    for seed in range(100, 124):
+    for seed in range(1000, 1200):
         S = _S(c, seed)
         H0 = torch.empty(N, K, device=dev())
         sym.symnmf_warm_start(c, S, None, W, K, 7, H0)
-        eta = math.sqrt(S.desc.mean / K)
-        st = sym.symnmf_state_create(c, S, K, sym.symnmf_params_default(eta=eta, max_iter=1000), H0)
+        st = sym.symnmf_state_create(c, S, K, sym.symnmf_params_default(max_iter=1500, **ADMM), H0)
         Hs = torch.empty(N, K, device=dev())
         sym.symnmf_solve_to_tol(c, S, st, H_out=Hs)
         Y = torch.empty(N, W, device=dev())
@@ -54,33 +60,44 @@ def test_trained_network_beats_random_initialisation():
         Xc = torch.empty(N, W, device=dev())
         sym.symnmf_canonical(c, Y, K, Xc)
         pairs.append((Xc, Hs))
+        if len(pairs) % 25 == 0:
+            print(f"[warm gain] training instance {len(pairs)} solved", flush=True)
     params = torch.empty(sym.symnmf_mlp_param_count(W, HID, K), device=dev())
-    sym.symnmf_mlp_init(c, W, HID, K, 1, params)
+    sym.symnmf_mlp_init(c, W, HID, K, 1000, params)
+    params[HID * W + HID * HID: HID * W + HID * HID + K * HID].zero_()
+    params[-K:].zero_()
     net = sym.symnmf_mlp_create(c, W, HID, K, params)
+    sym.symnmf_mlp_set_output(c, net, True)
     losses = []
-    for ep in range(15):
-        for Xc, Hs in pairs:
-            losses.append(sym.symnmf_mlp_train_step(c, net, Xc, Hs, lr=1e-3, loss_kind=1))
+    epochs, step = 40, 0
+    order = np.random.default_rng(1000)
+    for ep in range(epochs):
+        for j in order.permutation(len(pairs)):
+            lr = 1e-3 * 0.5 * (1.0 + np.cos(np.pi * step / (epochs * len(pairs))))
+            losses.append(sym.symnmf_mlp_train_step(c, net, pairs[j][0], pairs[j][1], lr=lr, weight_decay=1e-4,
+                                                    loss_kind=1))
+            step += 1
+        if ep % 10 == 0:
+            print(f"[warm gain] epoch {ep}", flush=True)
     first = sum(losses[: len(pairs)]) / len(pairs)
     last = sum(losses[-len(pairs):]) / len(pairs)
     assert last < first
-    # held-out instance: the random run defines f_ref
-    S = _S(c, 999)
-    Hr = torch.empty(N, K, device=dev())
-    sym.symnmf_init_H(c, S, K, 5, Hr)
-    eta = math.sqrt(S.desc.mean / K)
-    st = sym.symnmf_state_create(c, S, K, sym.symnmf_params_default(eta=eta, max_iter=4000), Hr)
-    Hf = torch.empty(N, K, device=dev())
-    stats, _ = sym.symnmf_solve_to_tol(c, S, st, H_out=Hf)
-    f_ref, _ = sym.symnmf_objective(c, S, Hf, K)
-    it_random = _iters_to(c, S, Hr, int(stats.t) + 10, f_ref)
-    Hm = torch.empty(N, K, device=dev())
-    sym.symnmf_warm_start(c, S, net, W, K, 7, Hm)
-    it_mlp = _iters_to(c, S, Hm, 4000, f_ref)
-    Hc = torch.empty(N, K, device=dev())
-    sym.symnmf_warm_start(c, S, None, W, K, 7, Hc)
-    it_coords = _iters_to(c, S, Hc, 4000, f_ref)
-    print(f"[warm gain] iterations to f_ref(1+1e-4): random {it_random}, network {it_mlp}, "
-          f"coordinates {it_coords}; loss {first:.4f} -> {last:.4f}", flush=True)
-    assert it_random is not None and it_mlp is not None
-    assert it_mlp < it_random
+    its = {"random": [], "coords": [], "mlp": []}
+    for seed in range(2000, 2008):
+        S = _S(c, seed)
+        starts = {"random": torch.empty(N, K, device=dev()), "coords": torch.empty(N, K, device=dev()),
+                  "mlp": torch.empty(N, K, device=dev())}
+        sym.symnmf_init_H(c, S, K, seed, starts["random"])
+        sym.symnmf_warm_start(c, S, None, W, K, 7, starts["coords"])
+        sym.symnmf_warm_start(c, S, net, W, K, 7, starts["mlp"])
+        f_ref = min(sym.symnmf_objective(c, S, _run(c, S, starts[nm], 3000, 3000)[0], K)[0]
+                    for nm in ("random", "coords"))
+        for nm, H0 in starts.items():
+            its[nm].append(_iters_to(c, S, _run(c, S, H0, 1500, 10), 10, f_ref))
+        print(f"[warm gain] held-out seed {seed}: " + ", ".join(f"{nm} {v[-1]}" for nm, v in its.items()), flush=True)
+    print(f"[warm gain] iterations to f_ref (1 + 1e-4): {its}; Gram loss {first:.4f} -> {last:.4f}", flush=True)
+    big = 10 ** 6                                    # a run that never reaches the tolerance
+    med = {nm: float(np.median([v if v is not None else big for v in vals])) for nm, vals in its.items()}
+    assert all(v is not None for v in its["mlp"])
+    assert med["mlp"] < med["random"]
+    assert med["mlp"] <= med["coords"]

@@ -118,12 +118,14 @@ def test_canonical_rejects_rank_deficient_sketch():
 
 @pytest.mark.parametrize("k,m", [(16, 1000), (5, 333), (64, 130)])
 @pytest.mark.parametrize("bf16", [False, True])
-def test_mlp_forward_matches_oracle(k, m, bf16):
+@pytest.mark.parametrize("residual", [False, True])
+def test_mlp_forward_matches_oracle(k, m, bf16, residual):
     P = _params32(k, seed=k)
     Xin = np.random.default_rng(m).normal(size=(m, WIDTH)).astype(np.float32).astype(np.float64)
-    ref, _ = w.forward(w.bf16_weights(P) if bf16 else P, Xin)
+    ref, _ = w.forward(w.bf16_weights(P) if bf16 else P, Xin, residual)
     c = ctx()
     net = sym.symnmf_mlp_create(c, WIDTH, HIDDEN, k, to_dev(_flat(P)))
+    sym.symnmf_mlp_set_output(c, net, residual)
     A = torch.empty(m, k, device=dev())
     sym.symnmf_mlp_forward(c, net, to_dev(Xin), A, bf16_weights=bf16)
     # FP32 activations and sums over 256 terms: relative 1e-5 of the layer scale
@@ -141,20 +143,23 @@ def test_mlp_init_matches_oracle():
         assert np.max(np.abs(got[name] - ref[name])) <= 1e-7 * max(1.0, np.max(np.abs(ref[name]))), name
 
 
-@pytest.mark.parametrize("loss_kind", [0, 1])
-def test_mlp_train_step_matches_oracle(loss_kind):
+@pytest.mark.parametrize("loss_kind,residual", [(0, False), (1, False), (1, True)])
+def test_mlp_train_step_matches_oracle(loss_kind, residual):
     k, m = 8, 1500
     P = _params32(k, seed=4)
     g = np.random.default_rng(7)
     Xin = g.normal(size=(m, WIDTH)).astype(np.float32).astype(np.float64)
     B = g.random((m, k)).astype(np.float32).astype(np.float64)
-    A, cache = w.forward(P, Xin)
+    A, cache = w.forward(P, Xin, residual)
+    if residual:   # the FP32 side takes the same side of max(., 0) wherever C + z is not within its noise
+        assert np.mean(np.abs(Xin[:, :k] + cache["z3"]) < 1e-4) < 1e-3
     L_ref, dA = (w.gram_loss if loss_kind == 0 else w.gram_cos_loss)(A, B)
     G_ref = w.backward(P, cache, dA)
     lr, wd = 1e-3, 1e-2
     P_ref = w.adamw_step({n: v.copy() for n, v in P.items()}, G_ref, {}, 1, lr=lr, wd=wd, eps=1e-8)
     c = ctx()
     net = sym.symnmf_mlp_create(c, WIDTH, HIDDEN, k, to_dev(_flat(P)))
+    sym.symnmf_mlp_set_output(c, net, residual)
     L = sym.symnmf_mlp_train_step(c, net, to_dev(Xin), to_dev(B), lr=lr, weight_decay=wd, eps=1e-8,
                                   loss_kind=loss_kind)
     assert L == pytest.approx(L_ref, rel=1e-5)
@@ -185,16 +190,20 @@ def test_mlp_training_fits_a_planted_target():
     assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
 
 
-@pytest.mark.parametrize("with_net", [False, True])
-def test_warm_start_matches_oracle(with_net):
+@pytest.mark.parametrize("with_net,residual", [(False, False), (True, False), (True, True)])
+def test_warm_start_matches_oracle(with_net, residual):
     Hs = synth.planted_factor(8, 700, 6).numpy()
     S = Hs @ Hs.T
     k = 6
     P = _params32(k, seed=11) if with_net else None
-    ref, _ = w.warm_start(S.astype(np.float32).astype(np.float64), k, 21, P, WIDTH)
+    if residual:                       # a small correction on top of the coordinates
+        P["W3"] = (P["W3"] * 0.05).astype(np.float32).astype(np.float64)
+    ref, _ = w.warm_start(S.astype(np.float32).astype(np.float64), k, 21, P, WIDTH, residual)
     c = ctx()
     Sd = sym.symnmf_S_load(c, to_dev(S, torch.float64), dtype=sym.S_FP32)
     net = sym.symnmf_mlp_create(c, WIDTH, HIDDEN, k, to_dev(_flat(P))) if with_net else None
+    if net is not None:
+        sym.symnmf_mlp_set_output(c, net, residual)
     H0 = torch.empty(700, k, device=dev())
     sym.symnmf_warm_start(c, Sd, net, WIDTH, k, 21, H0)
     # the GPU sketch is FP32 (relative ~1e-6), carried through the anchor solve

@@ -58,17 +58,21 @@ def test_scale_free_gram_loss_is_the_best_scalar_fit():
         assert fd == pytest.approx(dA[idx], rel=1e-6, abs=1e-12)
 
 
-def test_network_and_loss_gradients_match_finite_differences():
+@pytest.mark.parametrize("residual", [False, True])
+def test_network_and_loss_gradients_match_finite_differences(residual):
     g = np.random.default_rng(1)
     P = w.init_params(4, seed=3, width=8, hidden=16)
     X = g.normal(size=(20, 8))
     B = g.random((20, 4))
 
     def loss(P):
-        A, _ = w.forward(P, X)
+        A, _ = w.forward(P, X, residual)
         return w.gram_loss(A, B)[0]
 
-    A, cache = w.forward(P, X)
+    A, cache = w.forward(P, X, residual)
+    if residual:   # no entry of C + z at the kink of max(., 0), where the derivative jumps
+        assert np.min(np.abs(X[:, :4] + cache["z3"])) > 1e-4
+        assert 0 < np.mean(A > 0) < 1
     _, dA = w.gram_loss(A, B)
     G = w.backward(P, cache, dA)
     h = 1e-6
@@ -115,3 +119,22 @@ def test_spa_recovers_anchor_rows_of_a_separable_factor():
     assert o.subspace_error(C, Hs) < 1e-6          # FP64 cancellation floor ~2e-8
     assert sorted(anchors.tolist()) == [0, 1, 2, 3, 4]
     assert np.all(C > -1e-8)
+
+
+def test_residual_network_with_zero_last_layer_is_the_network_free_start():
+    """A = max(C + z, 0): with W3 = 0 and b3 = 0 the network returns the
+    coordinates clipped at zero, the start without a network; the gradient
+    then reaches W3 only through the rows and columns where C > 0."""
+    g = np.random.default_rng(4)
+    P = w.init_params(5, seed=2, width=8, hidden=16)
+    P["W3"][:] = 0.0
+    P["b3"][:] = 0.0
+    X = g.normal(size=(30, 8))
+    A, cache = w.forward(P, X, residual=True)
+    assert np.array_equal(A, np.maximum(X[:, :5], 0.0))
+    B = g.random((30, 5))
+    _, dA = w.gram_loss(A, B)
+    G = w.backward(P, cache, dA)
+    mask = X[:, :5] > 0.0
+    assert np.allclose(G["W3"], (dA * mask).T @ cache["a2"], rtol=1e-13, atol=1e-15)
+    assert np.allclose(G["b3"], (dA * mask).sum(axis=0), rtol=1e-13, atol=1e-15)
