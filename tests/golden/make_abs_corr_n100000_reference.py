@@ -11,10 +11,12 @@ iterations, so f_ref sits within a few 1e-6 of the limit the iteration tends
 to - far inside the 1e-4 tolerance it serves.  Every product with S is FP64 on
 the float32-stored matrix (oracle.StoredRows), as in the trajectory fixture.
 The file is rewritten every 50 iterations ("complete": false until the end).
+With ``--state PATH`` the iterate, the dual and the history are saved there
+at the same points (.npz, arrays only) and a later run resumes from them.
 
 Calls only ``oracle`` and ``synth``.  Run from the repository root:
-python tests/golden/make_abs_corr_n100000_reference.py   (hours on 8 cores;
-40 GB of host memory)
+python tests/golden/make_abs_corr_n100000_reference.py [--state /tmp/ref.npz]
+(hours on 8 cores; 40 GB of host memory)
 """
 import json
 import math
@@ -41,6 +43,7 @@ def log(msg):
 
 
 def main():
+    state = sys.argv[sys.argv.index("--state") + 1] if "--state" in sys.argv else None
     n, T, groups, k, rho = 100000, 2500, 32, 32, 500.0
     X = synth.overlap_returns(0, T=T, n=n, groups=groups, device="cpu").X.numpy()
     S = o.StoredRows.abs_corr(X)
@@ -51,6 +54,14 @@ def main():
     t0 = time.time()
     f_hist, trace = [], []
     best = (math.inf, -1)
+    if state and os.path.exists(state):
+        z = np.load(state)
+        solver.H, solver.U, solver.t = z["H"].copy(), z["U"].copy(), int(z["t"])
+        f_hist = [float(v) for v in z["f_hist"]]
+        trace = [{"t": int(r[0]), "f": float(r[1]), "E": float(r[2]), "kkt": float(r[3])} for r in z["trace"]]
+        best = (float(z["best"][0]), int(z["best"][1]))
+        t0 -= float(z["wall"])
+        log(f"resumed at t={solver.t} from {state}")
 
     def write(complete):
         out = {"n": n, "T": T, "groups": groups, "k": k, "seed": 0, "init_seed": 0, "method": "admm", "rho": rho,
@@ -71,6 +82,11 @@ def main():
             log(f"t={st.t} f={st.f:.12e} E={st.E:.6e} kkt={st.kkt:.4e}")
         if st.t % 50 == 0:
             write(False)
+            if state:
+                np.savez(state + ".tmp.npz", H=solver.H, U=solver.U, t=solver.t, f_hist=np.array(f_hist),
+                         trace=np.array([[r["t"], r["f"], r["E"], r["kkt"]] for r in trace]),
+                         best=np.array(best), wall=time.time() - t0)
+                os.replace(state + ".tmp.npz", state)
         if st.t >= WINDOW and (f_hist[st.t - WINDOW] - st.f) < STAG * st.f:
             break
     write(True)

@@ -57,6 +57,38 @@ def stored_numpy(S):
     return M.cpu().numpy()
 
 
+def stored_rows(S, rows):
+    """float64 rows (global indices) of what the solver multiplies with,
+    decoded from one 256-row tile row at a time (the tiles of a tile row are
+    contiguous in the tiled layout), for matrices too large to decode whole."""
+    d = S.desc
+    rows = np.asarray(rows, dtype=np.int64)
+    local = rows - d.row0
+    out = torch.empty(rows.size, d.n, dtype=torch.float64, device=S.buf.device)
+    if d.dtype == sym.S_FP64:
+        M = S.buf[: d.rows_pad * d.ld * 8].view(torch.float64).view(d.rows_pad, d.ld)
+        out[:] = M[torch.from_numpy(local).to(M.device), : d.n]
+        return out.cpu().numpy()
+    E, dt = {sym.S_FP32: (4, torch.float32), sym.S_BF16: (8, torch.bfloat16), sym.S_FP8: (16, torch.float8_e4m3fn)}[d.dtype]
+    esz = torch.tensor([], dtype=dt).element_size()
+    per = 256 * d.ld
+    for R in np.unique(local // 256):
+        sel = np.nonzero(local // 256 == R)[0]
+        flat = S.buf[R * per * esz: (R + 1) * per * esz].view(dt)
+        tile = untile(flat, 256, d.ld, E)[torch.from_numpy(local[sel] % 256).to(flat.device), : d.n].double()
+        out[torch.from_numpy(sel).to(out.device)] = tile
+    if d.dtype == sym.S_FP8:
+        so = d.panel_scale - d.data
+        do = d.diag - d.data
+        panels = (d.rows + d.fp8_panel_rows - 1) // d.fp8_panel_rows
+        scale = S.buf[so: so + 4 * panels].view(torch.float32).double()
+        diag = S.buf[do: do + 4 * d.rows].view(torch.float32).double()
+        li = torch.from_numpy(local).to(out.device)
+        out /= scale[li // d.fp8_panel_rows][:, None]
+        out[torch.arange(rows.size, device=out.device), torch.from_numpy(rows).to(out.device)] = diag[li]
+    return out.cpu().numpy()
+
+
 def to_dev(a, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).to(dev()).contiguous()
 

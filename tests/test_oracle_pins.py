@@ -180,6 +180,20 @@ def test_tpdm_population_limit_of_noiseless_factor_model():
     assert errs[1] < 0.06 and errs[1] < 0.3 * errs[0]
 
 
+def test_tpdm_rows_blockwise_equals_the_direct_form():
+    """The column-blocked form behind the full-size checks (rank transform and
+    radii per block of columns) gives the direct form's rows: blocks of 7
+    columns over 50 instruments, both tails, a q that makes the selection cut
+    through the middle of the radii."""
+    X = synth.tpdm_returns(3, T=3000, n=50, groups=4, nu=2.5, common=True).X.numpy()
+    rows = np.array([0, 7, 13, 49])
+    for lower in (True, False):
+        ref = o.tpdm(X, q=0.07, lower_tail=lower)
+        got = o.tpdm_rows(X, q=0.07, rows=rows, lower_tail=lower, col_block=7)
+        assert np.max(np.abs(got - ref[rows])) < 1e-14
+        assert np.all(got[np.arange(4), rows] == 1.0)
+
+
 # --- storage formats -------------------------------------------------------
 def test_benchmark_spectra_match_the_paper_table(golden_dir):
     """The appendix's benchmark construction (generator + |corr| or the
