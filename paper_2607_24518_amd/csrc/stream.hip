@@ -260,23 +260,32 @@ struct ImageShape {
     static constexpr int PLANE = KC * K;                                // bf16 elements per plane
 };
 
-// One work-group per chunk: the chunk's 256 x K rows of H (scaled by wt) are
-// staged in LDS with coalesced 16-byte loads, then every thread assembles
-// whole 16-byte image vectors (all three bf16 planes at once for KIND 1, 2)
-// and writes them in order.
+// One work-group per (chunk, block of CB columns of H): the block's 256 x CB
+// values (scaled by wt) are staged in LDS with 16-byte loads, then every
+// thread assembles whole 16-byte image vectors (all three bf16 planes at once
+// for KIND 1, 2) and writes them in order.  Each 16-column block is a
+// contiguous run of every plane of the image.  At k = 64 a work-group takes
+// 16 columns (17 KB of LDS, eight work-groups per CU instead of two); below,
+// the whole chunk.
+template <int KIND, int K>
+constexpr int image_cols_per_wg() { return K == 64 ? 16 : K; }
+
 template <int KIND, int K>
 __global__ __launch_bounds__(256) void h_image_kernel(const float* __restrict__ H, float wt,
                                                       u32x4* __restrict__ img) {
     using IS = ImageShape<KIND, K>;
-    constexpr int LDH = K + 1;                            // padded row: column reads spread over banks
+    constexpr int CB = image_cols_per_wg<KIND, K>();
+    constexpr int LDH = CB + 1;                           // padded row: column reads spread over banks
     constexpr int EPV = KIND == 0 ? 4 : 8;                // H values per image vector
     constexpr int VP = KC * K / EPV;                      // vectors per plane
+    constexpr int VB = VP / (K / CB);                     // ... per plane and column block
     __shared__ float Hs[KC * LDH];
     const int64_t chunk = blockIdx.x;
-    const float4* src = (const float4*)(H + chunk * KC * K);
-    for (int q = threadIdx.x; q < KC * K / 4; q += 256) {
-        const float4 x = src[q];
-        const int r = (4 * q) / K, c = (4 * q) % K;
+    const int blk = blockIdx.y;
+    const float* src = H + chunk * KC * K + CB * blk;
+    for (int q = threadIdx.x; q < KC * CB / 4; q += 256) {
+        const int r = q / (CB / 4), c = 4 * (q % (CB / 4));
+        const float4 x = *(const float4*)(src + (int64_t)r * K + c);
         float* d = Hs + r * LDH + c;
         d[0] = x.x * wt;
         d[1] = x.y * wt;
@@ -285,9 +294,10 @@ __global__ __launch_bounds__(256) void h_image_kernel(const float* __restrict__ 
     }
     __syncthreads();
     u32x4* out = img + chunk * IS::NV;
-    for (int v = threadIdx.x; v < VP; v += 256) {
+    for (int v = blk * VB + threadIdx.x; v < (blk + 1) * VB; v += 256) {
         int kk0, col;
         image_vector_origin<KIND>(v, kk0, col);
+        col -= CB * blk;
         if (KIND == 0) {
             u32x4 o;
 #pragma unroll
@@ -318,7 +328,7 @@ int64_t h_image_words(int32_t stype, int64_t k, int64_t n_chunks) {
 
 hipError_t launch_h_image(const float* H, int32_t stype, int64_t k, int64_t n_chunks, float wt, uint32_t* img,
                           hipStream_t stream) {
-    dim3 grid(n_chunks), block(256);
+    dim3 grid(n_chunks, k == 64 ? 4 : 1), block(256);
 #define IMG(KIND, KK) hipLaunchKernelGGL((h_image_kernel<KIND, KK>), grid, block, 0, stream, H, wt, (u32x4*)img)
     if (stype == SYMNMF_S_FP32) {
         if (k == 16) IMG(0, 16); else if (k == 32) IMG(0, 32); else if (k == 64) IMG(0, 64); else return hipErrorInvalidValue;
