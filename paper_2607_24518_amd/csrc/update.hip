@@ -99,6 +99,23 @@ __global__ __launch_bounds__(UT, sizeof(HT) == 4 ? 7 : 1) void update_kernel(Upd
             }
         }
     }
+    // the S.H partials of this thread's elements, summed over the writing
+    // work-groups in increasing order as below, but with the loads of all
+    // elements of one work-group issued together (a row of the n = 10^6 share
+    // has ten partials: one after another they are ten dependent load latencies
+    // per element)
+    HT shv[full_k ? NJ : 1];
+    if (full_k) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) shv[j] = 0;
+        for (int64_t w = w_lo; w <= w_hi; ++w) {
+            // element f = r k + c of the slice: its partial entry is f past the
+            // slot's first row of this slice
+            const HT* pw = part + ((slot_mul * w + slot_base) * TR + r0) * (int64_t)k;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) shv[j] += pw[t + UT * j];
+        }
+    }
     double tr = 0.0, kkt = 0.0;
     int bad = 0;
     int jj = 0;
@@ -111,8 +128,12 @@ __global__ __launch_bounds__(UT, sizeof(HT) == 4 ? 7 : 1) void update_kernel(Upd
             const int64_t idx = prow * k + c;
             HT g, sh = 0, hg = 0;
             if (act >= 0) {
-                for (int64_t w = w_lo; w <= w_hi; ++w)
-                    sh += part[((slot_mul * w + slot_base) * TR + r0 + r) * (int64_t)k + c];
+                if (full_k) {
+                    sh = shv[jj < NJ ? jj : 0];
+                } else {
+                    for (int64_t w = w_lo; w <= w_hi; ++w)
+                        sh += part[((slot_mul * w + slot_base) * TR + r0 + r) * (int64_t)k + c];
+                }
                 if (a.fp8) {   // codes carry S * scale off the diagonal; S_ii is kept exactly
                     // and enters with the weight the plan gives column i of this row:
                     // 1 on full and row-sampled steps; on a block step 0 for rows in I
