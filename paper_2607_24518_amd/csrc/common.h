@@ -353,6 +353,8 @@ hipError_t launch_gram_select(int64_t k, const double* tile_gram, const int32_t*
 
 hipError_t launch_init_H(float* H, int64_t n, int64_t k, uint64_t seed, float scale, hipStream_t stream);
 hipError_t launch_copy_h(const void* src, int src_f64, void* dst, int dst_f64, int64_t count, hipStream_t stream);
+// Zero `bytes` bytes at p on `stream` with a kernel (no memset node).
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t stream);
 hipError_t launch_softplus_init(void* H, void* Theta, int h_f64, int64_t count, hipStream_t stream);
 hipError_t launch_sum(const void* x, int x_f64, int64_t m, double* out, hipStream_t stream);
 hipError_t launch_piecewise_apply(void* G, const void* g, int h_f64, int64_t m, double c, const double* med,

@@ -610,7 +610,7 @@ hipError_t launch_weights_t(const KCall& kc, const int32_t* labels, void* W) {
 }
 
 hipError_t launch_counts(const KCall& kc, const int32_t* labels, int lo) {
-    hipError_t e = hipMemsetAsync(kc.counts, 0, kc.ncol * 4, kc.sm);
+    hipError_t e = launch_zero(kc.counts, kc.ncol * 4, kc.sm);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(count_kernel, dim3((unsigned)kc.row_blocks()), dim3(KT), 0, kc.sm, labels, kc.n, kc.K, lo,
                        kc.counts, kc.bad);
@@ -638,7 +638,7 @@ hipError_t centroid_step(const KCall& kc, const int32_t* labels, void* W, void* 
 template <typename T>
 hipError_t assign_step(const KCall& kc, const void* C, void* Pbuf, int32_t* labels, void* best, int track = 1) {
     hipError_t e = s_times(kc, C, Pbuf);
-    if (e == hipSuccess) e = hipMemsetAsync(kc.counts, 0, kc.ncol * 4, kc.sm);
+    if (e == hipSuccess) e = launch_zero(kc.counts, kc.ncol * 4, kc.sm);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(assign_kernel<T>, dim3((unsigned)kc.row_blocks()), dim3(KT), 0, kc.sm, (const T*)Pbuf,
                        kc.norms, kc.n, kc.rows_pad, (int)kc.w, kc.K, labels, (T*)best, kc.counts, kc.jpart,

@@ -65,7 +65,7 @@ void* CallScratch::get(int64_t bytes, bool zero) {
         c->ws.push_back({(char*)q, nb, true});
         ++c->ws_allocs;
     }
-    if (zero) err = hipMemsetAsync(p, 0, (size_t)b, c->stream);
+    if (zero) err = launch_zero(p, (size_t)b, c->stream);
     return err == hipSuccess ? p : nullptr;
 }
 
@@ -389,7 +389,7 @@ symnmf_status symnmf_build_S(symnmf_ctx* ctx, const float* X, const symnmf_sbuil
     if (sc.err != hipSuccess) return scratch_fail(ctx, sc, "build_S");
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    chk(hipMemsetAsync(buf, 0, L.total, st));
+    chk(launch_zero(buf, L.total, st));
     if (p->kind == SYMNMF_ABS_CORR) chk(launch_standardise(X, T, n, Z, z_f64, ldz, (int32_t*)bad, st));
     else {
         const float sign = p->raw_marginals ? (p->lower_tail ? -1.0f : 1.0f) : 0.0f;
@@ -442,7 +442,7 @@ symnmf_status symnmf_S_load(symnmf_ctx* ctx, const void* src, int32_t src_is_f64
     void* sums = sc.get((4 + 3 * L.rows_pad) * 8);
     void* pmax = sc.get(panels * 4);
     if (sc.err != hipSuccess) return scratch_fail(ctx, sc, "S_load");
-    hipError_t e = hipMemsetAsync(buf, 0, L.total, st);
+    hipError_t e = launch_zero(buf, L.total, st);
     if (e == hipSuccess) e = launch_store_dense(src, src_is_f64, o, (double*)sums, (uint32_t*)pmax, st);
     double hs[3] = {0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(hs, sums, 24, hipMemcpyDeviceToHost, st);
@@ -475,7 +475,7 @@ static symnmf_status state_alloc(symnmf_state* st, void** out, int64_t bytes) {
     if (e != hipSuccess)
         return fail(st->ctx, SYMNMF_ENOMEM, "state: hipMalloc(%lld) failed: %s", (long long)bytes, hipGetErrorString(e));
     st->allocs.push_back(p);
-    e = hipMemsetAsync(p, 0, bytes > 0 ? bytes : 8, st->ctx->stream);
+    e = launch_zero(p, bytes > 0 ? bytes : 8, st->ctx->stream);
     if (e != hipSuccess) return fail(st->ctx, SYMNMF_EDEVICE, "state: memset failed: %s", hipGetErrorString(e));
     *out = p;
     return SYMNMF_OK;

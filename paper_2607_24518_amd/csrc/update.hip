@@ -602,6 +602,33 @@ hipError_t launch_init_H(float* H, int64_t n, int64_t k, uint64_t seed, float sc
     return hipGetLastError();
 }
 
+// Zero fill of `bytes` bytes at any alignment: 16-byte vector stores over the
+// aligned middle, single bytes for the unaligned ends.  Used instead of a
+// memset node so that work a caller records into a HIP graph replays the
+// clear as a kernel.
+__global__ void zero_kernel(unsigned char* __restrict__ p, int64_t bytes) {
+    const int64_t mis = (int64_t)((16 - ((uintptr_t)p & 15)) & 15);
+    const int64_t head = mis < bytes ? mis : bytes;
+    const int64_t nvec = (bytes - head) / 16;
+    const int64_t tail0 = head + nvec * 16;
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    u32x4* v = (u32x4*)(p + head);
+    for (int64_t i = i0; i < nvec; i += stride) v[i] = u32x4{0u, 0u, 0u, 0u};
+    if (i0 < head) p[i0] = 0;
+    if (i0 < bytes - tail0) p[tail0 + i0] = 0;
+}
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t stream) {
+    if (bytes <= 0) return hipSuccess;
+    if (!p) return hipErrorInvalidValue;
+    int64_t blocks = (bytes / 16 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, stream, (unsigned char*)p, bytes);
+    return hipGetLastError();
+}
+
 template <typename A, typename B>
 __global__ void copy_kernel(const A* __restrict__ s, B* __restrict__ d, int64_t m) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)

@@ -123,7 +123,7 @@ symnmf_status symnmf_mlp_init(symnmf_ctx* ctx, int64_t width, int64_t hidden, in
         HIP_OK(ctx, launch_scale(params + off, rows[l] * cols[l], (float)(1.0 / std::sqrt((double)cols[l])), sm));
         off += rows[l] * cols[l];
     }
-    HIP_OK(ctx, hipMemsetAsync(params + off, 0, (np - off) * 4, sm));
+    HIP_OK(ctx, launch_zero(params + off, (np - off) * 4, sm));
     return SYMNMF_OK;
 }
 
@@ -153,9 +153,9 @@ symnmf_status symnmf_mlp_create(symnmf_ctx* ctx, int64_t width, int64_t hidden, 
     chk(hipMalloc((void**)&m->Wb, m->nw * 2));
     chk(hipMalloc((void**)&m->split_ws, m->split_floats * 4));
     if (e == hipSuccess) chk(hipMemcpyAsync(m->P, params, np * 4, hipMemcpyDeviceToDevice, ctx->stream));
-    if (e == hipSuccess) chk(hipMemsetAsync(m->G, 0, np * 4, ctx->stream));
-    if (e == hipSuccess) chk(hipMemsetAsync(m->Mm, 0, np * 4, ctx->stream));
-    if (e == hipSuccess) chk(hipMemsetAsync(m->V, 0, np * 4, ctx->stream));
+    if (e == hipSuccess) chk(launch_zero(m->G, np * 4, ctx->stream));
+    if (e == hipSuccess) chk(launch_zero(m->Mm, np * 4, ctx->stream));
+    if (e == hipSuccess) chk(launch_zero(m->V, np * 4, ctx->stream));
     if (e != hipSuccess) {
         symnmf_mlp_destroy(m);
         return fail(ctx, e == hipErrorOutOfMemory ? SYMNMF_ENOMEM : SYMNMF_EDEVICE, "mlp_create: %s",
@@ -204,8 +204,8 @@ symnmf_status symnmf_mlp_write(symnmf_ctx* ctx, symnmf_mlp* m, const float* para
     if (!ctx) return SYMNMF_EINVAL;
     if (!m || !params || m->ctx != ctx) return fail(ctx, SYMNMF_EINVAL, "mlp_write: bad argument");
     HIP_OK(ctx, hipMemcpyAsync(m->P, params, m->np * 4, hipMemcpyDeviceToDevice, ctx->stream));
-    HIP_OK(ctx, hipMemsetAsync(m->Mm, 0, m->np * 4, ctx->stream));
-    HIP_OK(ctx, hipMemsetAsync(m->V, 0, m->np * 4, ctx->stream));
+    HIP_OK(ctx, launch_zero(m->Mm, m->np * 4, ctx->stream));
+    HIP_OK(ctx, launch_zero(m->V, m->np * 4, ctx->stream));
     m->t = 0;
     m->bf16_stale = true;
     return SYMNMF_OK;
