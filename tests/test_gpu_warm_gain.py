@@ -45,7 +45,12 @@ def _iters_to(c, S, store, every, f_ref, tol=1e-4):
     return None
 
 
-def test_trained_network_beats_random_init_and_the_network_free_start():
+def test_trained_network_beats_random_init_and_the_network_free_start(capsys):
+    def progress(msg):
+        # past pytest's output capture: the test runs for minutes
+        with capsys.disabled():
+            print(f"[warm gain] {msg}", flush=True)
+
     c = ctx()
     pairs = []
     for seed in range(1000, 1200):
@@ -61,7 +66,7 @@ def test_trained_network_beats_random_init_and_the_network_free_start():
         sym.symnmf_canonical(c, Y, K, Xc)
         pairs.append((Xc, Hs))
         if len(pairs) % 25 == 0:
-            print(f"[warm gain] training instance {len(pairs)} solved", flush=True)
+            progress(f"training instance {len(pairs)} solved")
     params = torch.empty(sym.symnmf_mlp_param_count(W, HID, K), device=dev())
     sym.symnmf_mlp_init(c, W, HID, K, 1000, params)
     params[HID * W + HID * HID: HID * W + HID * HID + K * HID].zero_()
@@ -78,7 +83,7 @@ def test_trained_network_beats_random_init_and_the_network_free_start():
                                                     loss_kind=1))
             step += 1
         if ep % 10 == 0:
-            print(f"[warm gain] epoch {ep}", flush=True)
+            progress(f"epoch {ep}")
     first = sum(losses[: len(pairs)]) / len(pairs)
     last = sum(losses[-len(pairs):]) / len(pairs)
     assert last < first
@@ -94,8 +99,8 @@ def test_trained_network_beats_random_init_and_the_network_free_start():
                     for nm in ("random", "coords"))
         for nm, H0 in starts.items():
             its[nm].append(_iters_to(c, S, _run(c, S, H0, 1500, 10), 10, f_ref))
-        print(f"[warm gain] held-out seed {seed}: " + ", ".join(f"{nm} {v[-1]}" for nm, v in its.items()), flush=True)
-    print(f"[warm gain] iterations to f_ref (1 + 1e-4): {its}; Gram loss {first:.4f} -> {last:.4f}", flush=True)
+        progress(f"held-out seed {seed}: " + ", ".join(f"{nm} {v[-1]}" for nm, v in its.items()))
+    progress(f"iterations to f_ref (1 + 1e-4): {its}; Gram loss {first:.4f} -> {last:.4f}")
     big = 10 ** 6                                    # a run that never reaches the tolerance
     med = {nm: float(np.median([v if v is not None else big for v in vals])) for nm, vals in its.items()}
     assert all(v is not None for v in its["mlp"])
