@@ -148,8 +148,11 @@ def roofline(prof, rows, n, k, dtype, workload):
 
 def ttt_leg(sym, torch, ctx, X, stores, k, H0, max_steps):
     """FP32 vs BF16 storage, ADMM, time to 1e-4 of the committed FP64 oracle
-    reference; subspace errors against the device FP64 ADMM run from the same
-    H0 (the oracle's run repeated on the device)."""
+    reference, and FP32 from the network-free warm start (sketch S Omega of
+    width 64 and its canonical coordinates; the trained network needs a
+    training run of its own, in the warm-start study); subspace errors
+    against the device FP64 ADMM run from the same H0 (the oracle's run
+    repeated on the device)."""
     import studies
 
     n = H0.shape[0]
@@ -172,9 +175,12 @@ def ttt_leg(sym, torch, ctx, X, stores, k, H0, max_steps):
            "reference_factor": {"what": "device FP64 ADMM, same run", "f": f_dev,
                                 "rel_to_f_ref": (f_dev - f_ref) / f_ref, "seconds": round(ref_s, 2)},
            "variants": {}}
-    for name in ("fp32", "bf16"):
-        e = studies.ttt_run(ctx, stores[name], k, studies.variant_params(name + "-admm", eta),
-                            lambda H: H.copy_(H0), objective_of, f_ref, 1e-4, max_steps, every, store)
+    inits = {"fp32": lambda H: H.copy_(H0), "bf16": lambda H: H.copy_(H0),
+             "fp32_warm_coords": lambda H: sym.symnmf_warm_start(ctx, S32, None, 64, k, 7, H)}
+    for name, init in inits.items():
+        dt = name.split("_")[0]
+        e = studies.ttt_run(ctx, stores[dt], k, studies.variant_params(dt + "-admm", eta),
+                            init, objective_of, f_ref, 1e-4, max_steps, every, store)
         e.pop("times")
         nsave = max_steps // every
         e["subspace_error_final"] = sym.symnmf_subspace_error(ctx, store[nsave - 1], Wref)
@@ -182,9 +188,11 @@ def ttt_leg(sym, torch, ctx, X, stores, k, H0, max_steps):
             e["subspace_error_at_tol"] = sym.symnmf_subspace_error(ctx, store[e["iters"] // every - 1], Wref)
         out["variants"][name] = e
         log(f"time to tolerance {name}: {e}")
-    a, b = out["variants"]["fp32"].get("seconds"), out["variants"]["bf16"].get("seconds")
-    if a and b:
-        out["bf16_speedup"] = round(a / b, 3)
+    a = out["variants"]["fp32"].get("seconds")
+    for name, key in (("bf16", "bf16_speedup"), ("fp32_warm_coords", "warm_coords_speedup")):
+        b = out["variants"][name].get("seconds")
+        if a and b:
+            out[key] = round(a / b, 3)
     del store
     torch.cuda.empty_cache()
     return out
