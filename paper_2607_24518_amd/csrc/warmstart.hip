@@ -63,7 +63,9 @@ hipError_t launch_sh_dense(const float* part, int64_t rows, int64_t rows_pad, in
 // then an epilogue.  A: TA = 0 -> M x K row-major, TA = 1 -> K x M.
 // B: TB = 0 -> N x K row-major (used transposed), TB = 1 -> K x N.
 // B may hold bf16 values (the network weights at inference).  64 x 64 output
-// tile, K step 16, 256 threads with 4 x 4 outputs each.  blockIdx.z splits K
+// tile, K step 16 staged in LDS; each of the four waves computes a 32 x 32
+// quarter as 2 x 2 blocks of v_mfma_f32_16x16x4_f32 (FP32 products and
+// accumulation: the bf16 weights are widened exactly).  blockIdx.z splits K
 // into ranges of kchunk: with more than one range every range writes its own
 // partial C + z M N (no bias, no epilogue) for a fixed-order reduction.
 // EPI: 0 none, 1 GELU x Phi(x) (Phi from erfc), 2 softplus.  Z (optional)
@@ -76,13 +78,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A, 
                                                    const float* __restrict__ bias, float* __restrict__ C,
                                                    float* __restrict__ Z, int64_t M, int64_t N, int64_t K,
                                                    int64_t kchunk, float alpha) {
-    __shared__ float As[16][64 + 1];
-    __shared__ float Bs[16][64 + 1];
-    const int t = threadIdx.x, ti = t >> 4, tj = t & 15;
+    // row stride 80: the four 16-lane groups of an MFMA operand read (rows kk
+    // .. kk + 3) fall on disjoint banks
+    __shared__ float As[16][80];
+    __shared__ float Bs[16][80];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int rb = 32 * (wv >> 1), cb = 32 * (wv & 1);   // this wave's quarter of the tile
+    const int li = lane & 15, lk = lane >> 4;
     const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
     const int64_t kb = (int64_t)blockIdx.z * kchunk;
     const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
-    float acc[4][4] = {};
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int64_t k0 = kb; k0 < ke; k0 += 16) {
         __syncthreads();
         for (int f = t; f < 16 * 64; f += 256) {
@@ -106,34 +116,37 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A, 
             }
         }
         __syncthreads();
+        // operand A: lane (i, q) holds A[row i][k = 4 s + q]; operand B: lane
+        // (j, q) holds op(B)[k = 4 s + q][column j]
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            float a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ti * 4 + i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tj * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int st = 0; st < 4; ++st) {
+            const int kk = 4 * st + lk;
+            const float a0 = As[kk][rb + li], a1 = As[kk][rb + 16 + li];
+            const float b0 = Bs[kk][cb + li], b1 = Bs[kk][cb + 16 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
         }
     }
     const bool split = gridDim.z > 1;
     float* Cz = C + (split ? (int64_t)blockIdx.z * M * N : 0);
+    // output: lane (j, q) holds rows 4 q + v, v < 4, of column j of each block
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t m = m0 + ti * 4 + i, nn = n0 + tj * 4 + j;
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t m = m0 + rb + 16 * bi + 4 * lk + v, nn = n0 + cb + 16 * bj + li;
             if (m >= M || nn >= N) continue;
-            float v = alpha * acc[i][j];
-            if (split) { Cz[m * N + nn] = v; continue; }
-            if (bias) v += bias[nn];
-            if (Z) Z[m * N + nn] = v;
-            if (EPI == 1) v = v * normal_cdf_f(v);
-            else if (EPI == 2) v = fmaxf(v, 0.0f) + log1pf(expf(-fabsf(v)));
-            Cz[m * N + nn] = v;
+            float v_ = alpha * acc[bi][bj][v];
+            if (split) { Cz[m * N + nn] = v_; continue; }
+            if (bias) v_ += bias[nn];
+            if (Z) Z[m * N + nn] = v_;
+            if (EPI == 1) v_ = v_ * normal_cdf_f(v_);
+            else if (EPI == 2) v_ = fmaxf(v_, 0.0f) + log1pf(expf(-fabsf(v_)));
+            Cz[m * N + nn] = v_;
         }
 }
 
