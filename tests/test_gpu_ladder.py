@@ -97,7 +97,7 @@ def test_rebind_rejects_another_matrix_or_precision(stores):
     sym.symnmf_step(c, stores["fp32"], st)
 
 
-@pytest.mark.parametrize("method", ["adagrad", "adam"])
+@pytest.mark.parametrize("method", ["adagrad", "adam", "admm"])
 def test_ladder_trace_equals_the_same_steps_by_hand(stores, method):
     """(Methods without check-time rules, so that plain steps are the same
     iteration as the trace.)"""
@@ -107,6 +107,8 @@ def test_ladder_trace_equals_the_same_steps_by_hand(stores, method):
     kw = {}
     if method == "adam":
         kw = dict(method=sym.ADAM, eta=0.1 * math.sqrt(S32.desc.mean / k))
+    elif method == "admm":
+        kw = dict(method=sym.ADMM, rho=500.0)
     H0 = torch.empty(n, k, device=dev())
     sym.symnmf_init_H(c, S32, k, 5, H0)
     st = sym.symnmf_state_create(c, S8, k, _params(S32, k, **kw), H0)
@@ -143,12 +145,13 @@ def test_ladder_ends_below_fp8_alone(stores):
     assert 0 < sw < steps and fl < f8
 
 
+@pytest.mark.parametrize("method", ["adagrad", "admm"])
 @pytest.mark.parametrize("lo,hi", [("fp8", "fp32"), ("fp8", "bf16"), ("bf16", "fp32")])
-def test_ladder_matches_the_oracle(lo, hi):
+def test_ladder_matches_the_oracle(lo, hi, method):
     """The laddered trace against the FP64 oracle taking the same iteration on
     the same stored matrices (decoded), moved by Solver.rebind after the
     switch check: the objective of the final iterate on the precise storage to
-    1e-5 relative (the FP32 bar)."""
+    1e-5 relative (the FP32 bar).  ADMM carries its dual U across the move."""
     X = synth.c1_instance(0).X.numpy()
     c = ctx()
     S_lo = sym.symnmf_build_S(c, to_dev(X), dtype=sym.DTYPES[lo], fp8_panel_rows=128)
@@ -157,11 +160,13 @@ def test_ladder_matches_the_oracle(lo, hi):
     n, k, steps = 512, 8, 100
     H0 = o.init_H(A_hi.mean(), n, k, 0, as_float32=True)
     eta = math.sqrt(A_hi.mean() / k)
-    st = sym.symnmf_state_create(c, S_lo, k, sym.symnmf_params_default(eta=eta, max_iter=10 ** 9), to_dev(H0))
+    gpu_kw, orc_kw = (dict(method=sym.ADMM, rho=500.0), dict(method=o.ADMM, rho=500.0)) if method == "admm" else ({}, {})
+    st = sym.symnmf_state_create(c, S_lo, k, sym.symnmf_params_default(eta=eta, max_iter=10 ** 9, **gpu_kw),
+                                 to_dev(H0))
     store = torch.empty(1, n, k, device=dev())
     _, _, sw = sym.symnmf_solve_trace_ladder(c, S_lo, S_hi, st, steps, steps, store, 1.0)
     assert sw == 50
-    solver = o.Solver(A_lo, k, o.Params(eta=eta), H0.astype(np.float64))
+    solver = o.Solver(A_lo, k, o.Params(eta=eta, **orc_kw), H0.astype(np.float64))
     for t in range(steps):
         if t == sw + 1:
             solver.rebind(A_hi)
