@@ -256,6 +256,7 @@ def time_to_tolerance(args):
     from the start of its initialisation to the copy of H_t (HIP events on
     the solver stream), with every check-time rule of the method applied.
     """
+    import numpy as np
     import torch
     import paper_2607_24518_amd as sym
 
@@ -278,7 +279,18 @@ def time_to_tolerance(args):
     else:
         plans = [[(st.split(":")[0], int(st.split(":")[1])) for st in pl.split("+")]
                  for pl in args.ttt_ref_plans.split(",")]
-    f_dev, f_dev_best, Wref, ref_s, ref_desc, ref_drop = fp64_reference(ctx, X, kind, k, H0, build, plans)
+    if args.ttt_ref_load:
+        # the device FP64 reference of an earlier run of the same workload and plans
+        z = np.load(args.ttt_ref_load)
+        assert str(z["plans"]) == repr(plans) and int(z["n"]) == n and int(z["k"]) == k, "another reference"
+        f_dev, f_dev_best, ref_s, ref_desc, ref_drop = (float(z["f_dev"]), float(z["f_dev_best"]), float(z["seconds"]),
+                                                        str(z["desc"]) + " (loaded)", float(z["drop"]))
+        Wref = torch.from_numpy(z["W"]).to(dev)
+    else:
+        f_dev, f_dev_best, Wref, ref_s, ref_desc, ref_drop = fp64_reference(ctx, X, kind, k, H0, build, plans)
+        if args.ttt_ref_save:
+            np.savez(args.ttt_ref_save, f_dev=f_dev, f_dev_best=f_dev_best, W=Wref.cpu().numpy(), seconds=ref_s,
+                     desc=ref_desc, drop=ref_drop, plans=repr(plans), n=n, k=k)
     if ref:
         f_ref = ref["f_ref"]
         results = {"f_ref": f_ref, "reference": f"FP64 oracle ADMM (rho {ref['rho']:g}) after {ref['iterations']} "
@@ -291,6 +303,8 @@ def time_to_tolerance(args):
                                                 f"{args.ttt_ref_plans})",
                    "reference_last_1000_drop": ref_drop, "reference_seconds": round(ref_s, 2)}
     log(f"f_ref {f_ref:.12e}; device FP64 run {f_dev:.12e}")
+    if args.ttt_ref_only:
+        return results
     results.update(tol=args.ttt_tol, variants={})
     for v in variants:
         for dt in v.split("-")[0].split(">"):       # "fp8>bf16": the precision ladder
@@ -432,7 +446,7 @@ def warm_start_study(args):
     torch.cuda.empty_cache()
 
     # 3. evaluation
-    def evaluate(S, k_eval, model, label, seed, ref_steps, steps, f_ref_given=None):
+    def evaluate(S, k_eval, model, label, seed, ref_steps, steps, f_ref_given=None, W_ref=None):
         nn = S.desc.n
         params = admm_params(S)
 
@@ -471,6 +485,11 @@ def warm_start_study(args):
             e = ttt_scan(objective_of, store, steps // every, f_ref, args.ttt_tol, every, wt)
             e["init_seconds"] = round(w_init, 4)
             e["rel_initial"] = (f0 - f_ref) / f_ref
+            if W_ref is not None:
+                e["subspace_error_final"] = sym.symnmf_subspace_error(ctx, store[steps // every - 1], W_ref)
+                if e.get("iters"):
+                    e["subspace_error_at_tol"] = sym.symnmf_subspace_error(ctx, store[e["iters"] // every - 1],
+                                                                           W_ref)
             e["at_tol"] = {}
             for t2 in tols:
                 e2 = ttt_scan(objective_of, store, steps // every, f_ref, t2, every, wt)
@@ -521,9 +540,19 @@ def warm_start_study(args):
         ref = committed_reference(0, 100000, 2500, 32, k, 0)
         X = synth.overlap_returns(0, T=2500, n=100000, groups=32, device="cpu").X.to(dev)
         S = sym.symnmf_build_S(ctx, X, dtype=sym.S_FP32)
+        W_ref = None
+        if ref:
+            # reference factor of the subspace errors: the oracle's FP64 ADMM run
+            # repeated on the device from the oracle's H0
+            H0 = torch.empty(100000, k, device=dev)
+            init_factor(ctx, S, k, 0, H0, ref["mean"])
+            f_dev, _, W_ref, _, _, _ = fp64_reference(ctx, X, 0, k, H0, {"kind": 0},
+                                                      [[(f"admm{ref['rho']:g}", ref["iterations"])]])
+            out["c3_device_fp64_same_run_rel"] = (f_dev - ref["f_ref"]) / ref["f_ref"]
+            del H0
         del X
         out["c3_abs_corr_n100000"] = evaluate(S, k, net, "n=100000 |corr|", 0, args.warm_ref_iters,
-                                              args.warm_c3_max, ref["f_ref"] if ref else None)
+                                              args.warm_c3_max, ref["f_ref"] if ref else None, W_ref)
     return out
 
 
@@ -720,6 +749,9 @@ def main():
                     help="device FP64 reference runs where no oracle reference is committed: comma-separated plans, "
                          "each a '+'-joined list of method:iterations stages")
     ap.add_argument("--ttt-tols", default="1e-2,1e-3", help="further tolerances scanned on the same runs")
+    ap.add_argument("--ttt-ref-save", default="", help="save the device FP64 reference (f, factor) to this .npz")
+    ap.add_argument("--ttt-ref-load", default="", help="use the device FP64 reference saved by --ttt-ref-save")
+    ap.add_argument("--ttt-ref-only", action="store_true", help="stop after the reference run")
     ap.add_argument("--warm", action="store_true", help="learned warm start study instead of the step rate")
     ap.add_argument("--warm-family", default="panel", choices=["panel", "overlap"])
     ap.add_argument("--warm-n", type=int, default=20000)
@@ -779,8 +811,8 @@ def main():
         return
     if args.ttt:
         res = time_to_tolerance(args)
-        base = res["variants"].get("fp32-admm", {}).get("seconds")
-        for v in res["variants"].values():
+        base = res.get("variants", {}).get("fp32-admm", {}).get("seconds")
+        for v in res.get("variants", {}).values():
             if base and v.get("seconds"):
                 v["speedup_vs_fp32_admm"] = round(base / v["seconds"], 3)
         print(json.dumps({"metric": "time to relative objective tolerance", "unit": "s",
