@@ -325,9 +325,9 @@ __global__ __launch_bounds__(256) void admm_minv_kernel(const double* __restrict
 
 template <typename HT, int KB>
 __global__ __launch_bounds__(UT) void admm_update_kernel(UpdateArgs a, PlanView p) {
-    __shared__ HT Ws[SR * KB];
-    __shared__ HT Wns[SR * KB];
-    __shared__ HT As[SR * KB];
+    __shared__ __align__(32) HT Ws[SR * KB];
+    __shared__ __align__(32) HT Wns[SR * KB];
+    __shared__ __align__(32) HT As[SR * KB];
     __shared__ HT Gs[KB * KB];
     __shared__ HT Ms[KB * KB];
     __shared__ double red[UT / 64];
@@ -354,9 +354,43 @@ __global__ __launch_bounds__(UT) void admm_update_kernel(UpdateArgs a, PlanView 
     HT* Go = (HT*)a.Gout;
     HT* Wn = (HT*)a.Hn;
     const HT rho = (HT)a.rho;
+    // With k == KB the elements f = t + UT j of a thread share the column
+    // c = t % KB: the S.W partials are loaded writer by writer for all of them
+    // at once, and the Gram and M^-1 entries of the column are read from LDS
+    // once for all rows (rows in 4-wide vectors); every sum keeps the order
+    // of the per-element loops below.
+    constexpr int NJ = SR * KB / UT;
+    typedef HT hvec4 __attribute__((ext_vector_type(4)));
+    const bool full_k = k == KB;
+    const int cc = t % KB, rb = t / KB;
+    HT swv[NJ], wgv[NJ];
+    if (full_k) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) swv[j] = wgv[j] = 0;
+        for (int64_t w = w_lo; w <= w_hi; ++w) {
+            const HT* pw = part + ((slot_mul * w + slot_base) * TR + r0) * (int64_t)k;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) swv[j] += pw[t + UT * j];
+        }
+        for (int b = 0; b < KB; b += 4) {
+            const HT g0 = Gs[b * KB + cc], g1 = Gs[(b + 1) * KB + cc], g2 = Gs[(b + 2) * KB + cc],
+                     g3 = Gs[(b + 3) * KB + cc];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const hvec4 wv = *(const hvec4*)&Ws[(rb + j * (UT / KB)) * KB + b];
+                HT v = wgv[j];
+                v += wv[0] * g0;
+                v += wv[1] * g1;
+                v += wv[2] * g2;
+                v += wv[3] * g3;
+                wgv[j] = v;
+            }
+        }
+    }
     double tr = 0.0, kkt = 0.0;
     int bad = 0;
-    for (int f = t; f < SR * k; f += UT) {
+    int jj = 0;
+    for (int f = t; f < SR * k; f += UT, ++jj) {
         const int r = f / k, c = f - r * k;
         const int64_t prow = tile * TR + r0 + r;
         HT av = 0;
@@ -364,11 +398,19 @@ __global__ __launch_bounds__(UT) void admm_update_kernel(UpdateArgs a, PlanView 
             const HT w = Ws[r * KB + c];
             const int64_t idx = prow * k + c;
             HT sw = 0;
-            for (int64_t wg = w_lo; wg <= w_hi; ++wg)
-                sw += part[((slot_mul * wg + slot_base) * TR + r0 + r) * (int64_t)k + c];
+            if (full_k) {
+                sw = swv[jj < NJ ? jj : 0];
+            } else {
+                for (int64_t wg = w_lo; wg <= w_hi; ++wg)
+                    sw += part[((slot_mul * wg + slot_base) * TR + r0 + r) * (int64_t)k + c];
+            }
             if (a.fp8) sw = sw / (HT)a.panel_scale[prow / a.panel_rows] + (HT)a.diag[prow] * w;
             HT wg = 0;
-            for (int b = 0; b < k; ++b) wg += Ws[r * KB + b] * Gs[b * KB + c];
+            if (full_k) {
+                wg = wgv[jj < NJ ? jj : 0];
+            } else {
+                for (int b = 0; b < k; ++b) wg += Ws[r * KB + b] * Gs[b * KB + c];
+            }
             const HT g = (HT)4 * (wg - sw);
             tr += (double)w * (double)sw;
             const HT pg = w > (HT)0 ? g : (g < (HT)0 ? g : (HT)0);
@@ -380,14 +422,38 @@ __global__ __launch_bounds__(UT) void admm_update_kernel(UpdateArgs a, PlanView 
         As[r * KB + c] = av;
     }
     __syncthreads();
-    for (int f = t; f < SR * k; f += UT) {
+    HT hv[NJ];
+    if (full_k) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) hv[j] = 0;
+        for (int b = 0; b < KB; b += 4) {
+            const HT m0 = Ms[b * KB + cc], m1 = Ms[(b + 1) * KB + cc], m2 = Ms[(b + 2) * KB + cc],
+                     m3 = Ms[(b + 3) * KB + cc];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const hvec4 av4 = *(const hvec4*)&As[(rb + j * (UT / KB)) * KB + b];
+                HT v = hv[j];
+                v += av4[0] * m0;
+                v += av4[1] * m1;
+                v += av4[2] * m2;
+                v += av4[3] * m3;
+                hv[j] = v;
+            }
+        }
+    }
+    jj = 0;
+    for (int f = t; f < SR * k; f += UT, ++jj) {
         const int r = f / k, c = f - r * k;
         const int64_t prow = tile * TR + r0 + r;
         HT wn = 0;
         if (prow < a.rows) {
             const int64_t idx = prow * k + c;
             HT h = 0;
-            for (int j = 0; j < k; ++j) h += As[r * KB + j] * Ms[j * KB + c];
+            if (full_k) {
+                h = hv[jj < NJ ? jj : 0];
+            } else {
+                for (int j = 0; j < k; ++j) h += As[r * KB + j] * Ms[j * KB + c];
+            }
             const HT u = Ud[idx];
             wn = h + u > (HT)0 ? h + u : (HT)0;
             Ud[idx] = u + h - wn;
@@ -397,11 +463,33 @@ __global__ __launch_bounds__(UT) void admm_update_kernel(UpdateArgs a, PlanView 
     }
     __syncthreads();
     double* tg = a.tile_gram + slice * (int64_t)k * k;
-    for (int e = t; e < k * k; e += UT) {
-        const int ia = e / k, ib = e - ia * k;
-        double s = 0.0;
-        for (int r = 0; r < SR; ++r) s += (double)Wns[r * KB + ia] * (double)Wns[r * KB + ib];
-        tg[e] = s;
+    if (KB >= 32 && k == KB) {
+        // entries (ia0 + q, ib), q < NQ, as in the update kernel: the same FP64
+        // sums over the slice rows, consecutive ia read as 4-wide vectors
+        constexpr int NQ = KB >= 32 ? (KB * KB) / UT : 4;
+        static_assert(NQ % 4 == 0, "4-wide Gram reads need NQ % 4 == 0");
+        const int ib = t % KB, ia0 = (t / KB) * NQ;
+        double sq[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sq[q] = 0.0;
+        for (int r = 0; r < SR; ++r) {
+            const double hb = (double)Wns[r * KB + ib];
+#pragma unroll
+            for (int q = 0; q < NQ; q += 4) {
+                const hvec4 wv = *(const hvec4*)&Wns[r * KB + ia0 + q];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sq[q + e] += (double)wv[e] * hb;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tg[(ia0 + q) * k + ib] = sq[q];
+    } else {
+        for (int e = t; e < k * k; e += UT) {
+            const int ia = e / k, ib = e - ia * k;
+            double s = 0.0;
+            for (int r = 0; r < SR; ++r) s += (double)Wns[r * KB + ia] * (double)Wns[r * KB + ib];
+            tg[e] = s;
+        }
     }
     const double str = block_sum(tr, red);
     const double skk = block_sum(kkt, red);
