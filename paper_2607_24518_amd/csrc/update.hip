@@ -104,7 +104,7 @@ __global__ __launch_bounds__(UT, sizeof(HT) == 4 ? 7 : 1) void update_kernel(Upd
     // elements of one work-group issued together (a row of the n = 10^6 share
     // has ten partials: one after another they are ten dependent load latencies
     // per element)
-    HT shv[full_k ? NJ : 1];
+    HT shv[NJ];
     if (full_k) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) shv[j] = 0;
@@ -118,8 +118,9 @@ __global__ __launch_bounds__(UT, sizeof(HT) == 4 ? 7 : 1) void update_kernel(Upd
     }
     double tr = 0.0, kkt = 0.0;
     int bad = 0;
-    int jj = 0;
-    for (int f = t; f < SR * k; f += UT, ++jj) {
+    // one element f = r k + c of the slice; with full_k its S.H sum and
+    // H (H^T H) entry come in precomputed (sh_in, hg_in)
+    auto element = [&](int f, HT sh_in, HT hg_in) {
         const int r = f / k, c = f - r * k;             // slice row, column
         const int64_t prow = tile * TR + r0 + r;
         HT hn = 0;
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(UT, sizeof(HT) == 4 ? 7 : 1) void update_kernel(Upd
             HT g, sh = 0, hg = 0;
             if (act >= 0) {
                 if (full_k) {
-                    sh = shv[jj < NJ ? jj : 0];
+                    sh = sh_in;
                 } else {
                     for (int64_t w = w_lo; w <= w_hi; ++w)
                         sh += part[((slot_mul * w + slot_base) * TR + r0 + r) * (int64_t)k + c];
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(UT, sizeof(HT) == 4 ? 7 : 1) void update_kernel(Upd
                     sh = sh / (HT)a.panel_scale[prow / a.panel_rows] + dw * (HT)a.diag[prow] * h;
                 }
                 if (full_k) {
-                    hg = hgv[jj < NJ ? jj : 0];
+                    hg = hg_in;
                 } else {
                     for (int b = 0; b < k; ++b) hg += Hs[r * KB + b] * Gs[b * KB + c];
                 }
@@ -226,6 +227,14 @@ __global__ __launch_bounds__(UT, sizeof(HT) == 4 ? 7 : 1) void update_kernel(Upd
             Hn[(g0 + r) * k + c] = hn;
         }
         Hns[r * KB + c] = hn;
+    };
+    if (full_k) {
+        // the thread's elements f = t + UT j with compile-time j, so the
+        // precomputed sums stay in registers
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) element(t + UT * j, shv[j], hgv[j]);
+    } else {
+        for (int f = t; f < SR * k; f += UT) element(f, (HT)0, (HT)0);
     }
     __syncthreads();
     double* tg = a.tile_gram + slice * (int64_t)k * k;
