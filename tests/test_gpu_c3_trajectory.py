@@ -113,3 +113,43 @@ def test_fp64_admm_trajectory_at_full_size(fx):
                                                         np.max(np.abs(Ur - Uref)) / np.max(Wref)))
     assert np.max(np.abs(Wr - Wref)) <= 1e-5 * np.max(Wref)
     assert np.max(np.abs(Ur - Uref)) <= 1e-5 * np.max(Wref)
+
+
+REFERENCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "abs_corr_n100000_k32_reference.json")
+
+
+def test_fp64_admm_reference_run_at_full_size(fx, capsys):
+    """The whole reference run of the time-to-tolerance results: 1500 FP64
+    ADMM iterations (rho 500) from the oracle's H0 on FP64 storage, compared
+    with the oracle's run (tests/golden/abs_corr_n100000_k32_reference.json,
+    written by the oracle-only script beside it) at every 10th iterate it
+    recorded, and its final objective f_ref.  Bound: the oracle solves the
+    problem of the float32-rounded S, which moves f by at most
+    2 sqrt(f) 2^-24 ||S||_F, about 8e-7 relative here; the runs are not
+    chaotic (an FP64 run from H0 perturbed by 1e-7 stays within 2e-7)."""
+    d, c, Xg, H0 = fx
+    with open(REFERENCE) as fh:
+        ref = json.load(fh)
+    assert ref["complete"] and (ref["n"], ref["T"], ref["groups"], ref["k"], ref["seed"], ref["init_seed"]) == \
+        (d["n"], d["T"], d["groups"], d["k"], d["seed"], d["init_seed"])
+    assert ref["mean"] == d["mean"]
+    n, k = d["n"], d["k"]
+    S = sym.symnmf_build_S(c, Xg, dtype=sym.S_FP64)
+    st = sym.symnmf_state_create(c, S, k, sym.symnmf_params_default(method=sym.ADMM, rho=ref["rho"]),
+                                 to_dev(H0, torch.float64))
+    trace = {e["t"]: e["f"] for e in ref["trace"]}
+    worst = 0.0
+    for t in range(ref["iterations"]):
+        s = sym.symnmf_step(c, S, st, want_stats=(t in trace or t == ref["iterations"] - 1))
+        if t in trace:
+            assert s.t == t
+            worst = max(worst, abs(s.f - trace[t]) / trace[t])
+        if t % 300 == 0:
+            with capsys.disabled():
+                print(f"[reference run] t={t} worst relative difference so far {worst:.2e}", flush=True)
+    rel_final = abs(s.f - ref["f_ref"]) / ref["f_ref"]
+    with capsys.disabled():
+        print(f"[reference run] {len(trace)} recorded iterates: max relative difference {worst:.3e}; "
+              f"final f {s.f:.12e} vs f_ref {ref['f_ref']:.12e} ({rel_final:.2e})", flush=True)
+    assert worst <= 1e-6
+    assert rel_final <= 1e-6
