@@ -124,15 +124,19 @@ ADAM_ETA = {"adam": 0.1, "nadam": 0.03, "adan": 0.01}
 
 
 def variant_params(variant, eta_base, seed=0):
-    """Solver parameters of a variant name "<storage>[-<method>][-softplus][-principal]";
-    "admm<rho>" selects ADMM with that penalty (plain "admm": rho = 500)."""
+    """Solver parameters of a variant name "<storage>[-<method>][-softplus][-principal][-eta<c>]";
+    "admm<rho>" selects ADMM with that penalty (plain "admm": rho = 500); "eta<c>"
+    multiplies the method's step size by c."""
     import paper_2607_24518_amd as sym
 
     parts = variant.split("-")
-    rho = 500.0
+    rho, eta_mul = 500.0, 1.0
     for q in parts[1:]:
         if q.startswith("admm") and q[4:]:
             rho = float(q[4:])
+        if q.startswith("eta") and q[3:]:
+            eta_mul = float(q[3:])
+    eta_base = eta_base * eta_mul
     parts = ["admm" if q.startswith("admm") else q for q in parts]
     method = next((q for q in parts[1:] if q in METHODS), "adagrad")
     kw = dict(method=METHODS[method], eta=eta_base, softplus=int("softplus" in parts), max_iter=10 ** 9, seed=seed)
