@@ -194,6 +194,34 @@ def test_tpdm_rows_blockwise_equals_the_direct_form():
         assert np.all(got[np.arange(4), rows] == 1.0)
 
 
+def test_stored_rows_is_the_float32_rounded_matrix_in_fp64():
+    """The oracle's form for n = 10^5 (S kept as float32, every product in
+    FP64, slabs of 128 rows): on a 700-instrument instance (ragged last slab,
+    panels of 256 rows) its entries are the float32 rounding of abs_corr's,
+    S @ H equals the explicit FP64 product of those entries, and a solver run
+    on it follows, step for step, the run on the dense rounded matrix."""
+    X = synth.c1_instance(4, T=800, n=700, groups=5).X.numpy()
+    dense = o.abs_corr(X)
+    S = o.StoredRows.abs_corr(X, panel_rows=256)
+    rounded = dense.astype(np.float32)
+    assert S.data.dtype == np.float32 and np.array_equal(S.data, rounded)
+    R = rounded.astype(np.float64)
+    assert S.fro2 == pytest.approx(float((R * R).sum()), rel=1e-14)
+    assert S.mean() == pytest.approx(float(R.mean()), rel=1e-14)
+    H = np.random.default_rng(3).random((700, 9))
+    assert np.max(np.abs((S @ H) - R @ H)) <= 1e-12 * np.max(np.abs(R @ H))
+    assert np.array_equal(S.rows(100, 300), R[100:300])
+    k = 6
+    H0 = o.init_H(R.mean(), 700, k, 2)
+    eta = math.sqrt(R.mean() / k)
+    a = o.Solver(S, k, o.Params(eta=eta), H0)
+    b = o.Solver(R, k, o.Params(eta=eta), H0)
+    for _ in range(20):
+        sa, sb = a.step(), b.step()
+        assert sa.f == pytest.approx(sb.f, rel=1e-12)
+    assert np.max(np.abs(a.H - b.H)) <= 1e-12 * np.max(np.abs(b.H))
+
+
 # --- storage formats -------------------------------------------------------
 def test_benchmark_spectra_match_the_paper_table(golden_dir):
     """The appendix's benchmark construction (generator + |corr| or the
