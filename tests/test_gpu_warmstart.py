@@ -210,6 +210,24 @@ def test_warm_start_matches_oracle(with_net, residual):
     assert np.max(np.abs(from_dev(H0) - ref)) <= 1e-4 * np.max(np.abs(ref))
 
 
+def test_residual_network_with_zero_last_layer_is_the_network_free_start(corr600):
+    """A residual network whose last layer (weights and bias) is zero adds
+    nothing to the coordinates: the warm start is the network-free one, bit
+    for bit (the starting point of every training run)."""
+    k = 8
+    c = ctx()
+    P = _params32(k, seed=4)
+    P["W3"] = np.zeros_like(P["W3"])
+    P["b3"] = np.zeros_like(P["b3"])
+    net = sym.symnmf_mlp_create(c, WIDTH, HIDDEN, k, to_dev(_flat(P)))
+    sym.symnmf_mlp_set_output(c, net, True)
+    S = sym.symnmf_S_load(c, to_dev(corr600, torch.float64), dtype=sym.S_FP32)
+    Ha, Hb = torch.empty(600, k, device=dev()), torch.empty(600, k, device=dev())
+    sym.symnmf_warm_start(c, S, net, WIDTH, k, 9, Ha)
+    sym.symnmf_warm_start(c, S, None, WIDTH, k, 9, Hb)
+    assert torch.equal(Ha, Hb)
+
+
 def test_warm_start_without_network_recovers_planted_subspace():
     """On an exactly separable S = H* H*^T the network-free coordinates are
     H* up to column scaling: the subspace error is at rounding level."""
