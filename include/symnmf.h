@@ -49,7 +49,7 @@ typedef enum {
     SYMNMF_EDEVICE = 3,      /* HIP runtime error                               */
     SYMNMF_ENUMERIC = 4,     /* non-finite value in a reduction                 */
     SYMNMF_ENOTCONV = 5,     /* solve_to_tol hit max_iter before the stop rule  */
-    SYMNMF_EUNSUPPORTED = 6  /* valid request this build does not implement     */
+    SYMNMF_EUNSUPPORTED = 6  /* valid request the library does not implement   */
 } symnmf_status;
 
 /* Storage type of S.  The paper runs fp32; BF16 and FP8 storage are an
