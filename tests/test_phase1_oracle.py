@@ -181,3 +181,26 @@ def test_rebind_keeps_the_iteration_and_moves_it_to_the_new_matrix():
     assert st.E == pytest.approx(float(((S2 - H20 @ H20.T) ** 2).sum()) / float((S2 * S2).sum()), rel=1e-10)
     with pytest.raises(ValueError):
         c.rebind(S2[:10, :10])
+
+
+def test_rebind_carries_the_admm_dual():
+    """ADMM under the ladder's move: the dual U and the iterate W are carried,
+    and the next step is the ADMM update (eqs. admm_H, admm_W, admm_U) of the
+    new matrix from them."""
+    inst = synth.c1_instance(2, T=600, n=120, groups=3)
+    S = o.abs_corr(inst.X.double().numpy())
+    rng = np.random.default_rng(6)
+    S2 = S + 0.01 * np.abs(rng.standard_normal(S.shape))
+    S2 = 0.5 * (S2 + S2.T)
+    k = 8
+    H0 = o.init_H(S.mean(), 120, k, 2)
+    p = o.Params(method=o.ADMM, rho=50.0)              # an active dual: clipped entries by t = 40
+    a = o.Solver(S, k, p, H0)
+    for _ in range(40):
+        a.step()
+    W40, U40 = a.H.copy(), a.U.copy()
+    assert np.count_nonzero(U40) > 100
+    a.rebind(S2)
+    a.step()
+    W_exp, U_exp = o.admm_update(S2, W40, U40, 50.0)
+    assert np.array_equal(a.H, W_exp) and np.array_equal(a.U, U_exp)
